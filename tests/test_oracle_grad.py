@@ -1,0 +1,139 @@
+"""Pins of the oracle's adjoint (Sec. 4.1 end-to-end differentiation), losses
+(Eq. 11 and the PSNR metric) and Adam (Sec. 5.1)."""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import sparse as S
+from oracle import adjoint as A
+from oracle import loss as Lo
+from oracle import adam as Ad
+from synth import random_theta, uniform_image, gaussian_kernel
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _away_from_integers(th, h):
+    """Resample offsets so no sample position is within 10h of an integer
+    (the bilinear read has kinks there)."""
+    th = th.copy()
+    for j in range(2):
+        f = th[:, j] - np.floor(th[:, j])
+        bad = (f < 10 * h) | (f > 1 - 10 * h)
+        th[bad, j] += 0.5
+    return th
+
+
+def test_loss_hand_values():
+    vals = dict(l.split() for l in open(os.path.join(GOLD, "loss_hand.txt")) if l[0] != "#")
+    T = np.array([[0, 1, 0], [1, 4, 1], [0, 1, 0]]) / 8.0
+    K = np.zeros((3, 3))
+    assert abs(Lo.nmse(K, T) - float(vals["nmse"])) < 1e-16
+    assert abs(Lo.psnr_db(K, T) - float(vals["psnr"])) < 1e-12
+    assert abs(Lo.charbonnier(K, T) - float(vals["charbonnier"])) < 1e-15
+
+
+@pytest.mark.parametrize("kind", [Lo.NMSE, Lo.CHARBONNIER])
+def test_impulse_gradient_matches_central_fd(kind):
+    taps = [5, 6, 4]
+    M = 21
+    target = gaussian_kernel(M, 3.0)
+    th = _away_from_integers(random_theta(taps, 4.0, seed=21).astype(np.float64), 1e-6)
+    loss, _, g = A.impulse_loss_grad(target, th, taps, kind)
+    h = 1e-6
+    fd = np.zeros_like(th)
+    for idx in np.ndindex(*th.shape):
+        tp = th.copy(); tp[idx] += h
+        tm = th.copy(); tm[idx] -= h
+        lp = A.impulse_loss_grad(target, tp, taps, kind)[0]
+        lm = A.impulse_loss_grad(target, tm, taps, kind)[0]
+        fd[idx] = (lp - lm) / (2 * h)
+    err = np.abs(g - fd).max() / np.abs(fd).max()
+    assert err < 1e-7, err
+
+
+@pytest.mark.parametrize("boundary", [S.ZERO, S.CLAMP])
+def test_image_chain_vjp_fd_and_dot_product(boundary):
+    taps = [4, 3]
+    th = _away_from_integers(random_theta(taps, 3.0, seed=7).astype(np.float64), 1e-6)
+    X = uniform_image(11, 13, 2, seed=5).astype(np.float64)
+    G = np.random.default_rng(1).standard_normal((2, 11, 13))
+
+    def f(t, x):
+        return float(np.sum(G * S.chain(x, t, taps, boundary)))
+
+    dth, dX = A.chain_vjp(X, th, taps, boundary, G)
+    h = 1e-6
+    for idx in np.ndindex(*th.shape):
+        tp = th.copy(); tp[idx] += h
+        tm = th.copy(); tm[idx] -= h
+        fd = (f(tp, X) - f(tm, X)) / (2 * h)
+        assert abs(dth[idx] - fd) <= 1e-7 * max(1.0, abs(fd)), (idx, dth[idx], fd)
+    # the input adjoint is the transpose: <A x, y> = <x, A^T y> (chain is linear in x)
+    x2 = uniform_image(11, 13, 2, seed=9).astype(np.float64)
+    lhs = np.sum(G * S.chain(x2, th, taps, boundary))
+    rhs = np.sum(x2 * dX)
+    assert abs(lhs - rhs) <= 1e-13 * abs(lhs)
+
+
+def test_weight_gradient_closed_form_integer_offsets():
+    """Single layer, integer offsets: dL/dw_i = <G, X shifted by o_i>."""
+    X = uniform_image(9, 12, 1, seed=3)[0].astype(np.float64)
+    G = np.random.default_rng(2).standard_normal((9, 12))
+    lay = np.array([[2.0, -1.0, 0.3], [-3.0, 2.0, 0.5], [0.0, 0.0, 0.2]])
+    dl, _ = A.layer_vjp(X, lay, S.CLAMP, G)
+    y, x = np.mgrid[0:9, 0:12]
+    for i, (ox, oy, _) in enumerate(lay):
+        sh = X[np.clip(y - int(oy), 0, 8), np.clip(x - int(ox), 0, 11)]
+        assert abs(dl[i, 2] - np.sum(G * sh)) < 1e-13
+
+
+def test_adam_first_step_is_signed_lr():
+    g = np.array([[1e-9, -3.0, 0.5]])
+    th, _, _ = Ad.adam_update(np.zeros((1, 3)), g, np.zeros((1, 3)), np.zeros((1, 3)), 1, 0.01)
+    np.testing.assert_allclose(th, -0.01 * g / (np.abs(g) + 1e-8), rtol=1e-15)
+
+
+def test_adam_matches_torch_optim_adam_fp64():
+    """Same gradients fed to torch.optim.Adam (CPU, float64) with the same
+    linear learning-rate schedule."""
+    rng = np.random.default_rng(4)
+    S_ = 25
+    gs = rng.standard_normal((S_, 7, 3))
+    th = rng.standard_normal((7, 3))
+    p = torch.nn.Parameter(torch.tensor(th.copy(), dtype=torch.float64))
+    opt = torch.optim.Adam([p], lr=1e-2, betas=(0.9, 0.999), eps=1e-8)
+    m = np.zeros_like(th)
+    v = np.zeros_like(th)
+    for s in range(S_):
+        lr = Ad.lr_at(s, S_, 1e-2, 1e-3)
+        for grp in opt.param_groups:
+            grp["lr"] = lr
+        p.grad = torch.tensor(gs[s], dtype=torch.float64)
+        opt.step()
+        th, m, v = Ad.adam_update(th, gs[s], m, v, s + 1, lr)
+    np.testing.assert_allclose(th, p.detach().numpy(), rtol=1e-13, atol=1e-15)
+
+
+def test_lr_schedule_endpoints():
+    assert Ad.lr_at(0, 1000, 1e-3, 1e-4) == 1e-3
+    assert abs(Ad.lr_at(999, 1000, 1e-3, 1e-4) - 1e-4) < 1e-19
+    assert Ad.lr_at(0, 1, 1e-3, 1e-4) == 1e-3
+
+
+def test_optimiser_recovers_a_representable_target():
+    """Target = F_Theta_true(delta); from a perturbed start the loop gains
+    PSNR, and starting exactly at Theta_true stops before any update."""
+    taps = [4, 4]
+    M = 17
+    th_true = random_theta(taps, 3.0, seed=31).astype(np.float64)
+    target = S.impulse_response(M, th_true, taps)
+    p = Ad.OptParams(max_steps=150, lr0=1e-2, lr1=1e-3, psnr_stop_db=200.0)
+    start = th_true + np.random.default_rng(0).normal(0, 0.15, th_true.shape) * [1, 1, 0.1]
+    trace = []
+    _, ps, steps = Ad.optimize(target, start, taps, p, trace)
+    assert steps == 150 and ps > trace[0][1] + 10.0
+    _, ps0, steps0 = Ad.optimize(target, th_true, taps, p)
+    assert steps0 == 0 and ps0 == float("inf")
