@@ -1,0 +1,142 @@
+#!/usr/bin/env python3
+"""Benchmark: spatially varying sparse filtering of a 1920x1080x3 FP32 frame
+(16-entry 1-D basis of 4 layers x 8 taps, smooth per-pixel blur map), one GPU.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1]
+
+One step = one disk_sv_filter call on a frame already resident in HBM
+(basis preparation + the 4 gather passes).  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+METRIC = "SV sparse filter Mpix/s @1080p (% HBM peak); time-to-40dB, 4096 kernels, learned vs plain"
+HBM_PEAK_GBS = 8000.0
+H, W, C = 1080, 1920, 3
+TAPS = [8, 8, 8, 8]
+G = 16
+# algorithmic HBM bytes of one pass per pixel: read C floats, read P, write C floats
+PASS_BYTES_PER_PX = 4 * C + 4 + 4 * C
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--basis", choices=["fitted", "random"], default="fitted")
+    return ap.parse_args()
+
+
+def disk_targets():
+    """The basis targets: uniform disks of radius 2, 4, ..., 32 px."""
+    from synth import disk_kernel
+    return [disk_kernel(2.0 * (k + 1)) for k in range(G)]
+
+
+def build_basis(torch, disk, kind):
+    """Basis entries f_k for disks r_k = 2(k+1) (Sec. 4.3 offline stage)."""
+    if kind == "random" or not hasattr(disk, "fit_basis"):
+        from synth import random_theta
+        th = np.stack([random_theta(TAPS, 1.0 + 1.05 * k, seed=100 + k) for k in range(G)]).astype(np.float32)
+        return torch.as_tensor(th).cuda(), None
+    return disk.fit_basis(disk_targets(), TAPS)
+
+
+def cpu_baseline(basis_np, img, P):
+    """The FP64 oracle on a bounded sample of the same workload: the left half
+    of the frame (1080 x 960 x 3), all 4 passes."""
+    from oracle import svfilter as SV
+    crop = (slice(0, H), slice(0, W // 2))
+    im = img[:, crop[0], crop[1]].astype(np.float64)
+    pm = P[:, crop[0], crop[1]].astype(np.float64)
+    t = time.perf_counter()
+    SV.sv_chain(im, pm, basis_np.astype(np.float64), [G], TAPS)
+    dt = time.perf_counter() - t
+    px = im.shape[1] * im.shape[2]
+    return {"value": px / dt / 1e6, "unit": "Mpix/s", "cores": 1, "kind": "oracle",
+            "sample": f"left half of the frame ({im.shape[1]}x{im.shape[2]}x{C}), 4 passes, FP64 numpy, "
+                      f"{dt:.1f} s single-threaded"}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path (see DESIGN.md on sharding).",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_2512_04556_amd as disk
+    from synth import noise_image, param_map
+
+    img = noise_image(H, W, C, seed=2)
+    P = param_map(H, W, seed=3)
+    x = torch.as_tensor(img).cuda()
+    p = torch.as_tensor(P).cuda()
+    basis_t, fit_info = build_basis(torch, disk, a.basis)
+    basis = disk.make_basis(basis_t, TAPS, [G])
+    out = torch.empty_like(x)
+    ws = disk.sv_filter_workspace(basis, C, H, W)
+    stream = torch.cuda.current_stream()
+
+    for _ in range(a.warmup):
+        disk.disk_sv_filter(basis, x, p, out=out, ws=ws)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(a.steps):
+        disk.disk_sv_filter(basis, x, p, out=out, ws=ws)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = wall * 1e3 / a.steps
+    ev_ms = e0.elapsed_time(e1) / a.steps
+
+    # the dominant kernel: the gather pass, timed alone (prepared table, L passes per call)
+    table = disk.disk_sv_prepare(basis)
+    aws = torch.empty(int(ws.numel()), dtype=torch.uint8, device="cuda")
+    for _ in range(5):
+        disk.disk_sv_apply(basis, table, x, p, out=out, ws=aws)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(a.steps):
+        disk.disk_sv_apply(basis, table, x, p, out=out, ws=aws)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    pass_ms = e0.elapsed_time(e1) / (a.steps * len(TAPS))
+    pass_bytes = PASS_BYTES_PER_PX * H * W
+    achieved = pass_bytes / (pass_ms * 1e-3) / 1e9
+
+    mpix = H * W / (ms * 1e-3) / 1e6
+    frame_bytes = len(TAPS) * pass_bytes
+    res = {
+        "metric": METRIC, "value": round(mpix, 1), "unit": "Mpix/s", "n_gpus": 1, "steps": a.steps,
+        "warmup": a.warmup, "ms_per_step": round(ms, 5), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "sv_filter_1080p_f32", "H": H, "W": W, "C": C, "layers": len(TAPS),
+                   "taps_per_layer": TAPS[0], "basis_entries": G, "basis": a.basis if fit_info is None else "fitted",
+                   "halo": basis.halo},
+        "hbm_frac_frame": round(frame_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        "event_ms_per_step": round(ev_ms, 5),
+        "roofline": {"bound": "hbm", "kernel": "sv_pass_kernel", "achieved": round(achieved, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": None, "pass_ms": round(pass_ms, 5), "bytes_per_launch": pass_bytes},
+    }
+    if fit_info:
+        res["config"]["basis_fit"] = fit_info
+    if not a.no_cpu_baseline:
+        res["cpu_baseline"] = cpu_baseline(basis_t.cpu().numpy(), img, P)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,290 @@
+/*
+ * disk.h - C ABI of libdisk: the data-parallel hot path of DISK ("Differentiable
+ * Sparse Kernel Complex for Efficient Spatially-Variant Convolution", Wu, Cao,
+ * Huo, ICLR 2026) on AMD Instinct MI355X (gfx950).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Images are planar [C][H][W], row-major, row index y, column index x, pixel
+ *   centres at integers.  C <= 4.
+ * - A sparse kernel complex Theta (Sec. 4.1, Eq. 5) is a float32 array
+ *   [T][3] of rows (ox, oy, w), layer-major: layer l owns taps[l] consecutive
+ *   rows, T = sum_l taps[l].  Offsets are in pixels.
+ * - One sparse layer (Sec. 3.2, Eq. 2, chained as in Eq. 3) computes
+ *       Y[p] = sum_i w_i * B(X, p - o_i)
+ *   where B is the bilinear read (x0 = floor(sx), fx = sx - x0, likewise y).
+ *   A tap's weight therefore lands at c + o_i in the impulse response and
+ *   filtering is the true convolution with the synthesised kernel.
+ * - Boundary: DISK_ZERO (reads outside the canvas are 0; impulse canvases) or
+ *   DISK_CLAMP (indices clamped to the edge; images).
+ * - Every pointer documented as "device" must be a device pointer owned by the
+ *   caller, 16-byte aligned; "host" pointers are ordinary host memory.  The
+ *   library never allocates device memory: scratch space is passed in as
+ *   (ws, ws_bytes), sized by the matching *_workspace_size call.
+ * - Every call that takes a stream is asynchronous on that stream; arguments
+ *   are validated on the host before anything is enqueued.  Calls never throw,
+ *   exit or print.  On failure they return a negative disk_status and set a
+ *   thread-local message readable with disk_last_error().
+ * - Limits: 1 <= L <= DISK_MAX_LAYERS, 1 <= taps[l] <= DISK_MAX_TAPS,
+ *   1 <= C <= DISK_MAX_CHANNELS, impulse/target sides odd and <= DISK_MAX_SIDE.
+ */
+#ifndef DISK_H
+#define DISK_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DISK_MAX_LAYERS 8
+#define DISK_MAX_TAPS 32
+#define DISK_MAX_CHANNELS 4
+#define DISK_MAX_SIDE 255
+#define DISK_MAX_HALO 64
+
+typedef enum {
+    DISK_OK = 0,
+    DISK_INVALID_ARG = -1,        /* null pointer, bad enum, misaligned pointer */
+    DISK_BAD_SHAPE = -2,          /* sizes out of range / inconsistent */
+    DISK_WORKSPACE_TOO_SMALL = -3,
+    DISK_DEVICE = -4,             /* a HIP call or kernel launch failed */
+    DISK_UNSUPPORTED = -5         /* valid but not implemented (e.g. halo too large) */
+} disk_status;
+
+typedef enum { DISK_ZERO = 0, DISK_CLAMP = 1 } disk_boundary;
+typedef enum { DISK_F32 = 0, DISK_BF16 = 1 } disk_dtype;
+typedef enum { DISK_LOSS_NMSE = 0, DISK_LOSS_CHARBONNIER = 1 } disk_loss;
+
+/* Layer structure of one sparse kernel complex (Eq. 5). */
+typedef struct {
+    int32_t L;
+    int32_t taps[DISK_MAX_LAYERS];
+} disk_complex;
+
+const char* disk_status_string(disk_status s);
+/* Message of the last failing call on this thread ("" if none). */
+const char* disk_last_error(void);
+/* Library version string. */
+const char* disk_version(void);
+
+/* ------------------------------------------------------------------------- */
+/* Chain forward (Sec. 3.2 Eq. 3; impulse response Sec. 4.4 Eq. 10).          */
+/* ------------------------------------------------------------------------- */
+/*
+ * Applies the L sparse layers of Theta to an image, or to the discrete Dirac
+ * impulse.
+ *   cx     host: layer structure.
+ *   theta  device float [T][3].
+ *   in     device [C][H][W] of dtype `io`; NULL selects impulse mode: the input
+ *          is delta at ((W-1)/2, (H-1)/2), C must be 1, H and W odd, boundary
+ *          DISK_ZERO and io DISK_F32 (the result is K_syn of Eq. 10).
+ *   out    device [C][H][W] of dtype `io` (FP32 in impulse mode).
+ *   saved  device float [(L-1)][C][H][W] receiving X_1..X_{L-1} for
+ *          disk_backward, or NULL.
+ *   ws     device scratch of at least disk_forward_workspace_size() bytes.
+ * Intermediates are FP32; with io = DISK_BF16 the input is widened and the
+ * output rounded to nearest-even BF16.
+ */
+size_t disk_forward_workspace_size(const disk_complex* cx, int32_t C, int32_t H, int32_t W,
+                                   disk_dtype io, int32_t impulse, int32_t has_saved);
+disk_status disk_forward(const disk_complex* cx, const float* theta, const void* in, void* out,
+                         int32_t C, int32_t H, int32_t W, disk_dtype io, disk_boundary boundary,
+                         float* saved, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* ------------------------------------------------------------------------- */
+/* Adjoint of the chain (the end-to-end differentiation of Sec. 4.1).         */
+/* ------------------------------------------------------------------------- */
+/*
+ * Given G_L = dLoss/dout, computes
+ *   grad_theta  device float [T][3] (overwritten) = dLoss/dTheta, or NULL;
+ *   grad_in     device float [C][H][W] (overwritten) = dLoss/din, or NULL.
+ *   in          device float [C][H][W], the forward input; NULL = impulse mode
+ *               (same rules as disk_forward).
+ *   saved       device float [(L-1)][C][H][W] from disk_forward (NULL iff L == 1).
+ *   grad_out    device float [C][H][W].
+ * The input adjoint is the exact transpose of the forward gather: with
+ * DISK_CLAMP, border pixels collect the contributions of every clamped read.
+ * Reductions run in a fixed order (deterministic, no float atomics).
+ */
+size_t disk_backward_workspace_size(const disk_complex* cx, int32_t C, int32_t H, int32_t W);
+disk_status disk_backward(const disk_complex* cx, const float* theta, const float* in,
+                          const float* saved, const float* grad_out, float* grad_theta,
+                          float* grad_in, int32_t C, int32_t H, int32_t W, disk_boundary boundary,
+                          void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* ------------------------------------------------------------------------- */
+/* Batched optimisation (Sec. 4.1 Eq. 4, Sec. 4.4 Eq. 10-11, Sec. 5.1 Adam).   */
+/* ------------------------------------------------------------------------- */
+/* One target of a batch; device array [B] of these. */
+typedef struct {
+    int32_t side;        /* odd M, the target is M x M, impulse at its centre */
+    int32_t L;           /* layers */
+    int32_t taps_off;    /* index of taps[L] in the taps array */
+    int32_t theta_off;   /* first row of this target's Theta in the [*][3] array */
+    int32_t target_off;  /* first float of this target's M*M kernel */
+} disk_target;
+
+typedef struct {
+    int32_t max_steps;       /* Adam updates per target (>= 0) */
+    float lr0, lr1;          /* learning rate, linear from lr0 (step 0) to lr1 (last step) */
+    float beta1, beta2, eps; /* Adam */
+    float psnr_stop_db;      /* stop a target once PSNR >= this (INFINITY: never) */
+    int32_t loss;            /* disk_loss */
+    float charb_eps;         /* Charbonnier epsilon on the peak-normalised difference */
+} disk_opt_params;
+
+/*
+ * Fits every target's Theta by Adam on the impulse-response loss, all targets
+ * in one persistent launch.
+ *   desc     device disk_target [B];  taps  device int32 (per-target layer tap counts);
+ *   targets  device float (packed kernels);
+ *   theta    device float [*][3]: in = Theta_0, out = the fitted Theta;
+ *   psnr_db  device float [B]: PSNR of the returned Theta, 10 log10(max(K)^2 / MSE);
+ *   steps    device int32 [B]: Adam updates applied;
+ *   status   device int32 [B]: 0 ok, 1 stopped at the PSNR threshold,
+ *            2 diverged (non-finite loss; Theta left at the last finite value).
+ *   meta     host: B, the maximum side and total taps, used to size the launch.
+ * Loss: normalised MSE, mean((K_syn - K)^2) / max(K)^2, or Charbonnier.
+ */
+typedef struct {
+    int32_t B;
+    int32_t max_side;
+    int32_t max_T;
+} disk_batch_meta;
+size_t disk_optimize_workspace_size(const disk_batch_meta* meta);
+disk_status disk_optimize_batch(const disk_batch_meta* meta, const disk_target* desc,
+                                const int32_t* taps, const float* targets, float* theta,
+                                float* psnr_db, int32_t* steps, int32_t* status,
+                                const disk_opt_params* params, void* ws, size_t ws_bytes,
+                                hipStream_t stream);
+
+/*
+ * Radial initialisation (Sec. 4.1 Eq. 6) of every target of a batch, on the
+ * device: r_l = l * dr with dr = 2R / (L (L+1)), o_{l,i} = r_l (cos 2 pi i/N_l,
+ * sin 2 pi i/N_l) for i = 1..N_l, w = 1/N_l; R = min((M-1)/2, r99) with r99
+ * the smallest pixel-centre distance whose disk holds >= 99% of the target's
+ * mass (the paper defers the step size to an appendix; this is the reading
+ * adopted).  Arguments as in disk_optimize_batch; theta is written.
+ */
+disk_status disk_init_radial(const disk_batch_meta* meta, const disk_target* desc,
+                             const int32_t* taps, const float* targets, float* theta,
+                             hipStream_t stream);
+
+/*
+ * Shape-aware (sparse-sampling) initialisation (Sec. 4.2 Eq. 7), on the host
+ * in FP64: the first layer's taps are dart-thrown over the support
+ * {K > 0.01 max K} with radius r = sqrt(S / (N_1 pi)) (shrunk by 0.9 after
+ * 100 N_1 consecutive rejections), weights proportional to K at the rounded
+ * points; layers 2..L take the radial pattern with extent r.  Random draws:
+ * SplitMix64 stream keyed by (seed, target index).
+ *   target  host float [M][M];  taps host int32 [L];
+ *   theta   host float [T][3] (written);  r_out host (final radius) or NULL.
+ */
+disk_status disk_init_shape(const float* target, int32_t M, int32_t L, const int32_t* taps,
+                            uint64_t seed, int32_t index, float* theta, double* r_out);
+
+/* ------------------------------------------------------------------------- */
+/* Spatially varying filtering by filter-space interpolation (Sec. 4.3).      */
+/* ------------------------------------------------------------------------- */
+/*
+ * A basis (Eq. 8) of G = grid[0] (dims 1) or grid[0]*grid[1] (dims 2) complete
+ * parameter sets sharing one layer structure `cx`, at evenly spaced parameter
+ * values on [0, 1]; entry (i0, i1) is stored at index i0*grid[1] + i1.
+ * halo[l] bounds layer l's offsets: every |ox|, |oy| of layer l in every entry
+ * must be <= halo[l] - 1 (disk_basis_set_halo computes it).
+ */
+typedef struct {
+    int32_t dims;                    /* 1 or 2 */
+    int32_t grid[2];                 /* entries per axis (grid[1] ignored for dims 1) */
+    disk_complex cx;
+    int32_t halo[DISK_MAX_LAYERS];
+} disk_basis;
+
+/* Fills b->halo from a HOST copy of the basis [G][T][3]. */
+disk_status disk_basis_set_halo(disk_basis* b, const float* basis_theta_host);
+
+/*
+ * Per pixel p: u = clamp(P(p), 0, 1) (G - 1) per axis; the interpolation
+ * weights alpha are the hat (1-D) or bilinear (2-D) weights of the nodes
+ * around u (Eq. 9: convex, sum 1); Theta(p) = sum_k alpha_k Theta_k over
+ * offsets and weights; the L layers are applied with each pixel's own taps,
+ * CLAMP boundary, X_l[p] = sum_i w_{l,i}(p) B(X_{l-1}, p - o_{l,i}(p)).
+ *   basis_theta device float [G][T][3];   image device [C][H][W] of dtype io;
+ *   pmap        device float [dims][H][W]; out  device [C][H][W] of dtype io.
+ * If an offset in the basis exceeds its declared halo, the output is filled
+ * with NaN (no out-of-tile reads happen).
+ */
+size_t disk_sv_filter_workspace_size(const disk_basis* b, int32_t C, int32_t H, int32_t W,
+                                     disk_dtype io);
+disk_status disk_sv_filter(const disk_basis* b, const float* basis_theta, const void* image,
+                           const float* pmap, void* out, int32_t C, int32_t H, int32_t W,
+                           disk_dtype io, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/*
+ * The same filter in two steps, for a basis that serves many frames (the
+ * offline/runtime split of Sec. 4.3): disk_sv_prepare turns the basis into the
+ * per-(entry, tap) coefficient table the passes read (and checks the halos);
+ * disk_sv_apply runs the L passes with a prepared table.
+ *   table  device scratch of disk_sv_table_bytes() bytes, owned by the caller,
+ *          valid until the basis changes.
+ *   ws     (apply) device scratch of disk_sv_apply_workspace_size() bytes for
+ *          the FP32 intermediates (may be NULL when L == 1).
+ */
+size_t disk_sv_table_bytes(const disk_basis* b);
+disk_status disk_sv_prepare(const disk_basis* b, const float* basis_theta, void* table,
+                            size_t table_bytes, hipStream_t stream);
+size_t disk_sv_apply_workspace_size(const disk_basis* b, int32_t C, int32_t H, int32_t W,
+                                    disk_dtype io);
+disk_status disk_sv_apply(const disk_basis* b, const void* table, const void* image,
+                          const float* pmap, void* out, int32_t C, int32_t H, int32_t W,
+                          disk_dtype io, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* ------------------------------------------------------------------------- */
+/* Learned initialiser (not in the paper): conv encoder + MLP, BF16 in, FP32   */
+/* accumulate on MFMA.                                                        */
+/* ------------------------------------------------------------------------- */
+/*
+ * Network: 64x64x1 -> 6 x [conv3x3 stride 2 pad 1 + bias + ReLU] with widths
+ * 32, 64, 128, 128, 256, 256 -> FC 256->512 + ReLU -> FC 512->144.  The 144
+ * outputs are Theta for 4 layers x 12 taps: (ox/hw, oy/hw, w) with hw the
+ * target's half-width.
+ * Parameters: one float32 blob of disk_net_param_count() values, in the order
+ * conv1.W [32][1][3][3], conv1.b [32], ..., fc2.W [144][512], fc2.b [144]
+ * (PyTorch layout).  Activations and weights enter each layer rounded to BF16.
+ */
+int64_t disk_net_param_count(void);
+size_t disk_net_workspace_size(int32_t B);
+/*
+ *   params      device float [disk_net_param_count()];
+ *   targets64   device uint16 (bf16 bits) [B][64][64], peak-normalised;
+ *   half_width  device float [B];   theta device float [B][48][3] (written).
+ */
+disk_status disk_init_predict(const float* params, const uint16_t* targets64,
+                              const float* half_width, float* theta, int32_t B, void* ws,
+                              size_t ws_bytes, hipStream_t stream);
+/*
+ * One training step: forward, MSE against theta_ref (normalised units, [B][144]),
+ * backward, Adam on the FP32 master parameters (m, v: device float, same size).
+ * loss_out: device float [1] (mean squared error of this batch before the update).
+ */
+disk_status disk_net_train_step(float* params, float* adam_m, float* adam_v, int32_t step,
+                                float lr, const uint16_t* targets64, const float* theta_ref,
+                                int32_t B, float* loss_out, void* ws, size_t ws_bytes,
+                                hipStream_t stream);
+/* Resize targets to the network input: zero-pad up to 64 or area-average down,
+ * peak-normalise, round to BF16.  desc/targets as in disk_optimize_batch. */
+disk_status disk_net_prepare_inputs(const disk_batch_meta* meta, const disk_target* desc,
+                                    const float* targets, uint16_t* targets64,
+                                    float* half_width, hipStream_t stream);
+/* Scatter the network's [B][48][3] prediction into the batch's Theta layout
+ * (targets must have L = 4, 12 taps per layer). */
+disk_status disk_net_scatter_theta(const disk_batch_meta* meta, const disk_target* desc,
+                                   const float* theta48, float* theta, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DISK_H */

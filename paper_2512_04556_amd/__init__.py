@@ -1,0 +1,393 @@
+"""Python binding of libdisk (ctypes): argument marshalling only.
+
+Every function forwards to the C entry point of the same name in libdisk.so
+(declared in include/disk.h); torch supplies device memory (outputs and the
+workspace each call needs) and the current stream.  There is no fallback: if
+libdisk.so is missing, or a tensor is not on the GPU, the call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, c_double, c_float, c_int32, c_int64, c_size_t, c_uint64, c_void_p
+
+import torch
+
+__all__ = [
+    "lib", "DiskError", "ZERO", "CLAMP", "F32", "BF16", "LOSS_NMSE", "LOSS_CHARBONNIER",
+    "disk_forward", "disk_backward", "disk_sv_filter", "disk_sv_prepare", "disk_sv_apply", "Basis", "make_basis",
+    "disk_optimize_batch", "disk_init_radial", "disk_init_shape", "OptParams", "Batch", "make_batch",
+    "disk_init_predict", "disk_net_train_step", "disk_net_prepare_inputs", "disk_net_scatter_theta",
+    "disk_net_param_count",
+]
+
+ZERO, CLAMP = 0, 1
+F32, BF16 = 0, 1
+LOSS_NMSE, LOSS_CHARBONNIER = 0, 1
+MAX_LAYERS = 8
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB = None
+
+
+class DiskError(RuntimeError):
+    pass
+
+
+class DiskComplex(ctypes.Structure):
+    _fields_ = [("L", c_int32), ("taps", c_int32 * MAX_LAYERS)]
+
+
+class DiskBasis(ctypes.Structure):
+    _fields_ = [("dims", c_int32), ("grid", c_int32 * 2), ("cx", DiskComplex), ("halo", c_int32 * MAX_LAYERS)]
+
+
+class DiskOptParams(ctypes.Structure):
+    _fields_ = [("max_steps", c_int32), ("lr0", c_float), ("lr1", c_float), ("beta1", c_float),
+                ("beta2", c_float), ("eps", c_float), ("psnr_stop_db", c_float), ("loss", c_int32),
+                ("charb_eps", c_float)]
+
+
+class DiskBatchMeta(ctypes.Structure):
+    _fields_ = [("B", c_int32), ("max_side", c_int32), ("max_T", c_int32)]
+
+
+def lib():
+    """Load libdisk.so from the package directory (raises if it was not built)."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    path = os.path.join(_HERE, "libdisk.so")
+    if not os.path.exists(path):
+        raise DiskError(f"{path} is missing: build it with `python -m paper_2512_04556_amd.build`")
+    L = ctypes.CDLL(path)
+    P = c_void_p
+    sig = {
+        "disk_status_string": (ctypes.c_char_p, [c_int32]),
+        "disk_last_error": (ctypes.c_char_p, []),
+        "disk_version": (ctypes.c_char_p, []),
+        "disk_forward_workspace_size": (c_size_t, [POINTER(DiskComplex), c_int32, c_int32, c_int32, c_int32, c_int32, c_int32]),
+        "disk_forward": (c_int32, [POINTER(DiskComplex), P, P, P, c_int32, c_int32, c_int32, c_int32, c_int32, P, P, c_size_t, P]),
+        "disk_backward_workspace_size": (c_size_t, [POINTER(DiskComplex), c_int32, c_int32, c_int32]),
+        "disk_backward": (c_int32, [POINTER(DiskComplex), P, P, P, P, P, P, c_int32, c_int32, c_int32, c_int32, P, c_size_t, P]),
+        "disk_optimize_workspace_size": (c_size_t, [POINTER(DiskBatchMeta)]),
+        "disk_optimize_batch": (c_int32, [POINTER(DiskBatchMeta), P, P, P, P, P, P, P, POINTER(DiskOptParams), P, c_size_t, P]),
+        "disk_init_radial": (c_int32, [POINTER(DiskBatchMeta), P, P, P, P, P]),
+        "disk_init_shape": (c_int32, [P, c_int32, c_int32, P, c_uint64, c_int32, P, POINTER(c_double)]),
+        "disk_basis_set_halo": (c_int32, [POINTER(DiskBasis), P]),
+        "disk_sv_filter_workspace_size": (c_size_t, [POINTER(DiskBasis), c_int32, c_int32, c_int32, c_int32]),
+        "disk_sv_filter": (c_int32, [POINTER(DiskBasis), P, P, P, P, c_int32, c_int32, c_int32, c_int32, P, c_size_t, P]),
+        "disk_sv_table_bytes": (c_size_t, [POINTER(DiskBasis)]),
+        "disk_sv_prepare": (c_int32, [POINTER(DiskBasis), P, P, c_size_t, P]),
+        "disk_sv_apply_workspace_size": (c_size_t, [POINTER(DiskBasis), c_int32, c_int32, c_int32, c_int32]),
+        "disk_sv_apply": (c_int32, [POINTER(DiskBasis), P, P, P, P, c_int32, c_int32, c_int32, c_int32, P, c_size_t, P]),
+        "disk_net_param_count": (c_int64, []),
+        "disk_net_workspace_size": (c_size_t, [c_int32]),
+        "disk_init_predict": (c_int32, [P, P, P, P, c_int32, P, c_size_t, P]),
+        "disk_net_train_step": (c_int32, [P, P, P, c_int32, c_float, P, P, c_int32, P, P, c_size_t, P]),
+        "disk_net_prepare_inputs": (c_int32, [POINTER(DiskBatchMeta), P, P, P, P, P]),
+        "disk_net_scatter_theta": (c_int32, [POINTER(DiskBatchMeta), P, P, P, P]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    _LIB = L
+    return L
+
+
+def _check(status: int):
+    if status != 0:
+        L = lib()
+        raise DiskError(f"{L.disk_status_string(status).decode()}: {L.disk_last_error().decode()}")
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("expected a torch.Tensor")
+    if not t.is_contiguous():
+        raise DiskError("tensor must be contiguous")
+    return c_void_p(t.data_ptr())
+
+
+def _dev(t, name):
+    if t is not None and not t.is_cuda:
+        raise DiskError(f"{name} must be a GPU tensor")
+
+
+def _stream():
+    return c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _complex(taps):
+    taps = [int(t) for t in taps]
+    cx = DiskComplex()
+    cx.L = len(taps)
+    if not 1 <= cx.L <= MAX_LAYERS:
+        raise DiskError(f"L={cx.L} out of range")
+    for i, t in enumerate(taps):
+        cx.taps[i] = t
+    return cx
+
+
+def _workspace(nbytes, device):
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+
+
+def _io_dtype(t):
+    if t.dtype == torch.float32:
+        return F32
+    if t.dtype == torch.bfloat16:
+        return BF16
+    raise DiskError(f"unsupported image dtype {t.dtype}")
+
+
+# ---------------------------------------------------------------------------
+def disk_forward(theta, taps, inp=None, *, H=None, W=None, boundary=CLAMP, save=False, out=None):
+    """Chain forward.  ``inp`` [C][H][W] (f32/bf16) or None for the impulse
+    response on an H x W canvas.  Returns (out, saved) with saved the
+    intermediates [(L-1)][C][H][W] when ``save``."""
+    _dev(theta, "theta")
+    dev = theta.device
+    cx = _complex(taps)
+    if inp is None:
+        C, io, impulse = 1, F32, 1
+        H = int(H)
+        W = int(W if W is not None else H)
+        boundary = ZERO
+    else:
+        _dev(inp, "inp")
+        C, H, W = inp.shape
+        io, impulse = _io_dtype(inp), 0
+    if out is None:
+        out = torch.empty((C, H, W), dtype=torch.float32 if io == F32 else torch.bfloat16, device=dev)
+    saved = torch.empty((max(cx.L - 1, 1), C, H, W), dtype=torch.float32, device=dev) if save else None
+    L = lib()
+    nws = L.disk_forward_workspace_size(ctypes.byref(cx), C, H, W, io, impulse, int(save))
+    ws = _workspace(nws, dev)
+    _check(L.disk_forward(ctypes.byref(cx), _ptr(theta), _ptr(inp), _ptr(out), C, H, W, io, boundary,
+                          _ptr(saved) if save else None, _ptr(ws), ws.numel(), _stream()))
+    return out, saved
+
+
+def disk_backward(theta, taps, inp, saved, grad_out, *, boundary=CLAMP, need_theta=True, need_input=True):
+    """Adjoint.  Returns (grad_theta [T][3] or None, grad_in [C][H][W] or None)."""
+    _dev(theta, "theta")
+    _dev(grad_out, "grad_out")
+    dev = theta.device
+    cx = _complex(taps)
+    C, H, W = grad_out.shape
+    if inp is None:
+        boundary = ZERO
+    gt = torch.empty_like(theta) if need_theta else None
+    gi = torch.empty((C, H, W), dtype=torch.float32, device=dev) if need_input else None
+    L = lib()
+    ws = _workspace(L.disk_backward_workspace_size(ctypes.byref(cx), C, H, W), dev)
+    _check(L.disk_backward(ctypes.byref(cx), _ptr(theta), _ptr(inp), _ptr(saved), _ptr(grad_out), _ptr(gt),
+                           _ptr(gi), C, H, W, boundary, _ptr(ws), ws.numel(), _stream()))
+    return gt, gi
+
+
+# ---------------------------------------------------------------------------
+class Basis:
+    """A filter-space basis: device tensor [G][T][3] plus its C descriptor."""
+
+    def __init__(self, theta, taps, grid):
+        self.theta = theta.contiguous()
+        self.taps = [int(t) for t in taps]
+        self.grid = [int(g) for g in grid]
+        d = DiskBasis()
+        d.dims = len(self.grid)
+        d.grid[0] = self.grid[0]
+        d.grid[1] = self.grid[1] if len(self.grid) > 1 else 1
+        d.cx = _complex(self.taps)
+        host = self.theta.detach().to("cpu", torch.float32).contiguous()
+        _check(lib().disk_basis_set_halo(ctypes.byref(d), _ptr(host)))
+        self.desc = d
+
+    @property
+    def halo(self):
+        return [self.desc.halo[l] for l in range(len(self.taps))]
+
+
+def make_basis(theta, taps, grid):
+    return Basis(theta, taps, grid)
+
+
+def disk_sv_filter(basis: Basis, image, pmap, out=None, ws=None):
+    """Spatially varying filter of ``image`` [C][H][W] (f32/bf16) with the
+    per-pixel parameters ``pmap`` [dims][H][W] (f32)."""
+    _dev(image, "image")
+    _dev(pmap, "pmap")
+    C, H, W = image.shape
+    io = _io_dtype(image)
+    if out is None:
+        out = torch.empty_like(image)
+    L = lib()
+    nws = L.disk_sv_filter_workspace_size(ctypes.byref(basis.desc), C, H, W, io)
+    if ws is None or ws.numel() < nws:
+        ws = _workspace(nws, image.device)
+    _check(L.disk_sv_filter(ctypes.byref(basis.desc), _ptr(basis.theta), _ptr(image), _ptr(pmap), _ptr(out),
+                            C, H, W, io, _ptr(ws), ws.numel(), _stream()))
+    return out
+
+
+def sv_filter_workspace(basis: Basis, C, H, W, io=F32, device="cuda"):
+    nws = lib().disk_sv_filter_workspace_size(ctypes.byref(basis.desc), C, H, W, io)
+    return _workspace(nws, device)
+
+
+def disk_sv_prepare(basis: Basis, table=None):
+    """Coefficient table of a basis (device uint8 tensor), for disk_sv_apply."""
+    L = lib()
+    nb = L.disk_sv_table_bytes(ctypes.byref(basis.desc))
+    if table is None or table.numel() < nb:
+        table = _workspace(nb, basis.theta.device)
+    _check(L.disk_sv_prepare(ctypes.byref(basis.desc), _ptr(basis.theta), _ptr(table), table.numel(), _stream()))
+    return table
+
+
+def disk_sv_apply(basis: Basis, table, image, pmap, out=None, ws=None):
+    """The L passes of the SV filter with a prepared table."""
+    _dev(image, "image")
+    _dev(pmap, "pmap")
+    C, H, W = image.shape
+    io = _io_dtype(image)
+    if out is None:
+        out = torch.empty_like(image)
+    L = lib()
+    nws = L.disk_sv_apply_workspace_size(ctypes.byref(basis.desc), C, H, W, io)
+    if ws is None or ws.numel() < nws:
+        ws = _workspace(nws, image.device)
+    _check(L.disk_sv_apply(ctypes.byref(basis.desc), _ptr(table), _ptr(image), _ptr(pmap), _ptr(out), C, H, W, io,
+                           _ptr(ws), ws.numel(), _stream()))
+    return out
+
+
+# ---------------------------------------------------------------------------
+# batched optimisation and initialisers
+# ---------------------------------------------------------------------------
+class OptParams:
+    def __init__(self, max_steps=1000, lr0=1e-2, lr1=1e-3, beta1=0.9, beta2=0.999, eps=1e-8,
+                 psnr_stop_db=float("inf"), loss=LOSS_NMSE, charb_eps=1e-3):
+        self.c = DiskOptParams(int(max_steps), lr0, lr1, beta1, beta2, eps, psnr_stop_db, int(loss), charb_eps)
+
+
+class Batch:
+    """Packed batch of targets on the device (layout of disk_target)."""
+
+    def __init__(self, desc, taps, targets, max_side, max_T):
+        self.desc = desc          # int32 [B][5] device
+        self.taps = taps          # int32 device
+        self.targets = targets    # float32 device
+        self.meta = DiskBatchMeta(int(desc.shape[0]), int(max_side), int(max_T))
+        self.T_total = None
+
+    @property
+    def B(self):
+        return self.meta.B
+
+
+def make_batch(desc, taps, targets, device="cuda"):
+    """desc int32 [B][5] = (side, L, taps_off, theta_off, target_off) (numpy or
+    tensor), taps int32, targets float32 (packed kernels)."""
+    d = torch.as_tensor(desc, dtype=torch.int32)
+    tp = torch.as_tensor(taps, dtype=torch.int32)
+    tg = torch.as_tensor(targets, dtype=torch.float32)
+    max_side = int(d[:, 0].max())
+    Ts = [int(tp[int(d[b, 2]):int(d[b, 2]) + int(d[b, 1])].sum()) for b in range(d.shape[0])]
+    bt = Batch(d.to(device).contiguous(), tp.to(device).contiguous(), tg.to(device).contiguous(), max_side, max(Ts))
+    bt.T_total = int(max(int(d[b, 3]) + Ts[b] for b in range(d.shape[0])))
+    return bt
+
+
+def disk_optimize_batch(batch: Batch, theta, params: OptParams):
+    """Optimise every target of ``batch`` in place on ``theta`` [*][3].
+    Returns (psnr_db [B], steps [B], status [B])."""
+    dev = theta.device
+    B = batch.B
+    psnr = torch.empty(B, dtype=torch.float32, device=dev)
+    steps = torch.empty(B, dtype=torch.int32, device=dev)
+    status = torch.empty(B, dtype=torch.int32, device=dev)
+    L = lib()
+    ws = _workspace(L.disk_optimize_workspace_size(ctypes.byref(batch.meta)), dev)
+    _check(L.disk_optimize_batch(ctypes.byref(batch.meta), _ptr(batch.desc), _ptr(batch.taps), _ptr(batch.targets),
+                                 _ptr(theta), _ptr(psnr), _ptr(steps), _ptr(status), ctypes.byref(params.c),
+                                 _ptr(ws), ws.numel(), _stream()))
+    return psnr, steps, status
+
+
+def disk_init_radial(batch: Batch, theta=None):
+    dev = batch.desc.device
+    if theta is None:
+        theta = torch.empty((batch.T_total, 3), dtype=torch.float32, device=dev)
+    _check(lib().disk_init_radial(ctypes.byref(batch.meta), _ptr(batch.desc), _ptr(batch.taps), _ptr(batch.targets),
+                                  _ptr(theta), _stream()))
+    return theta
+
+
+def disk_init_shape(target, taps, seed, index=0):
+    """Host FP64 shape-aware init of one target (numpy/torch CPU float32 [M][M]).
+    Returns (theta float32 [T][3] CPU tensor, final radius)."""
+    t = torch.as_tensor(target, dtype=torch.float32).contiguous()
+    tp = torch.as_tensor([int(x) for x in taps], dtype=torch.int32).contiguous()
+    T = int(tp.sum())
+    out = torch.empty((T, 3), dtype=torch.float32)
+    r = c_double(0.0)
+    _check(lib().disk_init_shape(_ptr(t), int(t.shape[0]), int(tp.numel()), _ptr(tp), c_uint64(int(seed)),
+                                 int(index), _ptr(out), ctypes.byref(r)))
+    return out, r.value
+
+
+# ---------------------------------------------------------------------------
+# learned initialiser
+# ---------------------------------------------------------------------------
+def disk_net_param_count():
+    return int(lib().disk_net_param_count())
+
+
+def disk_init_predict(params, targets64, half_width):
+    B = int(targets64.shape[0])
+    dev = params.device
+    theta = torch.empty((B, 48, 3), dtype=torch.float32, device=dev)
+    L = lib()
+    ws = _workspace(L.disk_net_workspace_size(B), dev)
+    _check(L.disk_init_predict(_ptr(params), _ptr(targets64), _ptr(half_width), _ptr(theta), B, _ptr(ws),
+                               ws.numel(), _stream()))
+    return theta
+
+
+def disk_net_train_step(params, m, v, step, lr, targets64, theta_ref, ws=None):
+    B = int(targets64.shape[0])
+    dev = params.device
+    loss = torch.empty(1, dtype=torch.float32, device=dev)
+    L = lib()
+    nws = L.disk_net_workspace_size(B)
+    if ws is None or ws.numel() < nws:
+        ws = _workspace(nws, dev)
+    _check(L.disk_net_train_step(_ptr(params), _ptr(m), _ptr(v), int(step), float(lr), _ptr(targets64),
+                                 _ptr(theta_ref), B, _ptr(loss), _ptr(ws), ws.numel(), _stream()))
+    return loss
+
+
+def disk_net_prepare_inputs(batch: Batch):
+    dev = batch.desc.device
+    x = torch.empty((batch.B, 64, 64), dtype=torch.int16, device=dev)
+    hw = torch.empty(batch.B, dtype=torch.float32, device=dev)
+    _check(lib().disk_net_prepare_inputs(ctypes.byref(batch.meta), _ptr(batch.desc), _ptr(batch.targets), _ptr(x),
+                                         _ptr(hw), _stream()))
+    return x, hw
+
+
+def disk_net_scatter_theta(batch: Batch, theta48, theta=None):
+    dev = batch.desc.device
+    if theta is None:
+        theta = torch.empty((batch.T_total, 3), dtype=torch.float32, device=dev)
+    _check(lib().disk_net_scatter_theta(ctypes.byref(batch.meta), _ptr(batch.desc), _ptr(theta48), _ptr(theta),
+                                        _stream()))
+    return theta
+
+
+from .autograd import DiskChain  # noqa: E402  (torch.autograd.Function over disk_forward/backward)

@@ -1,0 +1,391 @@
+// C ABI of libdisk: argument validation, workspace carving and dispatch to
+// the HIP kernels.  Nothing here allocates device memory, throws, exits or
+// prints; failures return a negative disk_status with a thread-local message.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "internal.hpp"
+
+using namespace disk;
+
+namespace {
+
+thread_local std::string g_err;
+
+disk_status fail(disk_status s, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    std::vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return s;
+}
+
+disk_status ok() {
+    g_err.clear();
+    return DISK_OK;
+}
+
+disk_status hip_check(hipError_t e, const char* what) {
+    if (e != hipSuccess) return fail(DISK_DEVICE, "%s: %s", what, hipGetErrorString(e));
+    return DISK_OK;
+}
+
+#define DISK_TRY(expr)                          \
+    do {                                        \
+        disk_status _s = (expr);                \
+        if (_s != DISK_OK) return _s;           \
+    } while (0)
+#define DISK_HIP(expr, what) DISK_TRY(hip_check((expr), what))
+
+bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+disk_status check_ptr(const void* p, const char* name, bool nullable = false) {
+    if (!p) return nullable ? DISK_OK : fail(DISK_INVALID_ARG, "%s is NULL", name);
+    if (!aligned16(p)) return fail(DISK_INVALID_ARG, "%s is not 16-byte aligned", name);
+    return DISK_OK;
+}
+
+disk_status check_complex(const disk_complex* cx) {
+    if (!cx) return fail(DISK_INVALID_ARG, "complex is NULL");
+    if (cx->L < 1 || cx->L > DISK_MAX_LAYERS) return fail(DISK_BAD_SHAPE, "L=%d out of [1,%d]", cx->L, DISK_MAX_LAYERS);
+    for (int l = 0; l < cx->L; ++l)
+        if (cx->taps[l] < 1 || cx->taps[l] > DISK_MAX_TAPS)
+            return fail(DISK_BAD_SHAPE, "taps[%d]=%d out of [1,%d]", l, cx->taps[l], DISK_MAX_TAPS);
+    return DISK_OK;
+}
+
+disk_status check_image(int C, int H, int W) {
+    if (C < 1 || C > DISK_MAX_CHANNELS) return fail(DISK_BAD_SHAPE, "C=%d out of [1,%d]", C, DISK_MAX_CHANNELS);
+    if (H < 1 || W < 1) return fail(DISK_BAD_SHAPE, "H=%d W=%d must be >= 1", H, W);
+    if (static_cast<int64_t>(H) * W > (int64_t(1) << 30)) return fail(DISK_BAD_SHAPE, "image too large");
+    return DISK_OK;
+}
+
+// Bump allocator over the caller's workspace (256-byte aligned slices).
+struct Carve {
+    char* base;
+    size_t cap, used = 0;
+    Carve(void* b, size_t c) : base(static_cast<char*>(b)), cap(c) {}
+    template <typename T>
+    T* take(size_t n) {
+        used = (used + 255) & ~size_t(255);
+        T* p = base ? reinterpret_cast<T*>(base + used) : nullptr;
+        used += n * sizeof(T);
+        return p;
+    }
+};
+
+size_t image_floats(int C, int H, int W) { return static_cast<size_t>(C) * H * W; }
+
+}  // namespace
+
+extern "C" {
+
+const char* disk_status_string(disk_status s) {
+    switch (s) {
+        case DISK_OK: return "DISK_OK";
+        case DISK_INVALID_ARG: return "DISK_INVALID_ARG";
+        case DISK_BAD_SHAPE: return "DISK_BAD_SHAPE";
+        case DISK_WORKSPACE_TOO_SMALL: return "DISK_WORKSPACE_TOO_SMALL";
+        case DISK_DEVICE: return "DISK_DEVICE";
+        case DISK_UNSUPPORTED: return "DISK_UNSUPPORTED";
+    }
+    return "DISK_UNKNOWN";
+}
+
+const char* disk_last_error(void) { return g_err.c_str(); }
+const char* disk_version(void) { return "libdisk 0.1 gfx950"; }
+
+// ---------------------------------------------------------------------------
+// forward
+// ---------------------------------------------------------------------------
+static size_t forward_ws(const disk_complex* cx, int C, int H, int W, bool has_saved, Carve& cv,
+                         TapU** tapu, float** buf0, float** buf1) {
+    const LayerSpec sp = make_spec(*cx);
+    *tapu = cv.take<TapU>(sp.T);
+    const int nbuf = has_saved ? 0 : std::min(cx->L - 1, 2);
+    *buf0 = nbuf >= 1 ? cv.take<float>(image_floats(C, H, W)) : nullptr;
+    *buf1 = nbuf >= 2 ? cv.take<float>(image_floats(C, H, W)) : nullptr;
+    return cv.used;
+}
+
+size_t disk_forward_workspace_size(const disk_complex* cx, int32_t C, int32_t H, int32_t W, disk_dtype,
+                                   int32_t, int32_t has_saved) {
+    if (!cx || cx->L < 1 || cx->L > DISK_MAX_LAYERS) return 0;
+    Carve cv(nullptr, 0);
+    TapU* t;
+    float *a, *b;
+    return forward_ws(cx, C, H, W, has_saved != 0, cv, &t, &a, &b) + 256;
+}
+
+disk_status disk_forward(const disk_complex* cx, const float* theta, const void* in, void* out, int32_t C,
+                         int32_t H, int32_t W, disk_dtype io, disk_boundary boundary, float* saved, void* ws,
+                         size_t ws_bytes, hipStream_t stream) {
+    DISK_TRY(check_complex(cx));
+    DISK_TRY(check_image(C, H, W));
+    DISK_TRY(check_ptr(theta, "theta"));
+    DISK_TRY(check_ptr(in, "in", true));
+    DISK_TRY(check_ptr(out, "out"));
+    DISK_TRY(check_ptr(saved, "saved", true));
+    DISK_TRY(check_ptr(ws, "ws", true));
+    if (io != DISK_F32 && io != DISK_BF16) return fail(DISK_INVALID_ARG, "bad dtype %d", int(io));
+    if (boundary != DISK_ZERO && boundary != DISK_CLAMP) return fail(DISK_INVALID_ARG, "bad boundary %d", int(boundary));
+    const bool impulse = in == nullptr;
+    if (impulse) {
+        if (C != 1) return fail(DISK_BAD_SHAPE, "impulse mode needs C == 1");
+        if ((H & 1) == 0 || (W & 1) == 0) return fail(DISK_BAD_SHAPE, "impulse mode needs odd sides (H=%d W=%d)", H, W);
+        if (boundary != DISK_ZERO) return fail(DISK_INVALID_ARG, "impulse mode needs DISK_ZERO");
+        if (io != DISK_F32) return fail(DISK_INVALID_ARG, "impulse mode needs DISK_F32");
+    }
+    Carve cv(ws, ws_bytes);
+    TapU* tapu;
+    float *b0, *b1;
+    forward_ws(cx, C, H, W, saved != nullptr, cv, &tapu, &b0, &b1);
+    if (!ws || cv.used > ws_bytes)
+        return fail(DISK_WORKSPACE_TOO_SMALL, "workspace %zu < %zu bytes", ws_bytes, cv.used);
+    const LayerSpec sp = make_spec(*cx);
+    const size_t n = image_floats(C, H, W);
+    DISK_HIP(launch_prep_uniform(theta, sp.T, tapu, stream), "prep");
+    const int io_kind = io == DISK_BF16 ? 1 : 0;
+    for (int l = 0; l < sp.L; ++l) {
+        const void* src;
+        int src_kind;
+        if (l == 0) {
+            src = in;
+            src_kind = impulse ? 2 : io_kind;
+        } else {
+            src = saved ? saved + (l - 1) * n : ((l - 1) % 2 ? b1 : b0);
+            src_kind = 0;
+        }
+        void* dst;
+        int dst_kind;
+        if (l == sp.L - 1) {
+            dst = out;
+            dst_kind = io_kind;
+        } else {
+            dst = saved ? saved + l * n : (l % 2 ? b1 : b0);
+            dst_kind = 0;
+        }
+        DISK_HIP(launch_layer_uniform(C, boundary, src_kind, src, dst_kind, dst, tapu + sp.tap0[l], sp.taps[l], H, W,
+                                      stream),
+                 "layer");
+    }
+    return ok();
+}
+
+// ---------------------------------------------------------------------------
+// backward
+// ---------------------------------------------------------------------------
+static size_t backward_ws(const disk_complex* cx, int C, int H, int W, Carve& cv, TapU** tapu, float** partial,
+                          float** g0, float** g1) {
+    const LayerSpec sp = make_spec(*cx);
+    int maxN = 0;
+    for (int l = 0; l < sp.L; ++l) maxN = std::max(maxN, sp.taps[l]);
+    const int nblk = adjoint_tap_blocks(H, W);
+    *tapu = cv.take<TapU>(sp.T);
+    *partial = cv.take<float>(static_cast<size_t>(nblk) * maxN * 4 + maxN * 4);
+    *g0 = cv.take<float>(image_floats(C, H, W));
+    *g1 = cv.take<float>(image_floats(C, H, W));
+    return cv.used;
+}
+
+size_t disk_backward_workspace_size(const disk_complex* cx, int32_t C, int32_t H, int32_t W) {
+    if (!cx || cx->L < 1 || cx->L > DISK_MAX_LAYERS || H < 1 || W < 1) return 0;
+    Carve cv(nullptr, 0);
+    TapU* t;
+    float *p, *a, *b;
+    return backward_ws(cx, C, H, W, cv, &t, &p, &a, &b) + 256;
+}
+
+disk_status disk_backward(const disk_complex* cx, const float* theta, const float* in, const float* saved,
+                          const float* grad_out, float* grad_theta, float* grad_in, int32_t C, int32_t H, int32_t W,
+                          disk_boundary boundary, void* ws, size_t ws_bytes, hipStream_t stream) {
+    DISK_TRY(check_complex(cx));
+    DISK_TRY(check_image(C, H, W));
+    DISK_TRY(check_ptr(theta, "theta"));
+    DISK_TRY(check_ptr(in, "in", true));
+    DISK_TRY(check_ptr(grad_out, "grad_out"));
+    DISK_TRY(check_ptr(grad_theta, "grad_theta", true));
+    DISK_TRY(check_ptr(grad_in, "grad_in", true));
+    if (boundary != DISK_ZERO && boundary != DISK_CLAMP) return fail(DISK_INVALID_ARG, "bad boundary %d", int(boundary));
+    if (cx->L > 1) DISK_TRY(check_ptr(saved, "saved"));
+    const bool impulse = in == nullptr;
+    if (impulse) {
+        if (C != 1) return fail(DISK_BAD_SHAPE, "impulse mode needs C == 1");
+        if ((H & 1) == 0 || (W & 1) == 0) return fail(DISK_BAD_SHAPE, "impulse mode needs odd sides (H=%d W=%d)", H, W);
+        if (boundary != DISK_ZERO) return fail(DISK_INVALID_ARG, "impulse mode needs DISK_ZERO");
+    }
+    Carve cv(ws, ws_bytes);
+    TapU* tapu;
+    float *partial, *g0, *g1;
+    backward_ws(cx, C, H, W, cv, &tapu, &partial, &g0, &g1);
+    if (!ws || cv.used > ws_bytes)
+        return fail(DISK_WORKSPACE_TOO_SMALL, "workspace %zu < %zu bytes", ws_bytes, cv.used);
+    const LayerSpec sp = make_spec(*cx);
+    const size_t n = image_floats(C, H, W);
+    const int nblk = adjoint_tap_blocks(H, W);
+    DISK_HIP(launch_prep_uniform(theta, sp.T, tapu, stream), "prep");
+    const float* G = grad_out;
+    for (int l = sp.L - 1; l >= 0; --l) {
+        const void* X = l == 0 ? static_cast<const void*>(in) : static_cast<const void*>(saved + (l - 1) * n);
+        const int src_kind = (l == 0 && impulse) ? 2 : 0;
+        if (grad_theta) {
+            DISK_HIP(launch_adjoint_taps(C, boundary, src_kind, X, G, tapu + sp.tap0[l], sp.taps[l], H, W, partial,
+                                         stream),
+                     "adjoint taps");
+            DISK_HIP(launch_adjoint_finish(partial, nblk, theta + 3 * sp.tap0[l], tapu + sp.tap0[l], sp.taps[l],
+                                           grad_theta + 3 * sp.tap0[l], stream),
+                     "adjoint finish");
+        }
+        if (l > 0 || grad_in) {
+            float* Gn = l == 0 ? grad_in : (G == g0 ? g1 : g0);
+            DISK_HIP(launch_adjoint_input(C, boundary, G, tapu + sp.tap0[l], sp.taps[l], H, W, 0, nullptr, Gn, stream),
+                     "adjoint input");
+            G = Gn;
+        }
+    }
+    return ok();
+}
+
+// ---------------------------------------------------------------------------
+// spatially varying filter
+// ---------------------------------------------------------------------------
+static int basis_entries(const disk_basis* b) { return b->dims == 1 ? b->grid[0] : b->grid[0] * b->grid[1]; }
+
+static disk_status check_basis(const disk_basis* b) {
+    if (!b) return fail(DISK_INVALID_ARG, "basis is NULL");
+    DISK_TRY(check_complex(&b->cx));
+    if (b->dims != 1 && b->dims != 2) return fail(DISK_BAD_SHAPE, "basis dims=%d (1 or 2)", b->dims);
+    if (b->grid[0] < 1 || (b->dims == 2 && b->grid[1] < 1) || basis_entries(b) > 4096)
+        return fail(DISK_BAD_SHAPE, "basis grid out of range");
+    for (int l = 0; l < b->cx.L; ++l)
+        if (b->halo[l] < 1 || b->halo[l] > DISK_MAX_HALO)
+            return fail(DISK_UNSUPPORTED, "halo[%d]=%d outside [1,%d]", l, b->halo[l], DISK_MAX_HALO);
+    return DISK_OK;
+}
+
+disk_status disk_basis_set_halo(disk_basis* b, const float* basis_theta_host) {
+    if (!b || !basis_theta_host) return fail(DISK_INVALID_ARG, "NULL argument");
+    DISK_TRY(check_complex(&b->cx));
+    if (b->dims != 1 && b->dims != 2) return fail(DISK_BAD_SHAPE, "basis dims=%d (1 or 2)", b->dims);
+    const LayerSpec sp = make_spec(b->cx);
+    const int G = basis_entries(b);
+    for (int l = 0; l < sp.L; ++l) {
+        double m = 0.0;
+        for (int e = 0; e < G; ++e)
+            for (int i = sp.tap0[l]; i < sp.tap0[l] + sp.taps[l]; ++i) {
+                const float* r = basis_theta_host + (static_cast<size_t>(e) * sp.T + i) * 3;
+                if (!std::isfinite(r[0]) || !std::isfinite(r[1]) || !std::isfinite(r[2]))
+                    return fail(DISK_INVALID_ARG, "non-finite basis value (entry %d tap %d)", e, i);
+                m = std::max(m, std::max(std::fabs(double(r[0])), std::fabs(double(r[1]))));
+            }
+        b->halo[l] = static_cast<int32_t>(std::ceil(m)) + 1;
+    }
+    for (int l = sp.L; l < DISK_MAX_LAYERS; ++l) b->halo[l] = 0;
+    return ok();
+}
+
+static size_t sv_table_bytes_of(const disk_basis* b) {
+    const LayerSpec sp = make_spec(b->cx);
+    return ((sv_table_floats(b->dims, basis_entries(b), sp.T) * sizeof(float) + 255) & ~size_t(255)) + 256;
+}
+
+static size_t sv_apply_ws(const disk_basis* b, int C, int H, int W, Carve& cv, float** b0, float** b1) {
+    const int nbuf = std::min(b->cx.L - 1, 2);
+    *b0 = nbuf >= 1 ? cv.take<float>(image_floats(C, H, W)) : nullptr;
+    *b1 = nbuf >= 2 ? cv.take<float>(image_floats(C, H, W)) : nullptr;
+    return cv.used;
+}
+
+size_t disk_sv_table_bytes(const disk_basis* b) {
+    if (!b || b->cx.L < 1 || b->cx.L > DISK_MAX_LAYERS || (b->dims != 1 && b->dims != 2)) return 0;
+    return sv_table_bytes_of(b);
+}
+
+size_t disk_sv_apply_workspace_size(const disk_basis* b, int32_t C, int32_t H, int32_t W, disk_dtype) {
+    if (!b || b->cx.L < 1 || b->cx.L > DISK_MAX_LAYERS) return 0;
+    Carve cv(nullptr, 0);
+    float *a, *c;
+    return sv_apply_ws(b, C, H, W, cv, &a, &c) + 256;
+}
+
+size_t disk_sv_filter_workspace_size(const disk_basis* b, int32_t C, int32_t H, int32_t W, disk_dtype io) {
+    const size_t t = disk_sv_table_bytes(b);
+    if (!t) return 0;
+    return t + disk_sv_apply_workspace_size(b, C, H, W, io);
+}
+
+disk_status disk_sv_prepare(const disk_basis* b, const float* basis_theta, void* table, size_t table_bytes,
+                            hipStream_t stream) {
+    DISK_TRY(check_basis(b));
+    DISK_TRY(check_ptr(basis_theta, "basis_theta"));
+    DISK_TRY(check_ptr(table, "table"));
+    if (table_bytes < sv_table_bytes_of(b))
+        return fail(DISK_WORKSPACE_TOO_SMALL, "table %zu < %zu bytes", table_bytes, sv_table_bytes_of(b));
+    const LayerSpec sp = make_spec(b->cx);
+    const int G0 = b->grid[0], G1 = b->dims == 2 ? b->grid[1] : 1;
+    float* tab = static_cast<float*>(table);
+    int* flag = reinterpret_cast<int*>(static_cast<char*>(table) + sv_table_bytes_of(b) - 256);
+    DISK_HIP(launch_sv_prep(b->dims, G0, G1, sp, b->halo, basis_theta, tab, flag, stream), "sv prep");
+    return ok();
+}
+
+disk_status disk_sv_apply(const disk_basis* b, const void* table, const void* image, const float* pmap, void* out,
+                          int32_t C, int32_t H, int32_t W, disk_dtype io, void* ws, size_t ws_bytes,
+                          hipStream_t stream) {
+    DISK_TRY(check_basis(b));
+    DISK_TRY(check_image(C, H, W));
+    DISK_TRY(check_ptr(table, "table"));
+    DISK_TRY(check_ptr(image, "image"));
+    DISK_TRY(check_ptr(pmap, "pmap"));
+    DISK_TRY(check_ptr(out, "out"));
+    DISK_TRY(check_ptr(ws, "ws", true));
+    if (io != DISK_F32 && io != DISK_BF16) return fail(DISK_INVALID_ARG, "bad dtype %d", int(io));
+    if (image == out) return fail(DISK_INVALID_ARG, "image and out must not alias");
+    for (int l = 0; l < b->cx.L; ++l)
+        if (sv_lds_bytes(b->halo[l], C, 2) > 160 * 1024)
+            return fail(DISK_UNSUPPORTED, "halo[%d]=%d too large for C=%d", l, b->halo[l], C);
+    Carve cv(ws, ws_bytes);
+    float *b0, *b1;
+    sv_apply_ws(b, C, H, W, cv, &b0, &b1);
+    if (cv.used > 0 && (!ws || cv.used > ws_bytes))
+        return fail(DISK_WORKSPACE_TOO_SMALL, "workspace %zu < %zu bytes", ws_bytes, cv.used);
+    const LayerSpec sp = make_spec(b->cx);
+    const int G0 = b->grid[0], G1 = b->dims == 2 ? b->grid[1] : 1;
+    const float* tab = static_cast<const float*>(table);
+    const int* flag = reinterpret_cast<const int*>(static_cast<const char*>(table) + sv_table_bytes_of(b) - 256);
+    for (int l = 0; l < sp.L; ++l) {
+        const void* src = l == 0 ? image : ((l - 1) % 2 ? b1 : b0);
+        void* dst = l == sp.L - 1 ? out : (l % 2 ? b1 : b0);
+        const int sb = (l == 0 && io == DISK_BF16) ? 1 : 0;
+        const int db = (l == sp.L - 1 && io == DISK_BF16) ? 1 : 0;
+        DISK_HIP(launch_sv_pass(C, b->dims, sb, src, db, dst, pmap, tab, sp.tap0[l], sp.taps[l], sp.T, G0, G1, H, W,
+                                b->halo[l], flag, stream),
+                 "sv pass");
+    }
+    return ok();
+}
+
+disk_status disk_sv_filter(const disk_basis* b, const float* basis_theta, const void* image, const float* pmap,
+                           void* out, int32_t C, int32_t H, int32_t W, disk_dtype io, void* ws, size_t ws_bytes,
+                           hipStream_t stream) {
+    DISK_TRY(check_basis(b));
+    DISK_TRY(check_image(C, H, W));
+    DISK_TRY(check_ptr(ws, "ws", true));
+    const size_t tb = sv_table_bytes_of(b);
+    const size_t need = disk_sv_filter_workspace_size(b, C, H, W, io);
+    if (!ws || ws_bytes < need) return fail(DISK_WORKSPACE_TOO_SMALL, "workspace %zu < %zu bytes", ws_bytes, need);
+    if (image == out) return fail(DISK_INVALID_ARG, "image and out must not alias");
+    DISK_TRY(disk_sv_prepare(b, basis_theta, ws, tb, stream));
+    return disk_sv_apply(b, ws, image, pmap, out, C, H, W, io, static_cast<char*>(ws) + tb, ws_bytes - tb, stream);
+}
+
+}  // extern "C"

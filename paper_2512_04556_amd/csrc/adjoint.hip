@@ -1,0 +1,276 @@
+// Adjoint of a uniform-Theta sparse layer (the end-to-end differentiation of
+// Sec. 4.1): gradients w.r.t. every tap's offset and weight, and w.r.t. the
+// layer input.
+//
+// For a tap with corner offset (ix, iy) = floor(-o), fractions (fx, fy) and
+// weight w, let S_ab = sum_p G[p] X[map(p + (ix + a, iy + b))] (channels summed,
+// map = the boundary rule).  Then
+//   dL/dw   = sum_ab c_ab S_ab / w          (c_ab = w * bilinear corner weight)
+//   dL/dox  = -w [(1-fy)(S01 - S00) + fy (S11 - S10)]
+//   dL/doy  = -w [(1-fx)(S10 - S00) + fx (S11 - S01)]
+// so a tap costs four correlation sums per pixel.  Sums are reduced per block
+// (wave butterflies then a fixed LDS order) into partials, then across blocks
+// in a fixed order: results are bitwise reproducible.
+//
+// The input adjoint is the exact transpose of the gather:
+//   Gprev[q] = sum_i sum_ab c_ab sum_{p : map(p + d_ab) = q} G[p].
+// For ZERO the preimage is the single pixel q - d (if inside); for CLAMP a
+// border pixel's preimage is a run (edge) or block (corner) of pixels, which
+// the kernel sums directly.
+#include "common.hpp"
+#include "internal.hpp"
+
+namespace disk {
+
+constexpr int kTW = 64;
+constexpr int kRows = 8;
+constexpr int kTH = 4 * kRows;
+
+int adjoint_tap_blocks(int H, int W) {
+    const int ntiles = ((W + kTW - 1) / kTW) * ((H + kTH - 1) / kTH);
+    return 8 * ((ntiles + 7) / 8);
+}
+
+struct SrcF32 {
+    const float* p;
+    __device__ __forceinline__ float load(size_t i) const { return p[i]; }
+};
+struct SrcBF16 {
+    const uint16_t* p;
+    __device__ __forceinline__ float load(size_t i) const { return bf16_to_f32(p[i]); }
+};
+struct SrcImpulse {
+    size_t centre;
+    __device__ __forceinline__ float load(size_t i) const { return i == centre ? 1.0f : 0.0f; }
+};
+
+template <int C, int BOUND, class Src>
+__global__ __launch_bounds__(256) void adjoint_taps_kernel(Src src, const float* __restrict__ G,
+                                                           const TapU* __restrict__ taps, int N, int H,
+                                                           int W, int tiles_x, int per, int ntiles,
+                                                           float* __restrict__ partial) {
+    __shared__ float red[4][4];
+    const int tile = xcd_tile(blockIdx.x, per);
+    const bool active = tile < ntiles;
+    const int x = active ? (tile % tiles_x) * kTW + (threadIdx.x & 63) : W;
+    const int yb = active ? (tile / tiles_x) * kTH + (threadIdx.x >> 6) * kRows : H;
+    const size_t plane = static_cast<size_t>(H) * W;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+
+    for (int i = 0; i < N; ++i) {
+        const TapU t = taps[i];
+        float s[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+        if (x < W) {
+            int x0 = x + t.ix, x1 = x0 + 1;
+            const bool vx0 = x0 >= 0 && x0 < W, vx1 = x1 >= 0 && x1 < W;
+            x0 = min(max(x0, 0), W - 1);
+            x1 = min(max(x1, 0), W - 1);
+            for (int r = 0; r < kRows; ++r) {
+                const int y = yb + r;
+                if (y >= H) break;
+                int y0 = y + t.iy, y1 = y0 + 1;
+                const bool vy0 = y0 >= 0 && y0 < H, vy1 = y1 >= 0 && y1 < H;
+                y0 = min(max(y0, 0), H - 1);
+                y1 = min(max(y1, 0), H - 1);
+                const size_t r0 = static_cast<size_t>(y0) * W, r1 = static_cast<size_t>(y1) * W;
+                const size_t pix = static_cast<size_t>(y) * W + x;
+#pragma unroll
+                for (int c = 0; c < C; ++c) {
+                    const float g = G[c * plane + pix];
+                    float v00 = src.load(c * plane + r0 + x0), v01 = src.load(c * plane + r0 + x1);
+                    float v10 = src.load(c * plane + r1 + x0), v11 = src.load(c * plane + r1 + x1);
+                    if (BOUND == DISK_ZERO) {
+                        v00 = (vx0 && vy0) ? v00 : 0.0f;
+                        v01 = (vx1 && vy0) ? v01 : 0.0f;
+                        v10 = (vx0 && vy1) ? v10 : 0.0f;
+                        v11 = (vx1 && vy1) ? v11 : 0.0f;
+                    }
+                    s[0] = fmaf(g, v00, s[0]);
+                    s[1] = fmaf(g, v01, s[1]);
+                    s[2] = fmaf(g, v10, s[2]);
+                    s[3] = fmaf(g, v11, s[3]);
+                }
+            }
+        }
+#pragma unroll
+        for (int a = 0; a < 4; ++a) s[a] = wave_sum(s[a]);
+        if (lane == 0)
+#pragma unroll
+            for (int a = 0; a < 4; ++a) red[wave][a] = s[a];
+        __syncthreads();
+        if (threadIdx.x < 4) {
+            const int a = threadIdx.x;
+            const float v = (red[0][a] + red[1][a]) + (red[2][a] + red[3][a]);
+            partial[(static_cast<size_t>(blockIdx.x) * N + i) * 4 + a] = v;
+        }
+        __syncthreads();
+    }
+}
+
+// One block per (tap, corner): fixed-order strided sums then a fixed tree.
+__global__ __launch_bounds__(256) void adjoint_reduce_kernel(const float* __restrict__ partial, int nblk, int N,
+                                                             float* __restrict__ sums) {
+    __shared__ float buf[256];
+    const int i = blockIdx.x >> 2, a = blockIdx.x & 3;
+    float v = 0.0f;
+    for (int b = threadIdx.x; b < nblk; b += 256) v += partial[(static_cast<size_t>(b) * N + i) * 4 + a];
+    buf[threadIdx.x] = v;
+    __syncthreads();
+    for (int m = 128; m >= 1; m >>= 1) {
+        if (threadIdx.x < m) buf[threadIdx.x] += buf[threadIdx.x + m];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) sums[i * 4 + a] = buf[0];
+}
+
+__global__ void adjoint_finish_kernel(const float* __restrict__ sums, const float* __restrict__ theta, int N,
+                                      float* __restrict__ dtheta) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const float ox = theta[3 * i + 0], oy = theta[3 * i + 1], w = theta[3 * i + 2];
+    int ix, iy;
+    float fx, fy;
+    floor_frac(-ox, ix, fx);
+    floor_frac(-oy, iy, fy);
+    const float S00 = sums[4 * i + 0], S01 = sums[4 * i + 1], S10 = sums[4 * i + 2], S11 = sums[4 * i + 3];
+    const float gw = (1.0f - fy) * ((1.0f - fx) * S00 + fx * S01) + fy * ((1.0f - fx) * S10 + fx * S11);
+    const float gx = -w * ((1.0f - fy) * (S01 - S00) + fy * (S11 - S10));
+    const float gy = -w * ((1.0f - fx) * (S10 - S00) + fx * (S11 - S01));
+    dtheta[3 * i + 0] = gx;
+    dtheta[3 * i + 1] = gy;
+    dtheta[3 * i + 2] = gw;
+}
+
+template <int C, int BOUND, class Src>
+static hipError_t taps_launch(Src src, const float* G, const TapU* taps, int N, int H, int W, float* partial,
+                              hipStream_t s) {
+    const int tiles_x = (W + kTW - 1) / kTW, tiles_y = (H + kTH - 1) / kTH;
+    const int ntiles = tiles_x * tiles_y;
+    const int per = (ntiles + 7) / 8;
+    hipLaunchKernelGGL((adjoint_taps_kernel<C, BOUND, Src>), dim3(8 * per), dim3(256), 0, s, src, G, taps, N, H,
+                       W, tiles_x, per, ntiles, partial);
+    return hipGetLastError();
+}
+
+template <int C, int BOUND>
+static hipError_t taps_src(int src_kind, const void* X, const float* G, const TapU* taps, int N, int H, int W,
+                           float* partial, hipStream_t s) {
+    if (src_kind == 0) return taps_launch<C, BOUND>(SrcF32{static_cast<const float*>(X)}, G, taps, N, H, W, partial, s);
+    if (src_kind == 1) return taps_launch<C, BOUND>(SrcBF16{static_cast<const uint16_t*>(X)}, G, taps, N, H, W, partial, s);
+    const size_t centre = static_cast<size_t>((H - 1) / 2) * W + (W - 1) / 2;
+    return taps_launch<C, BOUND>(SrcImpulse{centre}, G, taps, N, H, W, partial, s);
+}
+
+template <int C>
+static hipError_t taps_bound(int boundary, int src_kind, const void* X, const float* G, const TapU* taps, int N,
+                             int H, int W, float* partial, hipStream_t s) {
+    if (boundary == DISK_ZERO) return taps_src<C, DISK_ZERO>(src_kind, X, G, taps, N, H, W, partial, s);
+    return taps_src<C, DISK_CLAMP>(src_kind, X, G, taps, N, H, W, partial, s);
+}
+
+hipError_t launch_adjoint_taps(int C, int boundary, int src_kind, const void* X, const float* G,
+                               const TapU* taps, int N, int H, int W, float* partial, hipStream_t s) {
+    switch (C) {
+        case 1: return taps_bound<1>(boundary, src_kind, X, G, taps, N, H, W, partial, s);
+        case 2: return taps_bound<2>(boundary, src_kind, X, G, taps, N, H, W, partial, s);
+        case 3: return taps_bound<3>(boundary, src_kind, X, G, taps, N, H, W, partial, s);
+        default: return taps_bound<4>(boundary, src_kind, X, G, taps, N, H, W, partial, s);
+    }
+}
+
+hipError_t launch_adjoint_finish(const float* partial, int nblk, const float* theta_layer, const TapU* taps,
+                                 int N, float* dtheta_layer, hipStream_t s) {
+    (void)taps;
+    // sums live right after the partials
+    float* sums = const_cast<float*>(partial) + static_cast<size_t>(nblk) * N * 4;
+    hipLaunchKernelGGL(adjoint_reduce_kernel, dim3(4 * N), dim3(256), 0, s, partial, nblk, N, sums);
+    hipLaunchKernelGGL(adjoint_finish_kernel, dim3((N + 63) / 64), dim3(64), 0, s, sums, theta_layer, N,
+                       dtheta_layer);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// input adjoint
+// ---------------------------------------------------------------------------
+// Preimage range along one axis of corner shift d: all p in [0, n) with
+// map(p + d) == q.
+template <int BOUND>
+__device__ __forceinline__ void preimage(int q, int d, int n, int& lo, int& hi) {
+    if (BOUND == DISK_ZERO) {
+        lo = hi = q - d;
+    } else {
+        lo = (q == 0) ? -0x3fffffff : q - d;
+        hi = (q == n - 1) ? 0x3fffffff : q - d;
+    }
+    lo = max(lo, 0);
+    hi = min(hi, n - 1);
+}
+
+template <int C, int BOUND>
+__global__ __launch_bounds__(256) void adjoint_input_kernel(const float* __restrict__ G,
+                                                            const TapU* __restrict__ taps, int N, int H,
+                                                            int W, float* __restrict__ Gprev) {
+    const int x = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
+    if (x >= W || y >= H) return;
+    const size_t plane = static_cast<size_t>(H) * W;
+    float acc[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) acc[c] = 0.0f;
+    const bool border = (BOUND == DISK_CLAMP) && (x == 0 || y == 0 || x == W - 1 || y == H - 1);
+    for (int i = 0; i < N; ++i) {
+        const TapU t = taps[i];
+        const float cw[4] = {t.c00, t.c01, t.c10, t.c11};
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+            const int dx = t.ix + (a & 1), dy = t.iy + (a >> 1);
+            if (!border) {
+                const int px = x - dx, py = y - dy;
+                if (px >= 0 && px < W && py >= 0 && py < H) {
+                    const size_t pi = static_cast<size_t>(py) * W + px;
+#pragma unroll
+                    for (int c = 0; c < C; ++c) acc[c] = fmaf(cw[a], G[c * plane + pi], acc[c]);
+                }
+            } else {
+                int xl, xh, yl, yh;
+                preimage<BOUND>(x, dx, W, xl, xh);
+                preimage<BOUND>(y, dy, H, yl, yh);
+                for (int py = yl; py <= yh; ++py)
+                    for (int px = xl; px <= xh; ++px) {
+                        const size_t pi = static_cast<size_t>(py) * W + px;
+#pragma unroll
+                        for (int c = 0; c < C; ++c) acc[c] = fmaf(cw[a], G[c * plane + pi], acc[c]);
+                    }
+            }
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < C; ++c) Gprev[c * plane + static_cast<size_t>(y) * W + x] = acc[c];
+}
+
+template <int C>
+static hipError_t input_bound(int boundary, const float* G, const TapU* taps, int N, int H, int W, float* Gprev,
+                              hipStream_t s) {
+    dim3 grid((W + 63) / 64, (H + 3) / 4), block(256);
+    if (boundary == DISK_ZERO)
+        hipLaunchKernelGGL((adjoint_input_kernel<C, DISK_ZERO>), grid, block, 0, s, G, taps, N, H, W, Gprev);
+    else
+        hipLaunchKernelGGL((adjoint_input_kernel<C, DISK_CLAMP>), grid, block, 0, s, G, taps, N, H, W, Gprev);
+    return hipGetLastError();
+}
+
+hipError_t launch_adjoint_input(int C, int boundary, const float* G, const TapU* taps, int N, int H, int W,
+                                int R, float* pad, float* Gprev, hipStream_t s) {
+    (void)R;
+    (void)pad;
+    switch (C) {
+        case 1: return input_bound<1>(boundary, G, taps, N, H, W, Gprev, s);
+        case 2: return input_bound<2>(boundary, G, taps, N, H, W, Gprev, s);
+        case 3: return input_bound<3>(boundary, G, taps, N, H, W, Gprev, s);
+        default: return input_bound<4>(boundary, G, taps, N, H, W, Gprev, s);
+    }
+}
+
+hipError_t launch_halo_of_taps(const TapU*, int, int*, hipStream_t) { return hipSuccess; }
+
+}  // namespace disk

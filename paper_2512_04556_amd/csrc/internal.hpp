@@ -1,0 +1,76 @@
+// Internal launch interface between the C ABI (abi.cpp) and the HIP sources.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/disk.h"
+
+namespace disk {
+
+// One uniform tap, prepared once per call: integer corner offset of the
+// gather at p - o and the four bilinear corner weights premultiplied by w.
+struct TapU {
+    int ix, iy;          // floor(-ox), floor(-oy)
+    float c00, c01, c10, c11;
+    int pad0, pad1;
+};
+static_assert(sizeof(TapU) == 32, "TapU layout");
+
+struct LayerSpec {
+    int L;
+    int taps[DISK_MAX_LAYERS];
+    int tap0[DISK_MAX_LAYERS];
+    int T;
+};
+
+inline LayerSpec make_spec(const disk_complex& cx) {
+    LayerSpec s{};
+    s.L = cx.L;
+    int o = 0;
+    for (int l = 0; l < cx.L; ++l) {
+        s.taps[l] = cx.taps[l];
+        s.tap0[l] = o;
+        o += cx.taps[l];
+    }
+    s.T = o;
+    return s;
+}
+
+// ---- chain.hip: uniform-Theta chain on images / impulse canvases ----------
+// Prepares TapU[T] from theta[T][3].
+hipError_t launch_prep_uniform(const float* theta, int T, TapU* out, hipStream_t s);
+// One layer.  src_kind: 0 = f32 image, 1 = bf16 image, 2 = impulse (centre).
+// dst_kind: 0 = f32, 1 = bf16.
+hipError_t launch_layer_uniform(int C, int boundary, int src_kind, const void* src, int dst_kind,
+                                void* dst, const TapU* taps, int N, int H, int W, hipStream_t s);
+
+// ---- adjoint.hip -------------------------------------------------------------
+// Per-tap correlation sums S_ab = sum_p G[p] X[p + (ix+a, iy+b)] (boundary
+// mapped) into partial[nblk][N][4]; returns nblk through *nblk_out.
+int adjoint_tap_blocks(int H, int W);
+hipError_t launch_adjoint_taps(int C, int boundary, int src_kind, const void* X, const float* G,
+                               const TapU* taps, int N, int H, int W, float* partial,
+                               hipStream_t s);
+// Reduces partials (fixed order) and writes dtheta rows [N][3] of this layer.
+hipError_t launch_adjoint_finish(const float* partial, int nblk, const float* theta_layer,
+                                 const TapU* taps, int N, float* dtheta_layer, hipStream_t s);
+// Input adjoint: Gprev = A^T G (exact transpose incl. CLAMP border folding).
+// pad: scratch of (H+2R)*(W+2R)*C floats for CLAMP (R = halo); may be null for ZERO.
+hipError_t launch_adjoint_input(int C, int boundary, const float* G, const TapU* taps, int N,
+                                int H, int W, int R, float* pad, float* Gprev, hipStream_t s);
+hipError_t launch_halo_of_taps(const TapU* taps, int T, int* out_halo, hipStream_t s);
+
+// ---- filter.hip: spatially varying filter ------------------------------------
+// Table row widths: 1-D 9 floats, 2-D 12 floats per (entry, tap).
+size_t sv_table_floats(int dims, int G, int T);
+hipError_t launch_sv_prep(int dims, int G0, int G1, const LayerSpec& spec, const int* halo,
+                          const float* basis, float* table, int* flag, hipStream_t s);
+int sv_rows_per_wave(int halo, int C);
+size_t sv_lds_bytes(int halo, int C, int py);
+hipError_t launch_sv_pass(int C, int dims, int src_bf16, const void* src, int dst_bf16, void* dst,
+                          const float* pmap, const float* table, int tap0, int N, int T, int G0,
+                          int G1, int H, int W, int halo, const int* flag, hipStream_t s);
+
+}  // namespace disk

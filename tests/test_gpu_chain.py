@@ -1,0 +1,117 @@
+"""GPU parity of the uniform chain forward (Eq. 3, impulse response Eq. 10)
+and its adjoint against the FP64 oracle, through the C ABI."""
+import numpy as np
+import pytest
+import torch
+
+import paper_2512_04556_amd as disk
+from oracle import sparse as S
+from oracle import adjoint as A
+from synth import random_theta, uniform_image, noise_image
+from tests.gpu_util import say, to_dev, to_np, bf16_round, rel_err, TOL_F32, TOL_BF16
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("M,taps,radius,seed", [
+    (31, [8, 8, 8], 7.0, 1),          # the tiny Gaussian configuration's shape
+    (63, [12, 12, 12, 12], 9.0, 2),
+    (127, [16, 10, 6, 14, 8, 12], 12.0, 3),
+    (15, [6, 6], 3.0, 4),
+    (5, [3], 4.0, 5),                 # offsets beyond the canvas: mass leaves
+])
+def test_impulse_response_parity(dev, M, taps, radius, seed):
+    th = random_theta(taps, radius, seed=seed)
+    say("impulse", M, taps, seed)
+    out, _ = disk.disk_forward(to_dev(th), taps, None, H=M, W=M)
+    want = S.impulse_response(M, th.astype(np.float64), taps)
+    e = rel_err(to_np(out), want)
+    print(f"impulse M={M} taps={taps}: max-abs/peak = {e:.2e}")
+    assert e <= TOL_F32
+
+
+def test_integer_taps_scatter_bitwise(dev):
+    g = np.random.default_rng(7)
+    N, M = 11, 21
+    th = np.zeros((N, 3), np.float32)
+    th[:, 0] = g.integers(-9, 10, N)
+    th[:, 1] = g.integers(-9, 10, N)
+    th[:, 2] = g.uniform(-1, 1, N)
+    say("integer scatter", M)
+    out, _ = disk.disk_forward(to_dev(th), [N], None, H=M, W=M)
+    want = np.zeros((M, M), np.float32)
+    c = (M - 1) // 2
+    for ox, oy, w in th:
+        want[c + int(oy), c + int(ox)] += w      # float32 sum in tap order
+    assert np.array_equal(to_np(out)[0].astype(np.float32), want)
+
+
+@pytest.mark.parametrize("C,H,W,boundary", [
+    (1, 256, 256, S.CLAMP), (3, 67, 133, S.CLAMP), (2, 45, 70, S.ZERO), (4, 17, 9, S.CLAMP), (1, 1, 1, S.CLAMP),
+])
+def test_image_forward_parity(dev, C, H, W, boundary):
+    taps = [8, 5, 7]
+    th = random_theta(taps, 6.0, seed=C * 100 + H)
+    img = uniform_image(H, W, C, seed=H + W)
+    say("image forward", C, H, W, boundary)
+    out, saved = disk.disk_forward(to_dev(th), taps, to_dev(img), boundary=boundary, save=True)
+    Xs = S.chain(img.astype(np.float64), th.astype(np.float64), taps, boundary, keep=True)
+    e = rel_err(to_np(out), Xs[-1])
+    print(f"image C={C} {H}x{W} b={boundary}: {e:.2e}")
+    assert e <= TOL_F32
+    for l in range(len(taps) - 1):
+        assert rel_err(to_np(saved[l]), Xs[l + 1]) <= TOL_F32
+
+
+def test_image_forward_bf16_io(dev):
+    taps = [8, 8, 8, 8]
+    th = random_theta(taps, 5.0, seed=9)
+    img = noise_image(120, 200, 3, seed=2, n_rects=20)
+    x = to_dev(img).bfloat16()
+    say("image forward bf16", img.shape)
+    out, _ = disk.disk_forward(to_dev(th), taps, x, boundary=S.CLAMP)
+    assert out.dtype == torch.bfloat16
+    want = S.chain(bf16_round(img), th.astype(np.float64), taps, S.CLAMP)
+    e = rel_err(to_np(out), want)
+    print(f"bf16 io: {e:.2e}")
+    assert e <= TOL_BF16
+
+
+@pytest.mark.parametrize("boundary,C,H,W", [(S.CLAMP, 2, 23, 37), (S.ZERO, 1, 30, 19), (S.CLAMP, 3, 70, 96)])
+def test_image_backward_parity(dev, boundary, C, H, W):
+    taps = [6, 4, 5]
+    th = random_theta(taps, 4.0, seed=H)
+    img = uniform_image(H, W, C, seed=W)
+    G = np.random.default_rng(H * W).standard_normal((C, H, W)).astype(np.float32)
+    say("image backward", boundary, C, H, W)
+    out, saved = disk.disk_forward(to_dev(th), taps, to_dev(img), boundary=boundary, save=True)
+    gt, gi = disk.disk_backward(to_dev(th), taps, to_dev(img), saved, to_dev(G), boundary=boundary)
+    wt, wi = A.chain_vjp(img.astype(np.float64), th.astype(np.float64), taps, boundary, G.astype(np.float64))
+    et, ei = rel_err(to_np(gt), wt), rel_err(to_np(gi), wi)
+    print(f"backward b={boundary}: dtheta {et:.2e} dinput {ei:.2e}")
+    assert et <= 1e-4 and ei <= TOL_F32
+
+
+@pytest.mark.parametrize("M,taps", [(31, [8, 8, 8]), (63, [12, 12, 12, 12]), (101, [7, 9, 5, 11, 6])])
+def test_impulse_backward_parity(dev, M, taps):
+    th = random_theta(taps, M / 6.0, seed=M)
+    G = np.random.default_rng(M).standard_normal((1, M, M)).astype(np.float32)
+    say("impulse backward", M, taps)
+    out, saved = disk.disk_forward(to_dev(th), taps, None, H=M, W=M, save=True)
+    gt, _ = disk.disk_backward(to_dev(th), taps, None, saved, to_dev(G), need_input=False)
+    wt, _ = A.chain_vjp(S.impulse(M)[None], th.astype(np.float64), taps, S.ZERO, G.astype(np.float64))
+    e = rel_err(to_np(gt), wt)
+    print(f"impulse backward M={M}: {e:.2e}")
+    assert e <= 1e-4
+
+
+def test_backward_deterministic(dev):
+    taps = [8, 8]
+    th = to_dev(random_theta(taps, 5.0, seed=3))
+    img = to_dev(uniform_image(200, 300, 3, seed=4))
+    G = to_dev(np.random.default_rng(5).standard_normal((3, 200, 300)))
+    say("backward determinism")
+    _, saved = disk.disk_forward(th, taps, img, save=True)
+    a = disk.disk_backward(th, taps, img, saved, G)
+    b = disk.disk_backward(th, taps, img, saved, G)
+    assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
