@@ -388,4 +388,79 @@ disk_status disk_sv_filter(const disk_basis* b, const float* basis_theta, const 
     return disk_sv_apply(b, ws, image, pmap, out, C, H, W, io, static_cast<char*>(ws) + tb, ws_bytes - tb, stream);
 }
 
+// ---------------------------------------------------------------------------
+// batched optimisation, initialisers
+// ---------------------------------------------------------------------------
+static disk_status check_meta(const disk_batch_meta* m) {
+    if (!m) return fail(DISK_INVALID_ARG, "meta is NULL");
+    if (m->B < 1) return fail(DISK_BAD_SHAPE, "B=%d must be >= 1", m->B);
+    if (m->max_side < 1 || m->max_side > DISK_MAX_SIDE || (m->max_side & 1) == 0)
+        return fail(DISK_BAD_SHAPE, "max_side=%d must be odd in [1,%d]", m->max_side, DISK_MAX_SIDE);
+    if (m->max_T < 1 || m->max_T > DISK_MAX_LAYERS * DISK_MAX_TAPS)
+        return fail(DISK_BAD_SHAPE, "max_T=%d out of range", m->max_T);
+    return DISK_OK;
+}
+
+static size_t optimize_ws(const disk_batch_meta* m, Carve& cv, int** order, int** queue, float** scratch,
+                          size_t* slot, int* nwg) {
+    *nwg = opt_workgroups(m->B);
+    *slot = opt_slot_floats(m->max_side, std::min(m->max_T, DISK_MAX_LAYERS));
+    *order = cv.take<int>(m->B);
+    *queue = cv.take<int>(64);
+    *scratch = cv.take<float>(*slot * *nwg);
+    return cv.used;
+}
+
+size_t disk_optimize_workspace_size(const disk_batch_meta* meta) {
+    if (!meta || meta->B < 1 || meta->max_side < 1 || meta->max_T < 1) return 0;
+    Carve cv(nullptr, 0);
+    int *o, *q, nwg;
+    float* sc;
+    size_t slot;
+    return optimize_ws(meta, cv, &o, &q, &sc, &slot, &nwg) + 256;
+}
+
+disk_status disk_optimize_batch(const disk_batch_meta* meta, const disk_target* desc, const int32_t* taps,
+                                const float* targets, float* theta, float* psnr_db, int32_t* steps, int32_t* status,
+                                const disk_opt_params* params, void* ws, size_t ws_bytes, hipStream_t stream) {
+    DISK_TRY(check_meta(meta));
+    DISK_TRY(check_ptr(desc, "desc"));
+    DISK_TRY(check_ptr(taps, "taps"));
+    DISK_TRY(check_ptr(targets, "targets"));
+    DISK_TRY(check_ptr(theta, "theta"));
+    DISK_TRY(check_ptr(psnr_db, "psnr_db"));
+    DISK_TRY(check_ptr(steps, "steps"));
+    DISK_TRY(check_ptr(status, "status"));
+    if (!params) return fail(DISK_INVALID_ARG, "params is NULL");
+    const disk_opt_params& p = *params;
+    if (p.max_steps < 0) return fail(DISK_INVALID_ARG, "max_steps=%d < 0", p.max_steps);
+    if (!(p.beta1 >= 0.0f && p.beta1 < 1.0f) || !(p.beta2 >= 0.0f && p.beta2 < 1.0f) || !(p.eps > 0.0f))
+        return fail(DISK_INVALID_ARG, "bad Adam hyper-parameters");
+    if (!std::isfinite(p.lr0) || !std::isfinite(p.lr1)) return fail(DISK_INVALID_ARG, "non-finite learning rate");
+    if (p.loss != DISK_LOSS_NMSE && p.loss != DISK_LOSS_CHARBONNIER) return fail(DISK_INVALID_ARG, "bad loss %d", p.loss);
+    if (p.loss == DISK_LOSS_CHARBONNIER && !(p.charb_eps > 0.0f)) return fail(DISK_INVALID_ARG, "charb_eps must be > 0");
+    Carve cv(ws, ws_bytes);
+    int *order, *queue, nwg;
+    float* scratch;
+    size_t slot;
+    optimize_ws(meta, cv, &order, &queue, &scratch, &slot, &nwg);
+    if (!ws || cv.used > ws_bytes)
+        return fail(DISK_WORKSPACE_TOO_SMALL, "workspace %zu < %zu bytes", ws_bytes, cv.used);
+    DISK_HIP(launch_optimize(meta->B, desc, taps, targets, theta, psnr_db, steps, status, p, order, queue, scratch,
+                             slot, nwg, meta->max_side, meta->max_T, stream),
+             "optimize");
+    return ok();
+}
+
+disk_status disk_init_radial(const disk_batch_meta* meta, const disk_target* desc, const int32_t* taps,
+                             const float* targets, float* theta, hipStream_t stream) {
+    DISK_TRY(check_meta(meta));
+    DISK_TRY(check_ptr(desc, "desc"));
+    DISK_TRY(check_ptr(taps, "taps"));
+    DISK_TRY(check_ptr(targets, "targets"));
+    DISK_TRY(check_ptr(theta, "theta"));
+    DISK_HIP(launch_init_radial(meta->B, desc, taps, targets, theta, stream), "init radial");
+    return ok();
+}
+
 }  // extern "C"

@@ -26,7 +26,9 @@
 #include "common.hpp"
 #include "internal.hpp"
 
+#include <algorithm>
 #include <cstdlib>
+#include <type_traits>
 
 namespace disk {
 
@@ -34,8 +36,8 @@ constexpr int kRow1D = 9;   // nAx nDx nAy nDy Aw Dw nDDx nDDy DDw
 constexpr int kRow2D = 12;  // (nA nD0 nD1 nD01) for x, y; (A D0 D1 D01) for w
 
 size_t sv_table_floats(int dims, int G, int T) {
-    // one spare row: the pipelined loop reads (but never uses) the row after the last tap
-    return (static_cast<size_t>(G) * T + 1) * (dims == 1 ? kRow1D : kRow2D);
+    // spare rows: the chunked loops read (but never use) up to 8 rows past the last tap
+    return (static_cast<size_t>(G) * T + 8) * (dims == 1 ? kRow1D : kRow2D);
 }
 
 struct PrepArgs {
@@ -149,8 +151,8 @@ __device__ __forceinline__ int mad24(int a, int b, int c) {
 }
 
 // Accumulate one tap with per-lane (nx, ny) = -offset and weight w.  `base` is
-// the byte address of the pixel's own position in the staged [row][col][C]
-// tile; rowB / colB are the byte strides of a row and a column.
+// the byte address of the pixel's own position in the staged tile, laid out
+// [row][col][C] with a row stride of rowB bytes.
 template <int C>
 __device__ __forceinline__ void gather_tap(float* acc, int base, int rowB, float nx, float ny, float w) {
     const int ix = cvt_flr(nx), iy = cvt_flr(ny);
@@ -172,101 +174,97 @@ __device__ __forceinline__ void gather_tap(float* acc, int base, int rowB, float
     }
 }
 
-template <int C, int DIMS, typename TIn, typename TOut, int PY>
-__global__ __launch_bounds__(256, 2) void sv_pass_kernel(
-    const TIn* __restrict__ X, TOut* __restrict__ Y, const float* __restrict__ P,
-    const float* __restrict__ table, int tap0, int N, int T, int G0, int G1, int H, int W, int halo,
-    int tiles_x, int per, int ntiles, const int* __restrict__ flag) {
-    extern __shared__ float lds[];
-    constexpr int TH = 4 * PY;
-    constexpr int RW = DIMS == 1 ? kRow1D : kRow2D;
-    const int tile = xcd_tile(blockIdx.x, per);
-    if (tile >= ntiles) return;
-    const size_t plane = static_cast<size_t>(H) * W;
-    const int tx0 = (tile % tiles_x) * kTW, ty0 = (tile / tiles_x) * TH;
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int x = tx0 + lane;
-
-    if (*flag) {  // an offset exceeds its declared halo: refuse to gather
-        if (x < W)
-            for (int j = 0; j < PY; ++j) {
-                const int y = ty0 + wave * PY + j;
-                if (y < H)
-                    for (int c = 0; c < C; ++c)
-                        IO<TOut>::store(Y, c * plane + static_cast<size_t>(y) * W + x, __builtin_nanf(""));
-            }
-        return;
+// The same tap for C = 3 or 4 with the tile stored as one float4 per pixel
+// (RGB padded, or RGBA): the four corners are four 128-bit LDS reads, the
+// widest and fastest LDS access on gfx950.  Floors are taken in FP32 and the
+// LDS byte address is formed with two exact FP32 FMAs (integers < 2^24) and one
+// conversion, cheaper than integer conversion plus 24-bit multiplies.
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) v4f lds_v4f;
+template <int C>
+__device__ __forceinline__ void gather_tap4(float* acc, float basef, float rowBf, int rowB, float nx, float ny,
+                                            float w) {
+    const float flx = floorf(nx), fly = floorf(ny);
+    const float fx = nx - flx, fy = ny - fly;
+    const float wy1 = w * fy, wy0 = w - wy1;
+    const float c01 = wy0 * fx, c00 = wy0 - c01;
+    const float c11 = wy1 * fx, c10 = wy1 - c11;
+    const int a0 = static_cast<int>(fmaf(flx, 16.0f, fmaf(fly, rowBf, basef)));
+    const lds_v4f* r0 = reinterpret_cast<const lds_v4f*>(static_cast<uintptr_t>(static_cast<uint32_t>(a0)));
+    const lds_v4f* r1 = reinterpret_cast<const lds_v4f*>(static_cast<uintptr_t>(static_cast<uint32_t>(a0 + rowB)));
+    const v4f v00 = r0[0], v01 = r0[1], v10 = r1[0], v11 = r1[1];
+    const float q00[4] = {v00.x, v00.y, v00.z, v00.w}, q01[4] = {v01.x, v01.y, v01.z, v01.w};
+    const float q10[4] = {v10.x, v10.y, v10.z, v10.w}, q11[4] = {v11.x, v11.y, v11.z, v11.w};
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        float a = acc[c];
+        a = fmaf(c00, q00[c], a);
+        a = fmaf(c01, q01[c], a);
+        a = fmaf(c10, q10[c], a);
+        a = fmaf(c11, q11[c], a);
+        acc[c] = a;
     }
+}
 
-    const int SX = kTW + 2 * halo, SY = TH + 2 * halo;
-    const int rowC = SX * C;
-    // Stage the tile + clamped halo.  Loads are batched (4 rows x up to 3
-    // column chunks x C per lane in flight) before any LDS store, so the
-    // memory latency is paid once per batch rather than once per row.
-    const int nq = (SX + 63) >> 6;
-    for (int r0 = wave; r0 < SY; r0 += 16) {
-        float v[4][3][C];
-#pragma unroll
-        for (int rr = 0; rr < 4; ++rr) {
-            const int gy = min(max(ty0 - halo + r0 + 4 * rr, 0), H - 1);
-            const size_t grow = static_cast<size_t>(gy) * W;
-#pragma unroll
-            for (int q = 0; q < 3; ++q) {
-                if (q < nq) {
-                    const int gx = min(max(tx0 - halo + lane + 64 * q, 0), W - 1);
-#pragma unroll
-                    for (int c = 0; c < C; ++c) v[rr][q][c] = IO<TIn>::load(X, c * plane + grow + gx);
-                }
-            }
-        }
-#pragma unroll
-        for (int rr = 0; rr < 4; ++rr) {
-            const int ly = r0 + 4 * rr;
-#pragma unroll
-            for (int q = 0; q < 3; ++q) {
-                const int lx = lane + 64 * q;
-                if (q < nq && ly < SY && lx < SX) {
-                    float* d = lds + ly * rowC + lx * C;
-#pragma unroll
-                    for (int c = 0; c < C; ++c) d[c] = v[rr][q][c];
-                }
-            }
-        }
-    }
+// Staged-tile row stride in dwords: (64 + 2 halo) pixels of C channels, padded
+// so that the four 16-lane rows of a wave fall in disjoint LDS banks
+// (row stride = 16, 33, 48, 1 mod 64 for C = 1..4).
+__host__ __device__ __forceinline__ int sv_row_dwords(int halo, int C) {
+    if (C >= 3) return (kTW + 2 * halo) * 4;  // float4 per pixel; 16-lane groups never conflict
+    const int raw = (kTW + 2 * halo) * C;
+    const int target = C == 1 ? 16 : C == 2 ? 33 : C == 3 ? 48 : 1;
+    return raw + ((target - raw % 64) + 64) % 64;
+}
 
-    // decode the parameter map for this lane's PY pixels
-    const int xc = min(x, W - 1);
-    float ta[PY], tb[PY];
-    int kk[PY];
+// Lane geometry shared by both pass kernels.  A work-group of NW waves owns a
+// 64 x (NW/4 * 4*PY) output tile.  Wave w owns columns [16 (w%4), 16 (w%4) + 16)
+// of row band w/4; lane (lx, ly) = (lane & 15, lane >> 4) handles rows 4j + ly,
+// j < PY, of its band.  Every per-wave decision (interval span) therefore covers
+// a 16 x 4PY block, small enough that a slowly varying map rarely spans a node.
+
+// Decode P for this lane's PY pixels: interval k and the fractions ta (axis 0)
+// and tb (axis 1 in 2-D, u itself in 1-D for the multi-interval path).
+template <int DIMS, int PY>
+__device__ __forceinline__ void sv_decode(const float (&pv)[PY][DIMS], int G0, int G1, float (&ta)[PY],
+                                          float (&tb)[PY], int (&kk)[PY]) {
 #pragma unroll
     for (int j = 0; j < PY; ++j) {
-        const int yc = min(ty0 + wave * PY + j, H - 1);
-        const size_t pi = static_cast<size_t>(yc) * W + xc;
-        const float u0 = fminf(fmaxf(P[pi], 0.0f), 1.0f) * static_cast<float>(G0 - 1);
+        const float u0 = fminf(fmaxf(pv[j][0], 0.0f), 1.0f) * static_cast<float>(G0 - 1);
         const int k0 = min(static_cast<int>(floorf(u0)), G0 - 1);
         ta[j] = u0 - static_cast<float>(k0);
         if (DIMS == 1) {
             kk[j] = k0;
-            tb[j] = u0;  // kept for the two-interval path
+            tb[j] = u0;
         } else {
-            const float u1 = fminf(fmaxf(P[plane + pi], 0.0f), 1.0f) * static_cast<float>(G1 - 1);
+            const float u1 = fminf(fmaxf(pv[j][DIMS - 1], 0.0f), 1.0f) * static_cast<float>(G1 - 1);
             const int k1 = min(static_cast<int>(floorf(u1)), G1 - 1);
             tb[j] = u1 - static_cast<float>(k1);
             kk[j] = k0 * G1 + k1;
         }
     }
-    __syncthreads();
+}
 
-    const int lds_base = lds_offset(lds);
-    const int rowB = rowC * 4;
-    int base[PY];
+// All N taps of one layer for this lane's PY pixels of a staged tile.
+template <int C, int DIMS, int PY>
+__device__ __forceinline__ void sv_tile_taps(float (&acc)[PY][C], const float (&ta)[PY], const float (&tb)[PY],
+                                             const int (&kk)[PY], int base0, int rowB,
+                                             const float* __restrict__ table, int tap0, int N, int T) {
+    constexpr int RW = DIMS == 1 ? kRow1D : kRow2D;
+    const float rowBf = static_cast<float>(rowB);
+    float basef[PY];
 #pragma unroll
-    for (int j = 0; j < PY; ++j) base[j] = lds_base + ((wave * PY + j + halo) * rowC + (lane + halo) * C) * 4;
-    float acc[PY][C];
+    for (int j = 0; j < PY; ++j) basef[j] = static_cast<float>(base0 + j * 4 * rowB);
 #pragma unroll
     for (int j = 0; j < PY; ++j)
 #pragma unroll
         for (int c = 0; c < C; ++c) acc[j][c] = 0.0f;
+#define SV_TAP(j, nx, ny, w)                                                                       \
+    do {                                                                                           \
+        if (C >= 3)                                                                                \
+            gather_tap4<C>(acc[j], basef[j], rowBf, rowB, (nx), (ny), (w));                        \
+        else                                                                                       \
+            gather_tap<C>(acc[j], base0 + (j) * 4 * rowB, rowB, (nx), (ny), (w));                  \
+    } while (0)
 
     int lo = kk[0], hi = kk[0];
 #pragma unroll
@@ -289,137 +287,392 @@ __global__ __launch_bounds__(256, 2) void sv_pass_kernel(
                 const float nAx = r[0], nDx = r[1], nAy = r[2], nDy = r[3], nAw = r[4], nDw = r[5];
 #pragma unroll
                 for (int j = 0; j < PY; ++j)
-                    gather_tap<C>(acc[j], base[j], rowB, fmaf(ta[j], Dx, Ax), fmaf(ta[j], Dy, Ay), fmaf(ta[j], Dw, Aw));
+                    SV_TAP(j, fmaf(ta[j], Dx, Ax), fmaf(ta[j], Dy, Ay), fmaf(ta[j], Dw, Aw));
                 Ax = nAx; Dx = nDx; Ay = nAy; Dy = nDy; Aw = nAw; Dw = nDw;
             }
         } else {
-        for (int i = 0; i < N; ++i) {
-            const float* r = e + i * RW;
-            {
+            for (int i = 0; i < N; ++i) {
+                const float* r = e + i * RW;
 #pragma unroll
                 for (int j = 0; j < PY; ++j) {
                     const float st = ta[j] * tb[j];
                     const float nx = fmaf(st, r[3], fmaf(tb[j], r[2], fmaf(ta[j], r[1], r[0])));
                     const float ny = fmaf(st, r[7], fmaf(tb[j], r[6], fmaf(ta[j], r[5], r[4])));
                     const float w = fmaf(st, r[11], fmaf(tb[j], r[10], fmaf(ta[j], r[9], r[8])));
-                    gather_tap<C>(acc[j], base[j], rowB, nx, ny, w);
+                    SV_TAP(j, nx, ny, w);
                 }
             }
         }
-        }
-    } else {
-        const int bmin = wave_min_i(lo), bmax = wave_max_i(hi);
-        if (DIMS == 1 && bmax == bmin + 1) {
-            // the block straddles one node: kinked line from interval bmin
-            const int kb = uniform(bmin);
-            float t0[PY], e1[PY];
+        return;
+    }
+    const int bmin = uniform(wave_min_i(lo)), bmax = uniform(wave_max_i(hi));
+    const int span = bmax - bmin;
+    if (DIMS == 1 && span <= 3) {
+        // The block straddles `span` nodes: the piecewise-linear Theta(u) over
+        // intervals bmin..bmax is the line of interval bmin plus one hinge
+        // max(0, u - m) (D_m - D_{m-1}) per interior node m.
+        const float* e = table + (static_cast<size_t>(bmin) * T + tap0) * RW;
+        const size_t step = static_cast<size_t>(T) * RW;
+        auto hinge_loop = [&](auto span_c) {
+            constexpr int SP = decltype(span_c)::value;
+            float t0[PY], h[SP][PY];
 #pragma unroll
             for (int j = 0; j < PY; ++j) {
-                t0[j] = tb[j] - static_cast<float>(kb);
-                e1[j] = fmaxf(t0[j] - 1.0f, 0.0f);
+                t0[j] = tb[j] - static_cast<float>(bmin);
+#pragma unroll
+                for (int m = 0; m < SP; ++m) h[m][j] = fmaxf(t0[j] - static_cast<float>(m + 1), 0.0f);
             }
-            const float* e = table + (static_cast<size_t>(kb) * T + tap0) * RW;
             for (int i = 0; i < N; ++i) {
                 const float* r = e + i * RW;
                 const float Ax = r[0], Dx = r[1], Ay = r[2], Dy = r[3], Aw = r[4], Dw = r[5];
-                const float Ex = r[6], Ey = r[7], Ew = r[8];
+                float Ex[SP], Ey[SP], Ew[SP];
 #pragma unroll
-                for (int j = 0; j < PY; ++j)
-                    gather_tap<C>(acc[j], base[j], rowB, fmaf(e1[j], Ex, fmaf(t0[j], Dx, Ax)),
-                                  fmaf(e1[j], Ey, fmaf(t0[j], Dy, Ay)), fmaf(e1[j], Ew, fmaf(t0[j], Dw, Aw)));
-            }
-        } else {
-            // general case: per-lane coefficients
-            for (int i = 0; i < N; ++i) {
+                for (int m = 0; m < SP; ++m) {
+                    Ex[m] = r[m * step + 6];
+                    Ey[m] = r[m * step + 7];
+                    Ew[m] = r[m * step + 8];
+                }
 #pragma unroll
                 for (int j = 0; j < PY; ++j) {
-                    const float* r = table + (static_cast<size_t>(kk[j]) * T + tap0 + i) * RW;
-                    if (DIMS == 1) {
-                        gather_tap<C>(acc[j], base[j], rowB, fmaf(ta[j], r[1], r[0]), fmaf(ta[j], r[3], r[2]),
-                                      fmaf(ta[j], r[5], r[4]));
-                    } else {
-                        const float st = ta[j] * tb[j];
-                        const float nx = fmaf(st, r[3], fmaf(tb[j], r[2], fmaf(ta[j], r[1], r[0])));
-                        const float ny = fmaf(st, r[7], fmaf(tb[j], r[6], fmaf(ta[j], r[5], r[4])));
-                        const float w = fmaf(st, r[11], fmaf(tb[j], r[10], fmaf(ta[j], r[9], r[8])));
-                        gather_tap<C>(acc[j], base[j], rowB, nx, ny, w);
+                    float nx = fmaf(t0[j], Dx, Ax), ny = fmaf(t0[j], Dy, Ay), w = fmaf(t0[j], Dw, Aw);
+#pragma unroll
+                    for (int m = 0; m < SP; ++m) {
+                        nx = fmaf(h[m][j], Ex[m], nx);
+                        ny = fmaf(h[m][j], Ey[m], ny);
+                        w = fmaf(h[m][j], Ew[m], w);
+                    }
+                    SV_TAP(j, nx, ny, w);
+                }
+            }
+        };
+        if (span == 1)
+            hinge_loop(std::integral_constant<int, 1>{});
+        else if (span == 2)
+            hinge_loop(std::integral_constant<int, 2>{});
+        else
+            hinge_loop(std::integral_constant<int, 3>{});
+        return;
+    }
+    // general case: per-lane coefficients, all rows' loads in flight together
+    for (int i = 0; i < N; ++i) {
+        float rr[PY][RW];
+#pragma unroll
+        for (int j = 0; j < PY; ++j) {
+            const float* r = table + (static_cast<size_t>(kk[j]) * T + tap0 + i) * RW;
+#pragma unroll
+            for (int q = 0; q < RW; ++q) rr[j][q] = r[q];
+        }
+#pragma unroll
+        for (int j = 0; j < PY; ++j) {
+            const float* r = rr[j];
+            if (DIMS == 1) {
+                SV_TAP(j, fmaf(ta[j], r[1], r[0]), fmaf(ta[j], r[3], r[2]), fmaf(ta[j], r[5], r[4]));
+            } else {
+                const float st = ta[j] * tb[j];
+                const float nx = fmaf(st, r[3], fmaf(tb[j], r[2], fmaf(ta[j], r[1], r[0])));
+                const float ny = fmaf(st, r[7], fmaf(tb[j], r[6], fmaf(ta[j], r[5], r[4])));
+                const float w = fmaf(st, r[11], fmaf(tb[j], r[10], fmaf(ta[j], r[9], r[8])));
+                SV_TAP(j, nx, ny, w);
+            }
+        }
+    }
+#undef SV_TAP
+}
+
+// Store one staged pixel (C channels) into the LDS tile.
+template <int C>
+__device__ __forceinline__ void sv_put(float* lds, int rowW, int ly, int cx, const float (&v)[C]) {
+    if (C >= 3) {
+        reinterpret_cast<float4*>(lds + ly * rowW)[cx] = make_float4(v[0], v[1], v[2], C == 4 ? v[C - 1] : 0.0f);
+    } else {
+        float* d = lds + ly * rowW + cx * C;
+#pragma unroll
+        for (int c = 0; c < C; ++c) d[c] = v[c];
+    }
+}
+
+template <int C, typename TOut, int PY>
+__device__ __forceinline__ void sv_store(TOut* __restrict__ Y, size_t plane, int W, int H, int x, int y0,
+                                         const float (&acc)[PY][C]) {
+    if (x >= W) return;
+#pragma unroll
+    for (int j = 0; j < PY; ++j) {
+        const int y = y0 + 4 * j;
+        if (y < H)
+#pragma unroll
+            for (int c = 0; c < C; ++c) IO<TOut>::store(Y, c * plane + static_cast<size_t>(y) * W + x, acc[j][c]);
+    }
+}
+
+// General pass kernel: one tile per work-group, any halo up to 64.
+template <int C, int DIMS, typename TIn, typename TOut, int PY, int NW>
+__global__ __launch_bounds__(64 * NW) void sv_pass_kernel(
+    const TIn* __restrict__ X, TOut* __restrict__ Y, const float* __restrict__ P,
+    const float* __restrict__ table, int tap0, int N, int T, int G0, int G1, int H, int W, int halo,
+    int tiles_x, int per, int ntiles, const int* __restrict__ flag) {
+    extern __shared__ float lds[];
+    constexpr int TH = 4 * PY * (NW / 4);
+    const int tile = xcd_tile(blockIdx.x, per);
+    if (tile >= ntiles) return;
+    const size_t plane = static_cast<size_t>(H) * W;
+    const int tx0 = (tile % tiles_x) * kTW, ty0 = (tile / tiles_x) * TH;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int lx = ((wave & 3) << 4) + (lane & 15), lyb = (wave >> 2) * 4 * PY + (lane >> 4);
+    const int x = tx0 + lx;
+
+    if (*flag) {  // an offset exceeds its declared halo: refuse to gather
+        float nan[PY][C];
+        for (int j = 0; j < PY; ++j)
+            for (int c = 0; c < C; ++c) nan[j][c] = __builtin_nanf("");
+        sv_store<C, TOut, PY>(Y, plane, W, H, x, ty0 + lyb, nan);
+        return;
+    }
+
+    const int SX = kTW + 2 * halo, SY = TH + 2 * halo;
+    const int rowW = sv_row_dwords(halo, C);
+    // decode loads first: their latency overlaps the staging below
+    const int xc = min(x, W - 1);
+    float pv[PY][DIMS];
+#pragma unroll
+    for (int j = 0; j < PY; ++j) {
+        const size_t pi = static_cast<size_t>(min(ty0 + 4 * j + lyb, H - 1)) * W + xc;
+#pragma unroll
+        for (int d = 0; d < DIMS; ++d) pv[j][d] = P[d * plane + pi];
+    }
+    // Stage the tile + clamped halo, loads batched (4 rows x up to 3 column
+    // chunks x C per lane in flight) before the LDS stores.
+    const int nq = (SX + 63) >> 6;
+    for (int r0 = wave; r0 < SY; r0 += 4 * NW) {
+        float v[4][3][C];
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) {
+            const int gy = min(max(ty0 - halo + r0 + NW * rr, 0), H - 1);
+            const size_t grow = static_cast<size_t>(gy) * W;
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                if (q < nq) {
+                    const int gx = min(max(tx0 - halo + lane + 64 * q, 0), W - 1);
+#pragma unroll
+                    for (int c = 0; c < C; ++c) v[rr][q][c] = IO<TIn>::load(X, c * plane + grow + gx);
+                }
+            }
+        }
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) {
+            const int ly = r0 + NW * rr;
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                const int cx = lane + 64 * q;
+                if (q < nq && ly < SY && cx < SX) sv_put<C>(lds, rowW, ly, cx, v[rr][q]);
+            }
+        }
+    }
+    float ta[PY], tb[PY];
+    int kk[PY];
+    sv_decode<DIMS, PY>(pv, G0, G1, ta, tb, kk);
+    __syncthreads();
+
+    const int rowB = rowW * 4;
+    constexpr int PXB = C >= 3 ? 16 : 4 * C;  // bytes per staged pixel
+    const int base0 = lds_offset(lds) + (lyb + halo) * rowB + (lx + halo) * PXB;
+    float acc[PY][C];
+    sv_tile_taps<C, DIMS, PY>(acc, ta, tb, kk, base0, rowB, table, tap0, N, T);
+    sv_store<C, TOut, PY>(Y, plane, W, H, x, ty0 + lyb, acc);
+}
+
+// Persistent, software-pipelined pass kernel (halo <= kPipeHalo): each
+// work-group walks a contiguous run of tiles of its XCD; while it gathers from
+// the tile in LDS, the next tile's inputs and parameter values are already in
+// flight into registers, so HBM/L2 latency overlaps the gather.  16 waves,
+// 2 row-steps per wave: a 64 x 32 tile.
+constexpr int kPipeHalo = 24;
+constexpr int kPipeNW = 16;
+constexpr int kPipePY = 2;
+constexpr int kPipeRPW = (4 * kPipePY * (kPipeNW / 4) + 2 * kPipeHalo + kPipeNW - 1) / kPipeNW;  // staged rows/wave
+constexpr int kPipeNQ = (kTW + 2 * kPipeHalo + 63) / 64;                                        // column chunks
+
+template <int C, int DIMS, typename TIn, typename TOut>
+__global__ __launch_bounds__(64 * kPipeNW) void sv_pass_pipe_kernel(
+    const TIn* __restrict__ X, TOut* __restrict__ Y, const float* __restrict__ P,
+    const float* __restrict__ table, int tap0, int N, int T, int G0, int G1, int H, int W, int halo,
+    int tiles_x, int per, int ntiles, const int* __restrict__ flag) {
+    extern __shared__ float lds[];
+    constexpr int PY = kPipePY, NW = kPipeNW;
+    constexpr int TH = 4 * PY * (NW / 4);
+    const int xcd = blockIdx.x & 7, nwg = gridDim.x >> 3;
+    const int tend = min((xcd + 1) * per, ntiles);
+    int tile = xcd * per + (blockIdx.x >> 3);
+    if (tile >= tend) return;
+    const size_t plane = static_cast<size_t>(H) * W;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int lx = ((wave & 3) << 4) + (lane & 15), lyb = (wave >> 2) * 4 * PY + (lane >> 4);
+
+    if (*flag) {  // an offset exceeds its declared halo: refuse to gather
+        float nan[PY][C];
+        for (int j = 0; j < PY; ++j)
+            for (int c = 0; c < C; ++c) nan[j][c] = __builtin_nanf("");
+        for (; tile < tend; tile += nwg)
+            sv_store<C, TOut, PY>(Y, plane, W, H, (tile % tiles_x) * kTW + lx, (tile / tiles_x) * TH + lyb, nan);
+        return;
+    }
+
+    const int SX = kTW + 2 * halo, SY = TH + 2 * halo;
+    const int rowW = sv_row_dwords(halo, C);
+    const int rowB = rowW * 4;
+    constexpr int PXB = C >= 3 ? 16 : 4 * C;
+    const int base0 = lds_offset(lds) + (lyb + halo) * rowB + (lx + halo) * PXB;
+    const int nq = (SX + 63) >> 6;               // <= kPipeNQ
+    const int nr = (SY - wave + NW - 1) / NW;    // staged rows of this wave, <= kPipeRPW
+
+    float stg[kPipeRPW][kPipeNQ][C];
+    float pv[PY][DIMS];
+    auto issue = [&](int t) {
+        const int tx0 = (t % tiles_x) * kTW, ty0 = (t / tiles_x) * TH;
+#pragma unroll
+        for (int rr = 0; rr < kPipeRPW; ++rr) {
+            if (rr < nr) {
+                const int gy = min(max(ty0 - halo + wave + NW * rr, 0), H - 1);
+                const size_t grow = static_cast<size_t>(gy) * W;
+#pragma unroll
+                for (int q = 0; q < kPipeNQ; ++q) {
+                    if (q < nq) {
+                        const int gx = min(max(tx0 - halo + lane + 64 * q, 0), W - 1);
+#pragma unroll
+                        for (int c = 0; c < C; ++c) stg[rr][q][c] = IO<TIn>::load(X, c * plane + grow + gx);
                     }
                 }
             }
         }
-    }
-
-    if (x < W) {
+        const int xc = min(tx0 + lx, W - 1);
 #pragma unroll
         for (int j = 0; j < PY; ++j) {
-            const int y = ty0 + wave * PY + j;
-            if (y < H)
+            const size_t pi = static_cast<size_t>(min(ty0 + 4 * j + lyb, H - 1)) * W + xc;
 #pragma unroll
-                for (int c = 0; c < C; ++c) IO<TOut>::store(Y, c * plane + static_cast<size_t>(y) * W + x, acc[j][c]);
+            for (int d = 0; d < DIMS; ++d) pv[j][d] = P[d * plane + pi];
         }
+    };
+
+    issue(tile);
+    for (;;) {
+        // the staged registers of `tile` -> LDS
+#pragma unroll
+        for (int rr = 0; rr < kPipeRPW; ++rr) {
+            const int ly = wave + NW * rr;
+#pragma unroll
+            for (int q = 0; q < kPipeNQ; ++q) {
+                const int cx = lane + 64 * q;
+                if (rr < nr && q < nq && cx < SX) sv_put<C>(lds, rowW, ly, cx, stg[rr][q]);
+            }
+        }
+        float ta[PY], tb[PY];
+        int kk[PY];
+        sv_decode<DIMS, PY>(pv, G0, G1, ta, tb, kk);
+        // Keep the decode (and its wait on this tile's P loads) ahead of the
+        // next tile's prefetch: vmcnt retires in order, so a decode sunk below
+        // the prefetch would wait for the whole prefetch.
+#pragma unroll
+        for (int j = 0; j < PY; ++j) asm volatile("" ::"v"(ta[j]), "v"(tb[j]), "v"(kk[j]));
+        __syncthreads();
+        const int x = (tile % tiles_x) * kTW + lx, y0 = (tile / tiles_x) * TH + lyb;
+        const int next = tile + nwg;
+        if (next < tend) issue(next);
+        float acc[PY][C];
+        sv_tile_taps<C, DIMS, PY>(acc, ta, tb, kk, base0, rowB, table, tap0, N, T);
+        sv_store<C, TOut, PY>(Y, plane, W, H, x, y0, acc);
+        if (next >= tend) break;
+        tile = next;
+        __syncthreads();  // every wave is done reading this tile before the next is written
     }
 }
 
-int sv_rows_per_wave(int halo, int C) {
-    // Tuning override (rows per wave: 2, 4, 8 or 16), read once.
-    static const int forced = [] {
-        const char* e = std::getenv("DISK_SV_ROWS");
-        const int v = e ? std::atoi(e) : 0;
-        return (v == 2 || v == 4 || v == 8 || v == 16) ? v : 0;
+// Tile choice.  DISK_SV_PIPE=0 forces the one-tile-per-work-group kernel (a
+// tuning override, read once).
+static int env_int(const char* name, int dflt) {
+    const char* e = std::getenv(name);
+    return e ? std::atoi(e) : dflt;
+}
+
+// LDS bytes of a tile of 4*rows rows.
+size_t sv_lds_bytes(int halo, int C, int rows) {
+    return static_cast<size_t>(sv_row_dwords(halo, C)) * (4 * rows + 2 * halo) * sizeof(float);
+}
+
+int sv_rows_per_wave(int halo, int C) { return sv_lds_bytes(halo, C, 8) <= 160 * 1024 ? 4 : 2; }
+
+static int cu_count() {
+    static const int n = [] {
+        int dev = 0, v = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v <= 0)
+            v = 256;
+        return v;
     }();
-    if (forced && sv_lds_bytes(halo, C, forced) <= 160 * 1024) return forced;
-    // Larger tiles amortise the halo; keep the staged tile within 80 KB so two
-    // work-groups share a CU.
-    for (int py : {8, 4}) {
-        if (sv_lds_bytes(halo, C, py) <= 80 * 1024) return py;
-    }
-    return 2;
+    return n;
 }
 
-size_t sv_lds_bytes(int halo, int C, int py) {
-    return static_cast<size_t>(kTW + 2 * halo) * (4 * py + 2 * halo) * C * sizeof(float);
-}
-
-template <int C, int DIMS, typename TIn, typename TOut, int PY>
-static hipError_t launch_typed(const void* src, void* dst, const float* pmap, const float* table, int tap0,
-                               int N, int T, int G0, int G1, int H, int W, int halo, const int* flag,
-                               hipStream_t s) {
-    const int tiles_x = (W + kTW - 1) / kTW, tiles_y = (H + 4 * PY - 1) / (4 * PY);
+template <int C, int DIMS, typename TIn, typename TOut>
+static hipError_t launch_pipe(const void* src, void* dst, const float* pmap, const float* table, int tap0, int N,
+                              int T, int G0, int G1, int H, int W, int halo, const int* flag, hipStream_t s) {
+    constexpr int TH = 4 * kPipePY * (kPipeNW / 4);
+    const int tiles_x = (W + kTW - 1) / kTW, tiles_y = (H + TH - 1) / TH;
     const int ntiles = tiles_x * tiles_y;
     const int per = (ntiles + 7) / 8;
-    const size_t lds = sv_lds_bytes(halo, C, PY);
-    auto fn = sv_pass_kernel<C, DIMS, TIn, TOut, PY>;
+    const size_t lds = sv_lds_bytes(halo, C, kPipePY * (kPipeNW / 4));
+    auto fn = sv_pass_pipe_kernel<C, DIMS, TIn, TOut>;
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(fn, dim3(8 * per), dim3(256), lds, s, static_cast<const TIn*>(src),
+    int occ = 0;
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, reinterpret_cast<const void*>(fn), 64 * kPipeNW, lds);
+    if (e != hipSuccess || occ < 1) occ = 1;
+    int per_xcd = (cu_count() * occ) / 8;                 // work-groups per XCD
+    per_xcd = std::max(1, std::min(per_xcd, per));
+    hipLaunchKernelGGL(fn, dim3(8 * per_xcd), dim3(64 * kPipeNW), lds, s, static_cast<const TIn*>(src),
+                       static_cast<TOut*>(dst), pmap, table, tap0, N, T, G0, G1, H, W, halo, tiles_x, per, ntiles,
+                       flag);
+    return hipGetLastError();
+}
+
+template <int C, int DIMS, typename TIn, typename TOut, int PY, int NW>
+static hipError_t launch_tiles(const void* src, void* dst, const float* pmap, const float* table, int tap0, int N,
+                               int T, int G0, int G1, int H, int W, int halo, const int* flag, hipStream_t s) {
+    constexpr int TH = 4 * PY * (NW / 4);
+    const int tiles_x = (W + kTW - 1) / kTW, tiles_y = (H + TH - 1) / TH;
+    const int ntiles = tiles_x * tiles_y;
+    const int per = (ntiles + 7) / 8;
+    const size_t lds = sv_lds_bytes(halo, C, PY * (NW / 4));
+    auto fn = sv_pass_kernel<C, DIMS, TIn, TOut, PY, NW>;
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(fn, dim3(8 * per), dim3(64 * NW), lds, s, static_cast<const TIn*>(src),
                        static_cast<TOut*>(dst), pmap, table, tap0, N, T, G0, G1, H, W, halo, tiles_x, per,
                        ntiles, flag);
     return hipGetLastError();
 }
 
-template <int C, int DIMS, int PY>
-static hipError_t launch_io(int src_bf16, const void* src, int dst_bf16, void* dst, const float* pmap,
-                            const float* table, int tap0, int N, int T, int G0, int G1, int H, int W, int halo,
-                            const int* flag, hipStream_t s) {
-    if (!src_bf16 && !dst_bf16)
-        return launch_typed<C, DIMS, float, float, PY>(src, dst, pmap, table, tap0, N, T, G0, G1, H, W, halo, flag, s);
-    if (src_bf16 && !dst_bf16)
-        return launch_typed<C, DIMS, uint16_t, float, PY>(src, dst, pmap, table, tap0, N, T, G0, G1, H, W, halo, flag, s);
-    if (!src_bf16 && dst_bf16)
-        return launch_typed<C, DIMS, float, uint16_t, PY>(src, dst, pmap, table, tap0, N, T, G0, G1, H, W, halo, flag, s);
-    return launch_typed<C, DIMS, uint16_t, uint16_t, PY>(src, dst, pmap, table, tap0, N, T, G0, G1, H, W, halo, flag, s);
+template <int C, int DIMS, typename TIn, typename TOut>
+static hipError_t launch_typed(const void* src, void* dst, const float* pmap, const float* table, int tap0, int N,
+                               int T, int G0, int G1, int H, int W, int halo, const int* flag, hipStream_t s) {
+    static const int pipe = env_int("DISK_SV_PIPE", 1);
+    if (pipe && halo <= kPipeHalo && sv_lds_bytes(halo, C, kPipePY * (kPipeNW / 4)) <= 160 * 1024)
+        return launch_pipe<C, DIMS, TIn, TOut>(src, dst, pmap, table, tap0, N, T, G0, G1, H, W, halo, flag, s);
+    if (sv_rows_per_wave(halo, C) == 4)
+        return launch_tiles<C, DIMS, TIn, TOut, 4, 8>(src, dst, pmap, table, tap0, N, T, G0, G1, H, W, halo, flag, s);
+    return launch_tiles<C, DIMS, TIn, TOut, 2, 4>(src, dst, pmap, table, tap0, N, T, G0, G1, H, W, halo, flag, s);
 }
 
 template <int C, int DIMS>
 static hipError_t launch_py(int src_bf16, const void* src, int dst_bf16, void* dst, const float* pmap,
                             const float* table, int tap0, int N, int T, int G0, int G1, int H, int W, int halo,
                             const int* flag, hipStream_t s) {
-    const int py = sv_rows_per_wave(halo, C);
-    if (py == 16) return launch_io<C, DIMS, 16>(src_bf16, src, dst_bf16, dst, pmap, table, tap0, N, T, G0, G1, H, W, halo, flag, s);
-    if (py == 8) return launch_io<C, DIMS, 8>(src_bf16, src, dst_bf16, dst, pmap, table, tap0, N, T, G0, G1, H, W, halo, flag, s);
-    if (py == 4) return launch_io<C, DIMS, 4>(src_bf16, src, dst_bf16, dst, pmap, table, tap0, N, T, G0, G1, H, W, halo, flag, s);
-    return launch_io<C, DIMS, 2>(src_bf16, src, dst_bf16, dst, pmap, table, tap0, N, T, G0, G1, H, W, halo, flag, s);
+    if (!src_bf16 && !dst_bf16)
+        return launch_typed<C, DIMS, float, float>(src, dst, pmap, table, tap0, N, T, G0, G1, H, W, halo, flag, s);
+    if (src_bf16 && !dst_bf16)
+        return launch_typed<C, DIMS, uint16_t, float>(src, dst, pmap, table, tap0, N, T, G0, G1, H, W, halo, flag, s);
+    if (!src_bf16 && dst_bf16)
+        return launch_typed<C, DIMS, float, uint16_t>(src, dst, pmap, table, tap0, N, T, G0, G1, H, W, halo, flag, s);
+    return launch_typed<C, DIMS, uint16_t, uint16_t>(src, dst, pmap, table, tap0, N, T, G0, G1, H, W, halo, flag, s);
 }
 
 template <int C>

@@ -73,4 +73,13 @@ hipError_t launch_sv_pass(int C, int dims, int src_bf16, const void* src, int ds
                           const float* pmap, const float* table, int tap0, int N, int T, int G0,
                           int G1, int H, int W, int halo, const int* flag, hipStream_t s);
 
+// ---- optimize.hip: batched optimiser and radial init --------------------------
+int opt_workgroups(int B);
+size_t opt_slot_floats(int max_side, int max_L);
+hipError_t launch_optimize(int B, const disk_target* desc, const int* taps, const float* targets, float* theta,
+                           float* psnr, int* steps, int* status, const disk_opt_params& p, int* order, int* queue,
+                           float* scratch, size_t slot_floats, int nwg, int max_side, int max_T, hipStream_t s);
+hipError_t launch_init_radial(int B, const disk_target* desc, const int* taps, const float* targets, float* theta,
+                              hipStream_t s);
+
 }  // namespace disk

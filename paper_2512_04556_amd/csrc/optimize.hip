@@ -1,0 +1,538 @@
+// Batched optimisation of sparse kernel complexes (Sec. 4.1 Eq. 4; impulse
+// supervision Sec. 4.4 Eq. 10-11; Adam with linear learning-rate decay,
+// Sec. 5.1), and the radial initialiser (Eq. 6), for thousands of targets of
+// uneven size in one persistent launch.
+//
+// One work-group owns one target at a time and runs every step of it
+// in-kernel: forward chain on the impulse canvas, loss and PSNR, the adjoint,
+// and the Adam update.  Work-groups pull targets from a queue ordered by
+// decreasing cost (side^2 x taps), so the longest targets start first.
+//
+// Canvases.  Each target keeps L canvases of side S = M + 2P (P = (M+1)/2 + 1)
+// in a per-work-group slot of the workspace: X_1..X_{L-1} and K_syn / G_L.
+// The zero frame of width P is the ZERO boundary: every gather whose corner
+// offsets stay within the frame (|offset| < ~M/2) is unconditional; taps
+// beyond it take a masked path.  During the backward pass G_{l-1} overwrites
+// X_{l-1}, which is dead once layer l's tap gradients are done.  The first
+// layer acts on the impulse, so X_1 is the deterministic sum of its taps'
+// bilinear splats and the first layer's tap gradients are point reads of G_1.
+//
+// Lanes: each wave walks 8 x 8 pixel blocks of the canvas, so lane utilisation
+// stays high from M = 15 to M = 255.  All reductions are fixed-order wave
+// butterflies plus an ordered LDS combine: results are bitwise reproducible.
+#include <algorithm>
+#include <cmath>
+
+#include "common.hpp"
+#include "internal.hpp"
+
+namespace disk {
+
+constexpr int kOptThreads = 256;
+constexpr int kOptWaves = kOptThreads / 64;
+constexpr int kMaxT = DISK_MAX_LAYERS * DISK_MAX_TAPS;  // 256
+constexpr int kChunk = 8;                               // taps per gradient chunk
+
+struct OptArgs {
+    int B;
+    const disk_target* desc;
+    const int* taps;
+    const float* targets;
+    float* theta;
+    float* psnr;
+    int* steps;
+    int* status;
+    disk_opt_params p;
+    const int* order;
+    int* queue;
+    float* scratch;
+    size_t slot_floats;
+    int max_side, max_T;
+};
+
+struct TapO {
+    int ix, iy;                 // floor(-o)
+    float c00, c01, c10, c11;   // w * bilinear corner weights
+    float fx, fy;               // fractions of -o
+};
+
+__device__ __forceinline__ int opt_pad(int M) { return (M + 1) / 2 + 1; }
+
+// Reduce v over the work-group in a fixed order; every thread gets the sum.
+__device__ __forceinline__ float wg_sum(float v, float* red) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    v = wave_sum(v);
+    __syncthreads();
+    if (lane == 0) red[wave] = v;
+    __syncthreads();
+    float s = 0.0f;
+#pragma unroll
+    for (int w = 0; w < kOptWaves; ++w) s += red[w];
+    return s;
+}
+
+__device__ __forceinline__ float wg_max(float v, float* red) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    v = wave_max(v);
+    __syncthreads();
+    if (lane == 0) red[wave] = v;
+    __syncthreads();
+    float s = red[0];
+#pragma unroll
+    for (int w = 1; w < kOptWaves; ++w) s = fmaxf(s, red[w]);
+    return s;
+}
+
+// Lane geometry of an 8 x 8 block walk.
+struct Walk {
+    int M, S, P, nbx, nblk;
+    __device__ Walk(int M_, int S_, int P_) : M(M_), S(S_), P(P_) {
+        nbx = (M + 7) >> 3;
+        nblk = nbx * nbx;
+    }
+    // pixel of block `blk` for this lane; `act` false for lanes past the edge
+    // (their index is clamped onto the canvas so every read stays in bounds)
+    __device__ __forceinline__ int pixel(int blk, int& x, int& y, bool& act) const {
+        const int lane = threadIdx.x & 63;
+        const int by = blk / nbx, bx = blk - by * nbx;
+        x = (bx << 3) + (lane & 7);
+        y = (by << 3) + (lane >> 3);
+        act = x < M && y < M;
+        return (min(y, M - 1) + P) * S + min(x, M - 1) + P;
+    }
+};
+
+// Value of a corner read that may leave the frame (masked path).
+__device__ __forceinline__ float masked(const float* buf, int x, int y, int dx, int dy, int M, int S, int P) {
+    const int xx = x + dx, yy = y + dy;
+    if (xx < 0 || xx >= M || yy < 0 || yy >= M) return 0.0f;
+    return buf[(yy + P) * S + xx + P];
+}
+
+// dst[p] = sum_taps sum_ab c_ab src[p + sgn * d_ab] over the interior (sgn = +1:
+// forward gather; sgn = -1: the transpose, used for G_{l-1}).
+template <int SGN>
+__device__ void gather_layer(const float* __restrict__ src, float* __restrict__ dst, const TapO* tp, int N,
+                             const Walk& wk) {
+    const int wave = threadIdx.x >> 6;
+    const int M = wk.M, S = wk.S, P = wk.P;
+    for (int blk = wave; blk < wk.nblk; blk += kOptWaves) {
+        int x, y;
+        bool act;
+        const int base = wk.pixel(blk, x, y, act);
+        float acc = 0.0f;
+        for (int i = 0; i < N; ++i) {
+            const TapO t = tp[i];
+            // corner offsets: forward p + (ix+a, iy+b); transpose q - (ix+a, iy+b)
+            const bool inside = t.ix >= -P && t.ix <= P - 1 && t.iy >= -P && t.iy <= P - 1;
+            if (inside) {
+                if (SGN > 0) {
+                    const float* q = src + base + t.iy * S + t.ix;
+                    acc = fmaf(t.c00, q[0], acc);
+                    acc = fmaf(t.c01, q[1], acc);
+                    acc = fmaf(t.c10, q[S], acc);
+                    acc = fmaf(t.c11, q[S + 1], acc);
+                } else {
+                    const float* q = src + base - t.iy * S - t.ix;
+                    acc = fmaf(t.c00, q[0], acc);
+                    acc = fmaf(t.c01, q[-1], acc);
+                    acc = fmaf(t.c10, q[-S], acc);
+                    acc = fmaf(t.c11, q[-S - 1], acc);
+                }
+            } else {
+                const int xc = min(x, M - 1), yc = min(y, M - 1);
+                acc = fmaf(t.c00, masked(src, xc, yc, SGN * t.ix, SGN * t.iy, M, S, P), acc);
+                acc = fmaf(t.c01, masked(src, xc, yc, SGN * (t.ix + 1), SGN * t.iy, M, S, P), acc);
+                acc = fmaf(t.c10, masked(src, xc, yc, SGN * t.ix, SGN * (t.iy + 1), M, S, P), acc);
+                acc = fmaf(t.c11, masked(src, xc, yc, SGN * (t.ix + 1), SGN * (t.iy + 1), M, S, P), acc);
+            }
+        }
+        if (act) dst[base] = acc;
+    }
+}
+
+__global__ __launch_bounds__(kOptThreads) void opt_kernel(OptArgs a) {
+    __shared__ float th[kMaxT * 3], am[kMaxT * 3], av[kMaxT * 3], gr[kMaxT * 3];
+    __shared__ TapO tap[kMaxT];
+    __shared__ float sS[kMaxT][4];
+    __shared__ float red[kOptWaves * kChunk * 4];
+    __shared__ int s_q;
+    __shared__ int t0[DISK_MAX_LAYERS + 1];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    float* slot = a.scratch + blockIdx.x * a.slot_floats;
+
+    for (;;) {
+        if (tid == 0) s_q = atomicAdd(a.queue, 1);
+        __syncthreads();
+        const int q = s_q;
+        __syncthreads();
+        if (q >= a.B) break;
+        const int b = a.order[q];
+        const disk_target d = a.desc[b];
+        const int M = d.side, L = d.L, P = opt_pad(M), S = M + 2 * P;
+        const int* ntap = a.taps + d.taps_off;
+        // validate the descriptor (it lives on the device): a malformed target
+        // is skipped with status 3
+        bool bad = M < 1 || (M & 1) == 0 || M > a.max_side || L < 1 || L > DISK_MAX_LAYERS;
+        int T = 0;
+        if (!bad)
+            for (int l = 0; l < L; ++l) {
+                bad |= ntap[l] < 1 || ntap[l] > DISK_MAX_TAPS;
+                T += ntap[l];
+            }
+        bad |= T > a.max_T || static_cast<size_t>(M + 2 * P) * (M + 2 * P) * L > a.slot_floats;
+        if (bad) {
+            if (tid == 0) {
+                a.psnr[b] = 0.0f;
+                a.steps[b] = 0;
+                a.status[b] = 3;
+            }
+            __syncthreads();
+            continue;
+        }
+        if (tid == 0) {
+            t0[0] = 0;
+            for (int l = 0; l < L; ++l) t0[l + 1] = t0[l] + ntap[l];
+        }
+        const float* tgt = a.targets + d.target_off;
+        float* theta_g = a.theta + 3 * static_cast<size_t>(d.theta_off);
+        const size_t SS = static_cast<size_t>(S) * S;
+        const Walk wk(M, S, P);
+        const int c = (M - 1) / 2;          // impulse centre (both axes)
+        const float n = static_cast<float>(M) * M;
+
+        // ---- target setup: parameters, moments, zeroed canvases, peak -------
+        for (int i = tid; i < 3 * T; i += kOptThreads) {
+            th[i] = theta_g[i];
+            am[i] = 0.0f;
+            av[i] = 0.0f;
+        }
+        for (size_t i = tid; i < SS * L; i += kOptThreads) slot[i] = 0.0f;
+        float pk = -INFINITY;
+        for (int i = tid; i < M * M; i += kOptThreads) pk = fmaxf(pk, tgt[i]);
+        pk = wg_max(pk, red);
+        const float inv_pk2 = 1.0f / (pk * pk);
+        float b1t = 1.0f, b2t = 1.0f;
+        float psnr = 0.0f;
+        int status = 0, step = 0;
+        __syncthreads();
+
+        for (step = 0;; ++step) {
+            // ---- taps of the current Theta --------------------------------
+            for (int i = tid; i < T; i += kOptThreads) {
+                const float ox = th[3 * i], oy = th[3 * i + 1], w = th[3 * i + 2];
+                TapO t;
+                floor_frac(-ox, t.ix, t.fx);
+                floor_frac(-oy, t.iy, t.fy);
+                const float wy1 = w * t.fy, wy0 = w - wy1;
+                t.c01 = wy0 * t.fx;
+                t.c00 = wy0 - t.c01;
+                t.c11 = wy1 * t.fx;
+                t.c10 = wy1 - t.c11;
+                tap[i] = t;
+            }
+            __syncthreads();
+
+            // ---- forward: X_1 = splats of layer 1 on the impulse ------------
+            float* X1 = slot + (L == 1 ? 0 : SS);
+            for (int blk = wave; blk < wk.nblk; blk += kOptWaves) {
+                int x, y;
+                bool act;
+                const int base = wk.pixel(blk, x, y, act);
+                float acc = 0.0f;
+                for (int i = 0; i < ntap[0]; ++i) {
+                    const TapO t = tap[i];
+                    // corner (a, b) of pixel p reads p + (ix+a, iy+b); the impulse is at c
+                    const int ax = c - x - t.ix, ay = c - y - t.iy;
+                    if (ax >= 0 && ax <= 1 && ay >= 0 && ay <= 1)
+                        acc += ay == 0 ? (ax == 0 ? t.c00 : t.c01) : (ax == 0 ? t.c10 : t.c11);
+                }
+                if (act) X1[base] = acc;
+            }
+            __syncthreads();
+            for (int l = 1; l < L; ++l) {
+                const float* src = slot + l * SS;
+                float* dst = slot + (l == L - 1 ? 0 : (l + 1) * SS);
+                gather_layer<1>(src, dst, tap + t0[l], ntap[l], wk);
+                __syncthreads();
+            }
+
+            // ---- loss, PSNR, G_L (in place of K_syn) ------------------------
+            float se = 0.0f, ch = 0.0f;
+            const float ce = a.p.charb_eps;
+            for (int blk = wave; blk < wk.nblk; blk += kOptWaves) {
+                int x, y;
+                bool act;
+                const int base = wk.pixel(blk, x, y, act);
+                if (act) {
+                    const float dv = slot[base] - tgt[y * M + x];
+                    se = fmaf(dv, dv, se);
+                    float g;
+                    if (a.p.loss == DISK_LOSS_CHARBONNIER) {
+                        const float dn = dv / pk;
+                        const float r = sqrtf(fmaf(dn, dn, ce * ce));
+                        ch += r;
+                        g = dn / (r * n * pk);
+                    } else {
+                        g = 2.0f * dv * inv_pk2 / n;
+                    }
+                    slot[base] = g;
+                }
+            }
+            se = wg_sum(se, red);
+            if (a.p.loss == DISK_LOSS_CHARBONNIER) ch = wg_sum(ch, red);
+            const float nmse = se * inv_pk2 / n;
+            const float loss = a.p.loss == DISK_LOSS_CHARBONNIER ? ch / n : nmse;
+            psnr = nmse > 0.0f ? -10.0f * log10f(nmse) : INFINITY;
+            if (!isfinite(loss)) {
+                status = 2;
+                break;
+            }
+            if (psnr >= a.p.psnr_stop_db) {
+                status = 1;
+                break;
+            }
+            if (step >= a.p.max_steps) break;
+
+            // ---- backward ----------------------------------------------------
+            for (int l = L - 1; l >= 0; --l) {
+                const float* G = slot + (l == L - 1 ? 0 : (l + 1) * SS);   // G_{l+1} (1-based l+1)
+                const TapO* tp = tap + t0[l];
+                const int N = ntap[l];
+                if (l == 0) {
+                    // layer 1 reads the impulse: S_ab = G_1[c - d_ab]
+                    for (int i = tid; i < N; i += kOptThreads) {
+                        const TapO t = tp[i];
+#pragma unroll
+                        for (int ab = 0; ab < 4; ++ab) {
+                            const int px = c - t.ix - (ab & 1), py = c - t.iy - (ab >> 1);
+                            sS[i][ab] = (px >= 0 && px < M && py >= 0 && py < M) ? G[(py + P) * S + px + P] : 0.0f;
+                        }
+                    }
+                } else {
+                    const float* X = slot + l * SS;   // X_l (1-based), input of this layer
+                    for (int i0 = 0; i0 < N; i0 += kChunk) {
+                        const int nc = min(kChunk, N - i0);
+                        float s[kChunk][4];
+#pragma unroll
+                        for (int k = 0; k < kChunk; ++k)
+#pragma unroll
+                            for (int ab = 0; ab < 4; ++ab) s[k][ab] = 0.0f;
+                        for (int blk = wave; blk < wk.nblk; blk += kOptWaves) {
+                            int x, y;
+                            bool act;
+                            const int base = wk.pixel(blk, x, y, act);
+                            const float g = act ? G[base] : 0.0f;
+#pragma unroll
+                            for (int k = 0; k < kChunk; ++k) {
+                                if (k < nc) {
+                                    const TapO t = tp[i0 + k];
+                                    float v00, v01, v10, v11;
+                                    if (t.ix >= -P && t.ix <= P - 1 && t.iy >= -P && t.iy <= P - 1) {
+                                        const float* q = X + base + t.iy * S + t.ix;
+                                        v00 = q[0];
+                                        v01 = q[1];
+                                        v10 = q[S];
+                                        v11 = q[S + 1];
+                                    } else {
+                                        const int xc = min(x, M - 1), yc = min(y, M - 1);
+                                        v00 = masked(X, xc, yc, t.ix, t.iy, M, S, P);
+                                        v01 = masked(X, xc, yc, t.ix + 1, t.iy, M, S, P);
+                                        v10 = masked(X, xc, yc, t.ix, t.iy + 1, M, S, P);
+                                        v11 = masked(X, xc, yc, t.ix + 1, t.iy + 1, M, S, P);
+                                    }
+                                    s[k][0] = fmaf(g, v00, s[k][0]);
+                                    s[k][1] = fmaf(g, v01, s[k][1]);
+                                    s[k][2] = fmaf(g, v10, s[k][2]);
+                                    s[k][3] = fmaf(g, v11, s[k][3]);
+                                }
+                            }
+                        }
+                        // fixed-order reduction of the chunk's 4 * nc sums
+#pragma unroll
+                        for (int k = 0; k < kChunk; ++k)
+#pragma unroll
+                            for (int ab = 0; ab < 4; ++ab) {
+                                const float v = wave_sum(s[k][ab]);
+                                if (lane == 0) red[(wave * kChunk + k) * 4 + ab] = v;
+                            }
+                        __syncthreads();
+                        if (tid < 4 * nc) {
+                            const int k = tid >> 2, ab = tid & 3;
+                            float v = 0.0f;
+                            for (int w = 0; w < kOptWaves; ++w) v += red[(w * kChunk + k) * 4 + ab];
+                            sS[i0 + k][ab] = v;
+                        }
+                        __syncthreads();
+                    }
+                }
+                __syncthreads();
+                // dTheta of this layer's taps
+                for (int i = tid; i < N; i += kOptThreads) {
+                    const TapO t = tp[i];
+                    const float w = th[3 * (t0[l] + i) + 2];
+                    const float S00 = sS[i][0], S01 = sS[i][1], S10 = sS[i][2], S11 = sS[i][3];
+                    const float fx = t.fx, fy = t.fy;
+                    gr[3 * (t0[l] + i) + 0] = -w * ((1.0f - fy) * (S01 - S00) + fy * (S11 - S10));
+                    gr[3 * (t0[l] + i) + 1] = -w * ((1.0f - fx) * (S10 - S00) + fx * (S11 - S01));
+                    gr[3 * (t0[l] + i) + 2] =
+                        (1.0f - fy) * ((1.0f - fx) * S00 + fx * S01) + fy * ((1.0f - fx) * S10 + fx * S11);
+                }
+                if (l > 0) {
+                    // G_l (1-based) = transpose of layer l+1 applied to G_{l+1}, into X_l's canvas
+                    gather_layer<-1>(G, slot + l * SS, tp, N, wk);
+                }
+                __syncthreads();
+            }
+
+            // ---- Adam ----------------------------------------------------------
+            const float lr = a.p.max_steps > 1
+                                 ? a.p.lr0 + (a.p.lr1 - a.p.lr0) * (static_cast<float>(step) /
+                                                                     static_cast<float>(a.p.max_steps - 1))
+                                 : a.p.lr0;
+            b1t *= a.p.beta1;
+            b2t *= a.p.beta2;
+            const float bc1 = 1.0f - b1t, bc2 = 1.0f - b2t;
+            for (int i = tid; i < 3 * T; i += kOptThreads) {
+                const float g = gr[i];
+                const float m = fmaf(a.p.beta1, am[i], (1.0f - a.p.beta1) * g);
+                const float v = fmaf(a.p.beta2, av[i], (1.0f - a.p.beta2) * g * g);
+                am[i] = m;
+                av[i] = v;
+                th[i] -= lr * (m / bc1) / (sqrtf(v / bc2) + a.p.eps);
+            }
+            __syncthreads();
+        }
+
+        for (int i = tid; i < 3 * T; i += kOptThreads) theta_g[i] = th[i];
+        if (tid == 0) {
+            a.psnr[b] = psnr;
+            a.steps[b] = step;
+            a.status[b] = status;
+        }
+        __syncthreads();
+    }
+}
+
+// Order targets by decreasing cost (side^2 x taps) with a bucketed counting
+// sort in one work-group, and reset the work queue.
+constexpr int kOrderBuckets = 4096;
+__global__ __launch_bounds__(1024) void opt_order_kernel(int B, const disk_target* __restrict__ desc,
+                                                         const int* __restrict__ taps, int* __restrict__ order,
+                                                         int* __restrict__ queue) {
+    __shared__ int hist[kOrderBuckets];
+    for (int i = threadIdx.x; i < kOrderBuckets; i += blockDim.x) hist[i] = 0;
+    __syncthreads();
+    auto key = [&](int b) {
+        const disk_target d = desc[b];
+        int T = 0;
+        for (int l = 0; l < d.L; ++l) T += taps[d.taps_off + l];
+        const float cost = static_cast<float>(d.side) * d.side * max(T, 1);
+        // log-spaced buckets, largest cost -> bucket 0
+        const int k = static_cast<int>(log2f(cost) * 128.0f);
+        return kOrderBuckets - 1 - min(max(k, 0), kOrderBuckets - 1);
+    };
+    for (int b = threadIdx.x; b < B; b += blockDim.x) atomicAdd(&hist[key(b)], 1);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int run = 0;
+        for (int i = 0; i < kOrderBuckets; ++i) {
+            const int h = hist[i];
+            hist[i] = run;
+            run += h;
+        }
+        *queue = 0;
+    }
+    __syncthreads();
+    for (int b = threadIdx.x; b < B; b += blockDim.x) order[atomicAdd(&hist[key(b)], 1)] = b;
+}
+
+int opt_workgroups(int B) {
+    int dev = 0, n = 0;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        n <= 0)
+        n = 256;
+    return std::max(1, std::min(B, 2 * n));
+}
+
+size_t opt_slot_floats(int max_side, int max_L) {
+    const int S = max_side + 2 * ((max_side + 1) / 2 + 1);
+    return (static_cast<size_t>(S) * S * max_L + 63) & ~size_t(63);
+}
+
+hipError_t launch_optimize(int B, const disk_target* desc, const int* taps, const float* targets, float* theta,
+                           float* psnr, int* steps, int* status, const disk_opt_params& p, int* order, int* queue,
+                           float* scratch, size_t slot_floats, int nwg, int max_side, int max_T, hipStream_t s) {
+    hipLaunchKernelGGL(opt_order_kernel, dim3(1), dim3(1024), 0, s, B, desc, taps, order, queue);
+    OptArgs a{B, desc, taps, targets, theta, psnr, steps, status, p, order, queue, scratch, slot_floats, max_side, max_T};
+    hipLaunchKernelGGL(opt_kernel, dim3(nwg), dim3(kOptThreads), 0, s, a);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Radial initialisation (Eq. 6), one work-group per target.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void init_radial_kernel(int B, const disk_target* __restrict__ desc,
+                                                          const int* __restrict__ taps,
+                                                          const float* __restrict__ targets,
+                                                          float* __restrict__ theta) {
+    __shared__ float red[4];
+    const int tid = threadIdx.x;
+    for (int b = blockIdx.x; b < B; b += gridDim.x) {
+        const disk_target d = desc[b];
+        const int M = d.side, h = (M - 1) / 2;
+        const float* K = targets + d.target_off;
+        // total mass, then the smallest integer squared radius whose disk holds 99%
+        float tot = 0.0f;
+        for (int i = tid; i < M * M; i += 256) tot += K[i];
+        auto wsum = [&](float v) {
+            v = wave_sum(v);
+            __syncthreads();
+            if ((tid & 63) == 0) red[tid >> 6] = v;
+            __syncthreads();
+            return (red[0] + red[1]) + (red[2] + red[3]);
+        };
+        tot = wsum(tot);
+        int lo = 0, hi = 2 * h * h;   // mass(hi) = tot
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            float m = 0.0f;
+            for (int i = tid; i < M * M; i += 256) {
+                const int y = i / M, x = i - y * M;
+                const int dx = x - h, dy = y - h;
+                if (dx * dx + dy * dy <= mid) m += K[i];
+            }
+            m = wsum(m);
+            if (m >= 0.99f * tot)
+                hi = mid;
+            else
+                lo = mid + 1;
+        }
+        const float R = fminf(static_cast<float>(h), sqrtf(static_cast<float>(lo)));
+        const int L = d.L;
+        const float dr = 2.0f * R / static_cast<float>(L * (L + 1));
+        float* out = theta + 3 * static_cast<size_t>(d.theta_off);
+        int off = 0;
+        for (int l = 0; l < L; ++l) {
+            const int N = taps[d.taps_off + l];
+            const float r = static_cast<float>(l + 1) * dr;
+            for (int i = tid; i < N; i += 256) {
+                const float ang = 6.283185307179586f * static_cast<float>(i + 1) / static_cast<float>(N);
+                out[3 * (off + i) + 0] = r * cosf(ang);
+                out[3 * (off + i) + 1] = r * sinf(ang);
+                out[3 * (off + i) + 2] = 1.0f / static_cast<float>(N);
+            }
+            off += N;
+        }
+        __syncthreads();
+    }
+}
+
+hipError_t launch_init_radial(int B, const disk_target* desc, const int* taps, const float* targets, float* theta,
+                              hipStream_t s) {
+    const int nblk = std::max(1, std::min(B, 4096));
+    hipLaunchKernelGGL(init_radial_kernel, dim3(nblk), dim3(256), 0, s, B, desc, taps, targets, theta);
+    return hipGetLastError();
+}
+
+}  // namespace disk

@@ -3,18 +3,6 @@
 #include "internal.hpp"
 
 extern "C" {
-size_t disk_optimize_workspace_size(const disk_batch_meta*) { return 0; }
-disk_status disk_optimize_batch(const disk_batch_meta*, const disk_target*, const int32_t*, const float*, float*,
-                                float*, int32_t*, int32_t*, const disk_opt_params*, void*, size_t, hipStream_t) {
-    return DISK_UNSUPPORTED;
-}
-disk_status disk_init_radial(const disk_batch_meta*, const disk_target*, const int32_t*, const float*, float*,
-                             hipStream_t) {
-    return DISK_UNSUPPORTED;
-}
-disk_status disk_init_shape(const float*, int32_t, int32_t, const int32_t*, uint64_t, int32_t, float*, double*) {
-    return DISK_UNSUPPORTED;
-}
 int64_t disk_net_param_count(void) { return 0; }
 size_t disk_net_workspace_size(int32_t) { return 0; }
 disk_status disk_init_predict(const float*, const uint16_t*, const float*, float*, int32_t, void*, size_t,
