@@ -9,7 +9,8 @@ For one layer with input X = X_{l-1}, output gradient G = dL/dX_l and a tap
 * dL/dw      = sum_p G[p] * B(X, p - o)
 * dL/do_x    = -w * sum_p G[p] * dB/ds_x(X, s)|_{s = p - o}   (likewise y),
   with dB/ds_x = (1-fy)(X[y0,x0+1] - X[y0,x0]) + fy(X[y0+1,x0+1] - X[y0+1,x0])
-  (floor makes it right-continuous at integer positions);
+  (floor makes it right-continuous at integer positions; x0 = p + floor(-o)
+  exactly, so the side of a kink is the same at every pixel);
 * dL/dX_{l-1} is the exact transpose of the gather: every output pixel sends
   G[p] * w * corner_weight to each of its four (boundary-mapped) corners;
   corners that fall outside a ZERO canvas send nothing, CLAMP corners send to
@@ -42,14 +43,14 @@ def layer_vjp(X, layer, boundary, G):
     dlayer = np.zeros((len(layer), 3))
     dX = np.zeros_like(X)
     for i, (ox, oy, w) in enumerate(np.asarray(layer, dtype=np.float64)):
-        sx = px - ox
-        sy = py - oy
-        x0f = np.floor(sx)
-        y0f = np.floor(sy)
-        fx = sx - x0f
-        fy = sy - y0f
-        x0 = x0f.astype(np.int64)
-        y0 = y0f.astype(np.int64)
+        # p - o with the integer part p + floor(-o) and the fraction from o
+        # alone (exact; see oracle.sparse.bilinear_offset)
+        flx = np.floor(-ox)
+        fly = np.floor(-oy)
+        fx = np.full(px.shape, -ox - flx)
+        fy = np.full(py.shape, -oy - fly)
+        x0 = (px + flx).astype(np.int64)
+        y0 = (py + fly).astype(np.int64)
         corners = []
         for dy in (0, 1):
             for dx in (0, 1):

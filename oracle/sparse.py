@@ -73,6 +73,29 @@ def bilinear(X, sx, sy, boundary):
             + fx * fy * _read(X, y0 + 1, x0 + 1, boundary))
 
 
+def bilinear_offset(X, px, py, ox, oy, boundary):
+    """B(X, p - o) for integer pixel coordinates p and offsets o.
+
+    Identical to ``bilinear(X, px - ox, py - oy)`` in exact arithmetic; the
+    integer part is formed as p + floor(-o) and the fraction as
+    -o - floor(-o), so no rounding of p - o can move a sample across an
+    integer (where the read's derivative is discontinuous) when |o| is below
+    the spacing of floats near p."""
+    X = np.asarray(X, dtype=np.float64)
+    nox = -np.asarray(ox, dtype=np.float64)
+    noy = -np.asarray(oy, dtype=np.float64)
+    fl_x = np.floor(nox)
+    fl_y = np.floor(noy)
+    fx = nox - fl_x
+    fy = noy - fl_y
+    x0 = (np.asarray(px) + fl_x).astype(np.int64)
+    y0 = (np.asarray(py) + fl_y).astype(np.int64)
+    return ((1.0 - fx) * (1.0 - fy) * _read(X, y0, x0, boundary)
+            + fx * (1.0 - fy) * _read(X, y0, x0 + 1, boundary)
+            + (1.0 - fx) * fy * _read(X, y0 + 1, x0, boundary)
+            + fx * fy * _read(X, y0 + 1, x0 + 1, boundary))
+
+
 def pixel_grid(H, W):
     """Integer pixel-centre coordinates (x, y), each of shape [H][W]."""
     y, x = np.mgrid[0:H, 0:W]
@@ -87,7 +110,7 @@ def sparse_layer(X, layer, boundary):
     px, py = pixel_grid(H, W)
     Y = np.zeros_like(X)
     for ox, oy, w in np.asarray(layer, dtype=np.float64):
-        Y += w * bilinear(X, px - ox, py - oy, boundary)
+        Y += w * bilinear_offset(X, px, py, ox, oy, boundary)
     return Y
 
 

@@ -15,7 +15,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from .sparse import CLAMP, bilinear, pixel_grid
+from .sparse import CLAMP, bilinear_offset, pixel_grid
 from .interp import tap_field
 
 
@@ -34,7 +34,7 @@ def sv_chain(image, pmap, basis, grid, taps, keep=False):
         Y = np.zeros_like(Xs[-1])
         for i in range(t0, t0 + int(N)):
             ox, oy, w = tap_field(basis, P, grid, i)
-            Y += w * bilinear(Xs[-1], px - ox, py - oy, CLAMP)
+            Y += w * bilinear_offset(Xs[-1], px, py, ox, oy, CLAMP)
         t0 += int(N)
         Xs.append(Y)
     return Xs if keep else Xs[-1]

@@ -1,0 +1,162 @@
+"""GPU parity of the batched optimiser (Sec. 4.1 Eq. 4, Sec. 4.4 Eq. 10-11,
+Adam of Sec. 5.1) and the radial initialiser (Eq. 6) against the FP64 oracle,
+through the C ABI."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import paper_2512_04556_amd as disk
+from oracle import adam as Ad
+from oracle import adjoint as A
+from oracle import init as I
+from oracle import loss as Lo
+from oracle import sparse as S
+from synth import gaussian_kernel, mixed_batch, pack_targets, shape_batch, TargetBatch
+from tests.gpu_util import say
+
+pytestmark = pytest.mark.gpu
+
+
+def _single(K, taps):
+    return TargetBatch([K.astype(np.float32)], np.array([len(taps)], np.int32), [np.array(taps, np.int32)], [{}])
+
+
+def _run(batch, theta0, **kw):
+    desc, taps, tg = pack_targets(batch)
+    bt = disk.make_batch(desc, taps, tg)
+    th = torch.as_tensor(np.asarray(theta0, np.float32)).cuda().contiguous()
+    ps, st, stat = disk.disk_optimize_batch(bt, th, disk.OptParams(**kw))
+    torch.cuda.synchronize()
+    return th.cpu().numpy().astype(np.float64), ps.cpu().numpy(), st.cpu().numpy(), stat.cpu().numpy()
+
+
+def _theta0(batch, init="radial"):
+    rows = []
+    for b in range(batch.B):
+        rows.append(I.radial_init(batch.kernels[b].astype(np.float64), batch.taps[b]))
+    return np.concatenate(rows).astype(np.float32)
+
+
+def test_radial_init_kernel_matches_oracle(dev):
+    batch = mixed_batch(64, seed=11)
+    desc, taps, tg = pack_targets(batch)
+    bt = disk.make_batch(desc, taps, tg)
+    say("init radial", batch.B)
+    got = disk.disk_init_radial(bt).cpu().numpy().astype(np.float64)
+    want = _theta0(batch).astype(np.float64)
+    for b in range(batch.B):
+        o, T = int(desc[b, 3]), int(np.sum(batch.taps[b]))
+        R = I.radial_extent(batch.kernels[b].astype(np.float64))
+        err = np.abs(got[o:o + T] - want[o:o + T]).max()
+        assert err <= 2e-6 * max(R, 1.0), (b, err, R)
+
+
+def test_zero_steps_reports_initial_psnr(dev):
+    K = gaussian_kernel(31, 6.0)
+    taps = [8, 8, 8]
+    batch = _single(K, taps)
+    th0 = _theta0(batch)
+    say("opt zero steps")
+    th, ps, st, stat = _run(batch, th0, max_steps=0)
+    Ks = S.impulse_response(31, th0.astype(np.float64), taps)
+    assert st[0] == 0 and stat[0] == 0
+    assert np.array_equal(th.astype(np.float32), th0)
+    assert abs(ps[0] - Lo.psnr_db(Ks, K)) < 1e-3
+
+
+@pytest.mark.parametrize("M,taps,loss", [(31, [8, 8, 8], Lo.NMSE), (45, [6, 9, 4, 7], Lo.NMSE),
+                                         (63, [12, 12, 12, 12], Lo.CHARBONNIER), (15, [6, 6], Lo.NMSE)])
+def test_one_adam_step_matches_oracle(dev, M, taps, loss):
+    """After one step Adam moves every parameter by -lr * g / (|g| + eps):
+    this pins the sign of every gradient component of the adjoint."""
+    K = shape_batch(1, M, len(taps), taps[0], seed=M).kernels[0] if M != 31 else gaussian_kernel(31, 6.0)
+    batch = _single(K, taps)
+    th0 = _theta0(batch)
+    say("opt one step", M, taps, loss)
+    th, ps, st, stat = _run(batch, th0, max_steps=1, lr0=1e-2, lr1=1e-2, loss=loss)
+    _, _, g = A.impulse_loss_grad(K.astype(np.float64), th0.astype(np.float64), taps, loss)
+    want, _, _ = Ad.adam_update(th0.astype(np.float64), g, np.zeros_like(g), np.zeros_like(g), 1, 1e-2)
+    assert st[0] == 1
+    # Components well above the rounding noise of the gradient move by exactly
+    # lr in the gradient's direction.  Components that vanish by symmetry (the
+    # tangential offsets of a radially symmetric target under the radial
+    # init) are noise in both precisions and may take either sign.
+    big = np.abs(g) > 1e-3 * np.abs(g).max()
+    np.testing.assert_allclose(th[big], want[big], rtol=0, atol=1e-6)
+    np.testing.assert_allclose(th, want, rtol=0, atol=1e-2 + 1e-6)
+
+
+def test_short_trajectory_matches_oracle(dev):
+    """Mixed-size batch, 10 steps from identical Theta_0: NMSE per target within
+    0.1 dB of the FP64 oracle (FP32 vs FP64 rounding only)."""
+    batch = mixed_batch(12, seed=21, side=(15, 63))
+    th0 = _theta0(batch)
+    say("opt short trajectory", batch.B)
+    th, ps, st, stat = _run(batch, th0, max_steps=10, lr0=1e-2, lr1=1e-3)
+    desc, _, _ = pack_targets(batch)
+    p = Ad.OptParams(max_steps=10, lr0=1e-2, lr1=1e-3)
+    for b in range(batch.B):
+        o, T = int(desc[b, 3]), int(np.sum(batch.taps[b]))
+        _, ps_o, st_o = Ad.optimize(batch.kernels[b].astype(np.float64), th0[o:o + T], batch.taps[b], p)
+        assert st[b] == 10 and stat[b] == 0
+        assert abs(ps[b] - ps_o) < 0.1, (b, ps[b], ps_o)
+
+
+def test_config1_gaussian_trajectory(dev):
+    """31x31 Gaussian sigma 6, 3 x 8 taps, radial init (Eq. 6), Adam at lr 1e-2:
+    the PSNR after 5, 10 and 20 steps agrees with the oracle to 0.01 dB.  (From
+    the exactly symmetric radial start the iteration later leaves a saddle along
+    directions set by rounding noise, so long runs are compared from a jittered
+    start below.)"""
+    K = gaussian_kernel(31, 6.0)
+    taps = [8, 8, 8]
+    batch = _single(K, taps)
+    th0 = _theta0(batch)
+    for n in (5, 10, 20):
+        say("opt config1 trajectory", n)
+        th, ps, st, stat = _run(batch, th0, max_steps=n, lr0=1e-2, lr1=1e-2)
+        _, ps_o, _ = Ad.optimize(K, th0, taps, Ad.OptParams(max_steps=n, lr0=1e-2, lr1=1e-2))
+        print(f"config1 {n} steps: GPU {ps[0]:.4f} dB oracle {ps_o:.4f} dB")
+        assert st[0] == n and abs(ps[0] - ps_o) < 0.01
+
+
+def test_config1_300_steps_from_jittered_start(dev):
+    K = gaussian_kernel(31, 6.0)
+    taps = [8, 8, 8]
+    batch = _single(K, taps)
+    th0 = _theta0(batch)
+    jit = np.random.default_rng(1).normal(0.0, 0.2, th0.shape).astype(np.float32)
+    jit[:, 2] = 0.0
+    th0 = th0 + jit
+    say("opt config1 300 steps jittered")
+    th, ps, st, stat = _run(batch, th0, max_steps=300, lr0=1e-2, lr1=1e-2)
+    _, ps_o, _ = Ad.optimize(K, th0, taps, Ad.OptParams(max_steps=300, lr0=1e-2, lr1=1e-2))
+    print(f"config1 jittered 300 steps: GPU {ps[0]:.3f} dB oracle {ps_o:.3f} dB")
+    assert st[0] == 300 and abs(ps[0] - ps_o) < 0.2
+
+
+def test_stopping_rule_and_invalid_target(dev):
+    batch = mixed_batch(3, seed=5, side=(15, 31))
+    th0 = _theta0(batch)
+    desc, taps, tg = pack_targets(batch)
+    desc = desc.copy()
+    desc[1, 0] = 16                         # even side: rejected on the device
+    bt = disk.make_batch(desc, taps, tg)
+    th = torch.as_tensor(th0).cuda()
+    say("opt stop rule")
+    ps, st, stat = disk.disk_optimize_batch(bt, th, disk.OptParams(max_steps=50, psnr_stop_db=-100.0))
+    stat = stat.cpu().numpy()
+    st = st.cpu().numpy()
+    assert stat[1] == 3
+    assert stat[0] == 1 and st[0] == 0 and stat[2] == 1 and st[2] == 0
+
+
+def test_batch_deterministic(dev):
+    batch = mixed_batch(40, seed=8, side=(15, 127))
+    th0 = _theta0(batch)
+    say("opt determinism")
+    a = _run(batch, th0, max_steps=5)
+    b = _run(batch, th0, max_steps=5)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])

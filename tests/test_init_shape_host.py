@@ -1,0 +1,37 @@
+"""The library's host shape-aware initialiser (Eq. 7) against the FP64 oracle:
+both follow the same dart-throwing definition with the same counter-based
+random stream, so the results agree to FP32 rounding of the oracle (CPU only,
+no GPU involved)."""
+import numpy as np
+import pytest
+
+import paper_2512_04556_amd as disk
+from oracle import init as I
+from synth import ring_kernel, polygon_kernel, star_kernel, gaussian_kernel
+
+
+@pytest.mark.parametrize("kind,M,taps,seed,index", [
+    ("ring", 63, [12, 12, 12, 12], 4, 0),
+    ("hex", 41, [8, 6], 9, 17),
+    ("star", 63, [16, 12, 8], 1, 3),
+    ("gauss", 31, [8, 8, 8], 2, 5),
+    ("ring", 15, [6], 7, 1),
+])
+def test_shape_init_matches_oracle(kind, M, taps, seed, index):
+    K = {"ring": lambda: ring_kernel(M, 0.9 * (M - 1) / 2, 0.6),
+         "hex": lambda: polygon_kernel(M, 6, 0.9 * (M - 1) / 2, 0.3),
+         "star": lambda: star_kernel(M, 5, 0.9 * (M - 1) / 2, 0.45, 0.2),
+         "gauss": lambda: gaussian_kernel(M, 4.0)}[kind]().astype(np.float32)
+    got, r = disk.disk_init_shape(K, taps, seed, index)
+    want, r_o = I.ss_init(K.astype(np.float64), taps, seed, index)
+    assert abs(r - r_o) <= 1e-12 * max(1.0, r_o)
+    np.testing.assert_array_equal(got.numpy(), want.astype(np.float32))
+
+
+def test_shape_init_rejects_bad_shapes():
+    K = np.ones((8, 8), np.float32)
+    with pytest.raises(disk.DiskError):
+        disk.disk_init_shape(K, [4], 1)          # even side
+    K = np.ones((9, 9), np.float32)
+    with pytest.raises(disk.DiskError):
+        disk.disk_init_shape(K, [40], 1)         # too many taps

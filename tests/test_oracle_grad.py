@@ -137,3 +137,18 @@ def test_optimiser_recovers_a_representable_target():
     assert steps == 150 and ps > trace[0][1] + 10.0
     _, ps0, steps0 = Ad.optimize(target, th_true, taps, p)
     assert steps0 == 0 and ps0 == float("inf")
+
+
+def test_kink_side_is_the_same_at_every_pixel():
+    """A tap offset o = +1e-16 samples just left of an integer: floor(p - o)
+    = p - 1 at every pixel p, so the offset derivative uses the left segment
+    everywhere.  On X[y, x] = x^2 with G = 1 that segment's slope is 2x - 1;
+    a rounded p - o would flip to the right segment (2x + 1) once ulp(p) > o."""
+    W = 64
+    X = np.tile((np.arange(W, dtype=np.float64) ** 2)[None, :], (3, 1))
+    G = np.zeros_like(X)
+    G[1, 1:] = 1.0                          # columns 1..63, one interior row
+    lay = np.array([[1e-16, 0.0, 0.5]])
+    dl, _ = A.layer_vjp(X, lay, S.CLAMP, G)
+    x = np.arange(1, W, dtype=np.float64)
+    assert dl[0, 0] == -0.5 * np.sum(2 * x - 1)
