@@ -145,7 +145,13 @@ typedef struct {
  *   psnr_db  device float [B]: PSNR of the returned Theta, 10 log10(max(K)^2 / MSE);
  *   steps    device int32 [B]: Adam updates applied;
  *   status   device int32 [B]: 0 ok, 1 stopped at the PSNR threshold,
- *            2 diverged (non-finite loss; Theta left at the last finite value).
+ *            2 diverged (non-finite loss; Theta left at the last finite value),
+ *            3 invalid descriptor (even or out-of-range side, L outside
+ *            1..DISK_MAX_LAYERS, a layer with 0 or more than DISK_MAX_TAPS taps,
+ *            side or total taps above meta's maxima, a negative offset
+ *            field); that target is skipped, its Theta untouched, psnr_db 0
+ *            and steps 0.  Offsets past the ends of the arrays cannot be
+ *            detected: they are the caller's responsibility.
  *   meta     host: B, the maximum side and total taps, used to size the launch.
  * Loss: normalised MSE, mean((K_syn - K)^2) / max(K)^2, or Charbonnier.
  */
@@ -167,7 +173,9 @@ disk_status disk_optimize_batch(const disk_batch_meta* meta, const disk_target* 
  * sin 2 pi i/N_l) for i = 1..N_l, w = 1/N_l; R = min((M-1)/2, r99) with r99
  * the smallest pixel-centre distance whose disk holds >= 99% of the target's
  * mass (the paper defers the step size to an appendix; this is the reading
- * adopted).  Arguments as in disk_optimize_batch; theta is written.
+ * adopted).  Arguments as in disk_optimize_batch; theta is written.  A target
+ * whose descriptor disk_optimize_batch would reject (status 3) is skipped and
+ * its Theta left as it was.
  */
 disk_status disk_init_radial(const disk_batch_meta* meta, const disk_target* desc,
                              const int32_t* taps, const float* targets, float* theta,

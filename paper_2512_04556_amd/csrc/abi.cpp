@@ -459,7 +459,8 @@ disk_status disk_init_radial(const disk_batch_meta* meta, const disk_target* des
     DISK_TRY(check_ptr(taps, "taps"));
     DISK_TRY(check_ptr(targets, "targets"));
     DISK_TRY(check_ptr(theta, "theta"));
-    DISK_HIP(launch_init_radial(meta->B, desc, taps, targets, theta, stream), "init radial");
+    DISK_HIP(launch_init_radial(meta->B, desc, taps, targets, theta, meta->max_side, meta->max_T, stream),
+             "init radial");
     return ok();
 }
 

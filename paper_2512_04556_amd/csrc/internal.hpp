@@ -80,6 +80,6 @@ hipError_t launch_optimize(int B, const disk_target* desc, const int* taps, cons
                            float* psnr, int* steps, int* status, const disk_opt_params& p, int* order, int* queue,
                            float* scratch, size_t slot_floats, int nwg, int max_side, int max_T, hipStream_t s);
 hipError_t launch_init_radial(int B, const disk_target* desc, const int* taps, const float* targets, float* theta,
-                              hipStream_t s);
+                              int max_side, int max_T, hipStream_t s);
 
 }  // namespace disk

@@ -173,7 +173,8 @@ __global__ __launch_bounds__(kOptThreads) void opt_kernel(OptArgs a) {
         const int* ntap = a.taps + d.taps_off;
         // validate the descriptor (it lives on the device): a malformed target
         // is skipped with status 3
-        bool bad = M < 1 || (M & 1) == 0 || M > a.max_side || L < 1 || L > DISK_MAX_LAYERS;
+        bool bad = M < 1 || (M & 1) == 0 || M > a.max_side || L < 1 || L > DISK_MAX_LAYERS ||
+                   d.taps_off < 0 || d.theta_off < 0 || d.target_off < 0;
         int T = 0;
         if (!bad)
             for (int l = 0; l < L; ++l) {
@@ -475,12 +476,25 @@ hipError_t launch_optimize(int B, const disk_target* desc, const int* taps, cons
 __global__ __launch_bounds__(256) void init_radial_kernel(int B, const disk_target* __restrict__ desc,
                                                           const int* __restrict__ taps,
                                                           const float* __restrict__ targets,
-                                                          float* __restrict__ theta) {
+                                                          float* __restrict__ theta, int max_side,
+                                                          int max_T) {
     __shared__ float red[4];
     const int tid = threadIdx.x;
     for (int b = blockIdx.x; b < B; b += gridDim.x) {
         const disk_target d = desc[b];
         const int M = d.side, h = (M - 1) / 2;
+        // same descriptor checks as the optimiser; a malformed target is left alone
+        bool bad = M < 1 || (M & 1) == 0 || M > max_side || d.L < 1 || d.L > DISK_MAX_LAYERS ||
+                   d.taps_off < 0 || d.theta_off < 0 || d.target_off < 0;
+        if (!bad) {
+            int T = 0;
+            for (int l = 0; l < d.L; ++l) {
+                bad |= taps[d.taps_off + l] < 1 || taps[d.taps_off + l] > DISK_MAX_TAPS;
+                T += taps[d.taps_off + l];
+            }
+            bad |= T > max_T;
+        }
+        if (bad) continue;   // uniform across the block: every thread reads the same descriptor
         const float* K = targets + d.target_off;
         // total mass, then the smallest integer squared radius whose disk holds 99%
         float tot = 0.0f;
@@ -529,9 +543,10 @@ __global__ __launch_bounds__(256) void init_radial_kernel(int B, const disk_targ
 }
 
 hipError_t launch_init_radial(int B, const disk_target* desc, const int* taps, const float* targets, float* theta,
-                              hipStream_t s) {
+                              int max_side, int max_T, hipStream_t s) {
     const int nblk = std::max(1, std::min(B, 4096));
-    hipLaunchKernelGGL(init_radial_kernel, dim3(nblk), dim3(256), 0, s, B, desc, taps, targets, theta);
+    hipLaunchKernelGGL(init_radial_kernel, dim3(nblk), dim3(256), 0, s, B, desc, taps, targets, theta,
+                       max_side, max_T);
     return hipGetLastError();
 }
 
