@@ -168,6 +168,25 @@ disk_status disk_optimize_batch(const disk_batch_meta* meta, const disk_target* 
                                 hipStream_t stream);
 
 /*
+ * Basis precompute (the offline stage of Sec. 4.3): fits the B targets in
+ * order by continuation, so that tap i plays the same role in every entry.
+ * Entry 0 starts from theta as given (e.g. disk_init_radial); entry k >= 1
+ * starts from the fitted entry k-1 with its offsets multiplied by scale[k]
+ * (e.g. r_k / r_{k-1}) and its weights copied, then runs the same
+ * optimisation as disk_optimize_batch (one launch per entry, in stream order).
+ * An entry whose layer structure differs from the previous entry's starts
+ * from theta as given.
+ *   scale   host float [B] (scale[0] unused), finite and > 0;
+ *   ws      device scratch of disk_fit_basis_workspace_size() bytes;
+ *   other arguments as in disk_optimize_batch.
+ */
+size_t disk_fit_basis_workspace_size(const disk_batch_meta* meta);
+disk_status disk_fit_basis(const disk_batch_meta* meta, const disk_target* desc, const int32_t* taps,
+                           const float* targets, float* theta, float* psnr_db, int32_t* steps, int32_t* status,
+                           const float* scale, const disk_opt_params* params, void* ws, size_t ws_bytes,
+                           hipStream_t stream);
+
+/*
  * Radial initialisation (Sec. 4.1 Eq. 6) of every target of a batch, on the
  * device: r_l = l * dr with dr = 2R / (L (L+1)), o_{l,i} = r_l (cos 2 pi i/N_l,
  * sin 2 pi i/N_l) for i = 1..N_l, w = 1/N_l; R = min((M-1)/2, r99) with r99

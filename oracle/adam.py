@@ -75,3 +75,22 @@ def optimize(target, theta0, taps, p: OptParams, trace=None):
     if trace is not None:
         trace.append((loss, ps))
     return theta, ps, p.max_steps
+
+
+def fit_continuation(targets, theta0, taps, scale, p: OptParams):
+    """Basis precompute by continuation (the offline stage of Sec. 4.3, with
+    the tap-correspondence reading: every entry shares one layer structure).
+    Entry 0 starts from ``theta0``; entry k starts from the fitted entry k-1
+    with its offsets multiplied by scale[k] and its weights kept.
+    Returns (thetas [G][T][3], psnr_db [G], steps [G])."""
+    thetas, psnrs, steps = [], [], []
+    start = np.array(theta0, dtype=np.float64).reshape(-1, 3)
+    for k, target in enumerate(targets):
+        if k > 0:
+            start = thetas[-1].copy()
+            start[:, :2] *= scale[k]
+        th, ps, st = optimize(target, start, taps, p)
+        thetas.append(th)
+        psnrs.append(ps)
+        steps.append(st)
+    return np.stack(thetas), np.array(psnrs), np.array(steps)

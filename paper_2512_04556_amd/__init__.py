@@ -16,7 +16,7 @@ import torch
 __all__ = [
     "lib", "DiskError", "ZERO", "CLAMP", "F32", "BF16", "LOSS_NMSE", "LOSS_CHARBONNIER",
     "disk_forward", "disk_backward", "disk_sv_filter", "disk_sv_prepare", "disk_sv_apply", "Basis", "make_basis",
-    "disk_optimize_batch", "disk_init_radial", "disk_init_shape", "OptParams", "Batch", "make_batch",
+    "disk_optimize_batch", "disk_init_radial", "disk_fit_basis", "pack_targets", "fit_basis", "disk_init_shape", "OptParams", "Batch", "make_batch",
     "disk_init_predict", "disk_net_train_step", "disk_net_prepare_inputs", "disk_net_scatter_theta",
     "disk_net_param_count",
 ]
@@ -73,6 +73,9 @@ def lib():
         "disk_optimize_workspace_size": (c_size_t, [POINTER(DiskBatchMeta)]),
         "disk_optimize_batch": (c_int32, [POINTER(DiskBatchMeta), P, P, P, P, P, P, P, POINTER(DiskOptParams), P, c_size_t, P]),
         "disk_init_radial": (c_int32, [POINTER(DiskBatchMeta), P, P, P, P, P]),
+        "disk_fit_basis_workspace_size": (c_size_t, [POINTER(DiskBatchMeta)]),
+        "disk_fit_basis": (c_int32, [POINTER(DiskBatchMeta), P, P, P, P, P, P, P, POINTER(c_float),
+                                     POINTER(DiskOptParams), P, c_size_t, P]),
         "disk_init_shape": (c_int32, [P, c_int32, c_int32, P, c_uint64, c_int32, P, POINTER(c_double)]),
         "disk_basis_set_halo": (c_int32, [POINTER(DiskBasis), P]),
         "disk_sv_filter_workspace_size": (c_size_t, [POINTER(DiskBasis), c_int32, c_int32, c_int32, c_int32]),
@@ -317,6 +320,52 @@ def disk_optimize_batch(batch: Batch, theta, params: OptParams):
                                  _ptr(theta), _ptr(psnr), _ptr(steps), _ptr(status), ctypes.byref(params.c),
                                  _ptr(ws), ws.numel(), _stream()))
     return psnr, steps, status
+
+
+def disk_fit_basis(batch: Batch, theta, scale, params: OptParams):
+    """Fit the targets of ``batch`` in order by continuation (entry k starts
+    from the fitted entry k-1, offsets times scale[k]); entry 0 starts from
+    ``theta`` as given.  Returns (psnr_db [B], steps [B], status [B])."""
+    dev = theta.device
+    B = batch.B
+    sc = (c_float * B)(*[float(x) for x in scale])
+    psnr = torch.empty(B, dtype=torch.float32, device=dev)
+    steps = torch.empty(B, dtype=torch.int32, device=dev)
+    status = torch.empty(B, dtype=torch.int32, device=dev)
+    L = lib()
+    ws = _workspace(L.disk_fit_basis_workspace_size(ctypes.byref(batch.meta)), dev)
+    _check(L.disk_fit_basis(ctypes.byref(batch.meta), _ptr(batch.desc), _ptr(batch.taps), _ptr(batch.targets),
+                            _ptr(theta), _ptr(psnr), _ptr(steps), _ptr(status), sc, ctypes.byref(params.c),
+                            _ptr(ws), ws.numel(), _stream()))
+    return psnr, steps, status
+
+
+def pack_targets(kernels, taps):
+    """Lay out square kernels (odd sides) that share the layer structure
+    ``taps`` as a batch: desc rows (side, L, taps_off, theta_off, target_off),
+    one taps list per target, kernels concatenated."""
+    taps = [int(t) for t in taps]
+    T = sum(taps)
+    desc, tp, flat, to = [], [], [], 0
+    for b, k in enumerate(kernels):
+        k = torch.as_tensor(k, dtype=torch.float32)
+        desc.append((int(k.shape[0]), len(taps), len(tp), b * T, to))
+        tp.extend(taps)
+        flat.append(k.reshape(-1))
+        to += int(k.numel())
+    return (torch.tensor(desc, dtype=torch.int32), torch.tensor(tp, dtype=torch.int32), torch.cat(flat))
+
+
+def fit_basis(kernels, taps, scale, params: OptParams = None):
+    """Basis precompute: radial init of the first entry, then continuation
+    over the entries in order.  Returns (theta [G][T][3] device, psnr_db,
+    steps, status) with the per-entry results on the host."""
+    params = params or OptParams(max_steps=1000, lr0=1e-2, lr1=1e-3)
+    batch = make_batch(*pack_targets(kernels, taps))
+    theta = disk_init_radial(batch)
+    psnr, steps, status = disk_fit_basis(batch, theta, scale, params)
+    return (theta.view(len(kernels), sum(int(t) for t in taps), 3), psnr.cpu().numpy(), steps.cpu().numpy(),
+            status.cpu().numpy())
 
 
 def disk_init_radial(batch: Batch, theta=None):

@@ -401,6 +401,18 @@ static disk_status check_meta(const disk_batch_meta* m) {
     return DISK_OK;
 }
 
+static disk_status check_opt_params(const disk_opt_params* params) {
+    if (!params) return fail(DISK_INVALID_ARG, "params is NULL");
+    const disk_opt_params& p = *params;
+    if (p.max_steps < 0) return fail(DISK_INVALID_ARG, "max_steps=%d < 0", p.max_steps);
+    if (!(p.beta1 >= 0.0f && p.beta1 < 1.0f) || !(p.beta2 >= 0.0f && p.beta2 < 1.0f) || !(p.eps > 0.0f))
+        return fail(DISK_INVALID_ARG, "bad Adam hyper-parameters");
+    if (!std::isfinite(p.lr0) || !std::isfinite(p.lr1)) return fail(DISK_INVALID_ARG, "non-finite learning rate");
+    if (p.loss != DISK_LOSS_NMSE && p.loss != DISK_LOSS_CHARBONNIER) return fail(DISK_INVALID_ARG, "bad loss %d", p.loss);
+    if (p.loss == DISK_LOSS_CHARBONNIER && !(p.charb_eps > 0.0f)) return fail(DISK_INVALID_ARG, "charb_eps must be > 0");
+    return DISK_OK;
+}
+
 static size_t optimize_ws(const disk_batch_meta* m, Carve& cv, int** order, int** queue, float** scratch,
                           size_t* slot, int* nwg) {
     *nwg = opt_workgroups(m->B);
@@ -431,14 +443,8 @@ disk_status disk_optimize_batch(const disk_batch_meta* meta, const disk_target* 
     DISK_TRY(check_ptr(psnr_db, "psnr_db"));
     DISK_TRY(check_ptr(steps, "steps"));
     DISK_TRY(check_ptr(status, "status"));
-    if (!params) return fail(DISK_INVALID_ARG, "params is NULL");
+    DISK_TRY(check_opt_params(params));
     const disk_opt_params& p = *params;
-    if (p.max_steps < 0) return fail(DISK_INVALID_ARG, "max_steps=%d < 0", p.max_steps);
-    if (!(p.beta1 >= 0.0f && p.beta1 < 1.0f) || !(p.beta2 >= 0.0f && p.beta2 < 1.0f) || !(p.eps > 0.0f))
-        return fail(DISK_INVALID_ARG, "bad Adam hyper-parameters");
-    if (!std::isfinite(p.lr0) || !std::isfinite(p.lr1)) return fail(DISK_INVALID_ARG, "non-finite learning rate");
-    if (p.loss != DISK_LOSS_NMSE && p.loss != DISK_LOSS_CHARBONNIER) return fail(DISK_INVALID_ARG, "bad loss %d", p.loss);
-    if (p.loss == DISK_LOSS_CHARBONNIER && !(p.charb_eps > 0.0f)) return fail(DISK_INVALID_ARG, "charb_eps must be > 0");
     Carve cv(ws, ws_bytes);
     int *order, *queue, nwg;
     float* scratch;
@@ -450,6 +456,51 @@ disk_status disk_optimize_batch(const disk_batch_meta* meta, const disk_target* 
                              slot, nwg, meta->max_side, meta->max_T, stream),
              "optimize");
     return ok();
+}
+
+disk_status disk_fit_basis(const disk_batch_meta* meta, const disk_target* desc, const int32_t* taps,
+                           const float* targets, float* theta, float* psnr_db, int32_t* steps, int32_t* status,
+                           const float* scale, const disk_opt_params* params, void* ws, size_t ws_bytes,
+                           hipStream_t stream) {
+    DISK_TRY(check_meta(meta));
+    DISK_TRY(check_ptr(desc, "desc"));
+    DISK_TRY(check_ptr(taps, "taps"));
+    DISK_TRY(check_ptr(targets, "targets"));
+    DISK_TRY(check_ptr(theta, "theta"));
+    DISK_TRY(check_ptr(psnr_db, "psnr_db"));
+    DISK_TRY(check_ptr(steps, "steps"));
+    DISK_TRY(check_ptr(status, "status"));
+    if (!scale) return fail(DISK_INVALID_ARG, "scale is NULL");
+    for (int k = 1; k < meta->B; ++k)
+        if (!(std::isfinite(scale[k]) && scale[k] > 0.0f))
+            return fail(DISK_INVALID_ARG, "scale[%d]=%g must be finite and > 0", k, static_cast<double>(scale[k]));
+    DISK_TRY(check_opt_params(params));
+    const disk_batch_meta one{1, meta->max_side, meta->max_T};
+    Carve cv(ws, ws_bytes);
+    int *order, *queue, nwg;
+    float* scratch;
+    size_t slot;
+    optimize_ws(&one, cv, &order, &queue, &scratch, &slot, &nwg);
+    if (!ws || cv.used > ws_bytes)
+        return fail(DISK_WORKSPACE_TOO_SMALL, "workspace %zu < %zu bytes", ws_bytes, cv.used);
+    for (int k = 0; k < meta->B; ++k) {
+        if (k > 0) DISK_HIP(launch_continue(desc, taps, theta, k, scale[k], stream), "continuation start");
+        DISK_HIP(launch_optimize(1, desc + k, taps, targets, theta, psnr_db + k, steps + k, status + k, *params,
+                                 order, queue, scratch, slot, nwg, meta->max_side, meta->max_T, stream),
+                 "optimize");
+    }
+    return ok();
+}
+
+size_t disk_fit_basis_workspace_size(const disk_batch_meta* meta) {
+    if (check_meta(meta) != DISK_OK) return 0;
+    const disk_batch_meta one{1, meta->max_side, meta->max_T};
+    Carve cv(nullptr, 0);
+    int *order, *queue, nwg;
+    float* scratch;
+    size_t slot;
+    optimize_ws(&one, cv, &order, &queue, &scratch, &slot, &nwg);
+    return cv.used;
 }
 
 disk_status disk_init_radial(const disk_batch_meta* meta, const disk_target* desc, const int32_t* taps,

@@ -448,6 +448,33 @@ __global__ __launch_bounds__(1024) void opt_order_kernel(int B, const disk_targe
     for (int b = threadIdx.x; b < B; b += blockDim.x) order[atomicAdd(&hist[key(b)], 1)] = b;
 }
 
+// Continuation start of basis entry k (k >= 1): Theta_k = Theta*_{k-1} with its
+// offsets scaled by `scale` and its weights copied, when both entries have the
+// same layer structure; otherwise Theta_k stays as given.
+__global__ __launch_bounds__(64) void continue_kernel(const disk_target* __restrict__ desc,
+                                                      const int* __restrict__ taps, float* __restrict__ theta, int k,
+                                                      float scale) {
+    const disk_target a = desc[k - 1], b = desc[k];
+    if (a.L != b.L || a.L < 1 || a.L > DISK_MAX_LAYERS || a.taps_off < 0 || b.taps_off < 0 || a.theta_off < 0 ||
+        b.theta_off < 0)
+        return;
+    int T = 0;
+    for (int l = 0; l < a.L; ++l) {
+        const int na = taps[a.taps_off + l], nb = taps[b.taps_off + l];
+        if (na != nb || na < 1 || na > DISK_MAX_TAPS) return;
+        T += na;
+    }
+    const float* src = theta + 3 * static_cast<size_t>(a.theta_off);
+    float* dst = theta + 3 * static_cast<size_t>(b.theta_off);
+    for (int i = threadIdx.x; i < 3 * T; i += 64) dst[i] = (i % 3 == 2) ? src[i] : src[i] * scale;
+}
+
+hipError_t launch_continue(const disk_target* desc, const int* taps, float* theta, int k, float scale,
+                           hipStream_t s) {
+    hipLaunchKernelGGL(continue_kernel, dim3(1), dim3(64), 0, s, desc, taps, theta, k, scale);
+    return hipGetLastError();
+}
+
 int opt_workgroups(int B) {
     int dev = 0, n = 0;
     if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||

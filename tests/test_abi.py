@@ -108,3 +108,32 @@ def test_basis_halo_from_host_copy():
     assert [d.halo[0], d.halo[1]] == [5, 9]
     th[0, 2, 2] = float("nan")
     assert disk.lib().disk_basis_set_halo(ctypes.byref(d), ctypes.c_void_p(host.data_ptr())) == -1
+
+
+def test_optimiser_and_basis_fit_validation():
+    L = disk.lib()
+    P = ctypes.c_void_p
+    fake = P(0x1000)
+    meta = disk.DiskBatchMeta(4, 31, 24)
+    prm = disk.OptParams(max_steps=10).c
+    sc = (ctypes.c_float * 4)(1.0, 2.0, 1.5, 1.2)
+    ws = 1 << 30
+    args = (ctypes.byref(meta), fake, fake, fake, fake, fake, fake, fake)
+    # even max_side, B < 1
+    bad = disk.DiskBatchMeta(4, 30, 24)
+    assert L.disk_optimize_batch(ctypes.byref(bad), *args[1:], ctypes.byref(prm), fake, ws, None) == -2
+    assert L.disk_fit_basis(ctypes.byref(disk.DiskBatchMeta(0, 31, 24)), *args[1:], sc, ctypes.byref(prm),
+                            fake, ws, None) == -2
+    # scale missing or not positive
+    assert L.disk_fit_basis(*args, None, ctypes.byref(prm), fake, ws, None) == -1
+    sc_bad = (ctypes.c_float * 4)(1.0, 2.0, 0.0, 1.2)
+    assert L.disk_fit_basis(*args, sc_bad, ctypes.byref(prm), fake, ws, None) == -1
+    assert b"scale[2]" in L.disk_last_error()
+    # Adam hyper-parameters
+    bad_p = disk.OptParams(max_steps=10, beta1=1.0).c
+    assert L.disk_fit_basis(*args, sc, ctypes.byref(bad_p), fake, ws, None) == -1
+    assert L.disk_optimize_batch(*args, ctypes.byref(bad_p), fake, ws, None) == -1
+    # workspace too small
+    need = L.disk_fit_basis_workspace_size(ctypes.byref(meta))
+    assert need > 0
+    assert L.disk_fit_basis(*args, sc, ctypes.byref(prm), fake, need - 512, None) == -3

@@ -160,3 +160,78 @@ def test_batch_deterministic(dev):
     a = _run(batch, th0, max_steps=5)
     b = _run(batch, th0, max_steps=5)
     assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+def _basis_batch(kernels, taps):
+    desc, tp, tg = disk.pack_targets(kernels, taps)
+    return disk.make_batch(desc, tp, tg)
+
+
+def test_fit_basis_continuation_start(dev):
+    """max_steps = 0: entry 0 keeps its start, entry k is entry k-1 with the
+    offsets times scale[k] (FP32 products, bitwise) and the weights copied."""
+    from synth import disk_kernel
+    taps = [6, 6, 6]
+    radii = [2.0, 3.0, 4.5, 6.0]
+    kernels = [disk_kernel(r) for r in radii]
+    bt = _basis_batch(kernels, taps)
+    th = disk.disk_init_radial(bt)
+    th0 = th.cpu().numpy().copy()
+    scale = [1.0] + [radii[k] / radii[k - 1] for k in range(1, 4)]
+    say("fit_basis zero steps")
+    ps, st, stat = disk.disk_fit_basis(bt, th, scale, disk.OptParams(max_steps=0))
+    got = th.cpu().numpy().reshape(4, 18, 3)
+    want = th0.reshape(4, 18, 3)[0].copy()
+    np.testing.assert_array_equal(got[0], want)
+    for k in range(1, 4):
+        want = want.copy()
+        want[:, :2] = want[:, :2] * np.float32(scale[k])
+        np.testing.assert_array_equal(got[k], want)
+    assert list(st.cpu().numpy()) == [0, 0, 0, 0]
+
+
+def test_fit_basis_matches_oracle_continuation(dev):
+    """20 Adam steps per entry on four disks r = 2, 3, 4, 5 (2 layers x 6
+    taps): PSNR per entry within 0.05 dB of the FP64 continuation, and
+    entry 0 bitwise equal to a plain disk_optimize_batch of that target."""
+    from synth import disk_kernel
+    taps = [6, 6]
+    radii = [2.0, 3.0, 4.0, 5.0]
+    kernels = [disk_kernel(r) for r in radii]
+    scale = [1.0] + [radii[k] / radii[k - 1] for k in range(1, 4)]
+    bt = _basis_batch(kernels, taps)
+    th = disk.disk_init_radial(bt)
+    th0 = th[:12].cpu().numpy().astype(np.float64)
+    prm = dict(max_steps=20, lr0=1e-2, lr1=1e-3)
+    say("fit_basis 20 steps")
+    ps, st, stat = disk.disk_fit_basis(bt, th, scale, disk.OptParams(**prm))
+    ps = ps.cpu().numpy()
+    p = Ad.OptParams(psnr_stop_db=float("inf"), **prm)
+    _, ps_o, _ = Ad.fit_continuation([k.astype(np.float64) for k in kernels], th0, taps, scale, p)
+    print("fit_basis PSNR", ps, "oracle", ps_o)
+    assert np.all(np.abs(ps - ps_o) <= 0.05), (ps, ps_o)
+    th1, ps1, _, _ = _run(_single(kernels[0], taps), th0.astype(np.float32), **prm)
+    np.testing.assert_array_equal(th.cpu().numpy()[:12], th1.astype(np.float32))
+    assert ps1[0] == ps[0]
+
+
+def test_fit_basis_exact_dilations_take_no_steps(dev):
+    """Targets that are exact dilations of one filter (computed by the
+    oracle): from the exact first entry every continuation start is already
+    above the stop threshold, so no entry takes a step."""
+    from synth import random_theta
+    taps = [4, 3]
+    th_true = random_theta(taps, 1.5, seed=5).astype(np.float64)
+    s = 1.25
+    kernels = []
+    for k in range(4):
+        t = th_true.copy()
+        t[:, :2] *= s ** k
+        kernels.append(S.impulse_response(2 * int(np.ceil(3.5 * s ** k)) + 9, t, taps).astype(np.float32))
+    bt = _basis_batch(kernels, taps)
+    th = torch.as_tensor(np.tile(th_true.astype(np.float32), (4, 1))).cuda().contiguous()
+    say("fit_basis dilations")
+    ps, st, stat = disk.disk_fit_basis(bt, th, [1.0] + [s] * 3,
+                                       disk.OptParams(max_steps=50, psnr_stop_db=100.0))
+    assert list(st.cpu().numpy()) == [0, 0, 0, 0], (st, ps)
+    assert list(stat.cpu().numpy()) == [1, 1, 1, 1]

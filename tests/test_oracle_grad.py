@@ -152,3 +152,25 @@ def test_kink_side_is_the_same_at_every_pixel():
     dl, _ = A.layer_vjp(X, lay, S.CLAMP, G)
     x = np.arange(1, W, dtype=np.float64)
     assert dl[0, 0] == -0.5 * np.sum(2 * x - 1)
+
+
+def test_continuation_follows_exact_dilations():
+    """Targets that are exact dilations of one representable filter, entry k
+    = F(Theta_true with offsets x s^k): started at Theta_true, every entry's
+    continuation start is already exact, so no entry takes a step."""
+    taps = [4, 3]
+    th_true = random_theta(taps, 1.5, seed=5).astype(np.float64)
+    s = 1.25
+    targets = []
+    for k in range(4):
+        th = th_true.copy()
+        th[:, :2] *= s ** k
+        targets.append(S.impulse_response(2 * int(np.ceil(3.5 * s ** k)) + 9, th, taps))
+    p = Ad.OptParams(max_steps=50, lr0=1e-2, lr1=1e-3, psnr_stop_db=250.0)
+    thetas, ps, steps = Ad.fit_continuation(targets, th_true, taps, [1.0] + [s] * 3, p)
+    assert list(steps) == [0, 0, 0, 0]
+    assert np.all(ps >= 250.0)
+    np.testing.assert_allclose(thetas[3][:, :2], th_true[:, :2] * s ** 3, rtol=1e-14)
+    # and a wrong-direction scale does need steps
+    _, _, steps2 = Ad.fit_continuation(targets, th_true, taps, [1.0] + [1 / s] * 3, p)
+    assert steps2[1] > 0
