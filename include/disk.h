@@ -270,46 +270,75 @@ disk_status disk_sv_apply(const disk_basis* b, const void* table, const void* im
                           disk_dtype io, void* ws, size_t ws_bytes, hipStream_t stream);
 
 /* ------------------------------------------------------------------------- */
-/* Learned initialiser (not in the paper): conv encoder + MLP, BF16 in, FP32   */
-/* accumulate on MFMA.                                                        */
+/* Learned initialiser (not in the paper): a conv encoder + MLP that predicts  */
+/* a starting Theta for the optimiser; BF16 operands, FP32 accumulation on     */
+/* MFMA.                                                                      */
 /* ------------------------------------------------------------------------- */
 /*
- * Network: 64x64x1 -> 6 x [conv3x3 stride 2 pad 1 + bias + ReLU] with widths
- * 32, 64, 128, 128, 256, 256 -> FC 256->512 + ReLU -> FC 512->144.  The 144
- * outputs are Theta for 4 layers x 12 taps: (ox/hw, oy/hw, w) with hw the
- * target's half-width.
+ * Network: 64x64x1 -> 6 x [conv 3x3, stride 2, zero padding 1, + bias, ReLU]
+ * with widths 32, 64, 128, 128, 256, 256 (spatial 64 -> 1) -> FC 256->512 +
+ * ReLU -> FC 512->144.  The 144 outputs are Theta for 4 layers x 12 taps, tap t
+ * at (3t, 3t+1, 3t+2) = (o_x / hw, o_y / hw, w), hw the input's scale
+ * (disk_net_prepare_inputs).
  * Parameters: one float32 blob of disk_net_param_count() values, in the order
- * conv1.W [32][1][3][3], conv1.b [32], ..., fc2.W [144][512], fc2.b [144]
- * (PyTorch layout).  Activations and weights enter each layer rounded to BF16.
+ * conv1.W [32][1][3][3], conv1.b [32], ..., fc1.W [512][256], fc1.b [512],
+ * fc2.W [144][512], fc2.b [144] (PyTorch layout).
+ * Precision: each layer's input activations and weights are rounded to BF16
+ * (nearest even) and contracted with FP32 accumulation; hidden outputs are
+ * ReLU(z) rounded to BF16.  Backward: the bias gradient sums dL/dz in FP32;
+ * both contractions take dL/dz rounded to BF16; the gradient of the BF16
+ * weights is applied to the FP32 master weights.
+ * Limits: 1 <= B <= DISK_NET_MAX_BATCH.  All reductions run in a fixed order
+ * (results are bitwise reproducible).
  */
+#define DISK_NET_MAX_BATCH 65536
 int64_t disk_net_param_count(void);
+/* Device scratch for disk_net_train_step at batch B (also enough for
+ * disk_init_predict, which needs only disk_net_predict_workspace_size(B)). */
 size_t disk_net_workspace_size(int32_t B);
+size_t disk_net_predict_workspace_size(int32_t B);
 /*
+ * Inference.
  *   params      device float [disk_net_param_count()];
- *   targets64   device uint16 (bf16 bits) [B][64][64], peak-normalised;
- *   half_width  device float [B];   theta device float [B][48][3] (written).
+ *   targets64   device uint16 (BF16 bits) [B][64][64] (disk_net_prepare_inputs);
+ *   half_width  device float [B] (hw of each input);
+ *   theta       device float [B][48][3] (written): offsets in target pixels
+ *               (network output x hw), weights as predicted.
  */
 disk_status disk_init_predict(const float* params, const uint16_t* targets64,
                               const float* half_width, float* theta, int32_t B, void* ws,
                               size_t ws_bytes, hipStream_t stream);
 /*
- * One training step: forward, MSE against theta_ref (normalised units, [B][144]),
- * backward, Adam on the FP32 master parameters (m, v: device float, same size).
- * loss_out: device float [1] (mean squared error of this batch before the update).
+ * One training step: forward, loss = mean over B x 144 of (y_hat - y)^2 with
+ * y = theta_ref in network units (offsets / hw), backward, then Adam
+ * (beta 0.9, 0.999, eps 1e-8, bias correction at `step` >= 1, learning rate
+ * lr) on the FP32 master parameters.
+ *   params, adam_m, adam_v  device float [disk_net_param_count()], updated;
+ *   theta_ref   device float [B][48][3], offsets in target pixels;
+ *   loss_out    device float [1]: the loss before the update;
+ *   grad_out    device float [disk_net_param_count()] or NULL: the gradient.
  */
 disk_status disk_net_train_step(float* params, float* adam_m, float* adam_v, int32_t step,
-                                float lr, const uint16_t* targets64, const float* theta_ref,
-                                int32_t B, float* loss_out, void* ws, size_t ws_bytes,
-                                hipStream_t stream);
-/* Resize targets to the network input: zero-pad up to 64 or area-average down,
- * peak-normalise, round to BF16.  desc/targets as in disk_optimize_batch. */
+                                float lr, const uint16_t* targets64, const float* half_width,
+                                const float* theta_ref, int32_t B, float* loss_out,
+                                float* grad_out, void* ws, size_t ws_bytes, hipStream_t stream);
+/*
+ * Network input of every target of a batch: the M x M target (centre
+ * c = (M-1)/2) is averaged by exact pixel-area overlap onto 64 x 64 cells of
+ * side s = max(1, M/64) centred on c, divided by its maximum and rounded to
+ * BF16; half_width[b] = 32 s.  desc/targets as in disk_optimize_batch; a
+ * target whose descriptor is invalid gets a zero input and half_width 0.
+ *   targets64  device uint16 [B][64][64] (written);  half_width device float [B].
+ */
 disk_status disk_net_prepare_inputs(const disk_batch_meta* meta, const disk_target* desc,
                                     const float* targets, uint16_t* targets64,
                                     float* half_width, hipStream_t stream);
-/* Scatter the network's [B][48][3] prediction into the batch's Theta layout
- * (targets must have L = 4, 12 taps per layer). */
+/* Copy the network's [B][48][3] prediction into the batch's Theta layout
+ * (rows theta_off .. theta_off+47 of target b).  Targets that do not have
+ * L = 4 and 12 taps per layer are left untouched. */
 disk_status disk_net_scatter_theta(const disk_batch_meta* meta, const disk_target* desc,
-                                   const float* theta48, float* theta, hipStream_t stream);
+                                   const int32_t* taps, const float* theta48, float* theta,
+                                   hipStream_t stream);
 
 #ifdef __cplusplus
 }

@@ -18,7 +18,7 @@ __all__ = [
     "disk_forward", "disk_backward", "disk_sv_filter", "disk_sv_prepare", "disk_sv_apply", "Basis", "make_basis",
     "disk_optimize_batch", "disk_init_radial", "disk_fit_basis", "pack_targets", "fit_basis", "disk_init_shape", "OptParams", "Batch", "make_batch",
     "disk_init_predict", "disk_net_train_step", "disk_net_prepare_inputs", "disk_net_scatter_theta",
-    "disk_net_param_count",
+    "disk_net_param_count", "net_workspace",
 ]
 
 ZERO, CLAMP = 0, 1
@@ -86,10 +86,11 @@ def lib():
         "disk_sv_apply": (c_int32, [POINTER(DiskBasis), P, P, P, P, c_int32, c_int32, c_int32, c_int32, P, c_size_t, P]),
         "disk_net_param_count": (c_int64, []),
         "disk_net_workspace_size": (c_size_t, [c_int32]),
+        "disk_net_predict_workspace_size": (c_size_t, [c_int32]),
         "disk_init_predict": (c_int32, [P, P, P, P, c_int32, P, c_size_t, P]),
-        "disk_net_train_step": (c_int32, [P, P, P, c_int32, c_float, P, P, c_int32, P, P, c_size_t, P]),
+        "disk_net_train_step": (c_int32, [P, P, P, c_int32, c_float, P, P, P, c_int32, P, P, P, c_size_t, P]),
         "disk_net_prepare_inputs": (c_int32, [POINTER(DiskBatchMeta), P, P, P, P, P]),
-        "disk_net_scatter_theta": (c_int32, [POINTER(DiskBatchMeta), P, P, P, P]),
+        "disk_net_scatter_theta": (c_int32, [POINTER(DiskBatchMeta), P, P, P, P, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -397,18 +398,27 @@ def disk_net_param_count():
     return int(lib().disk_net_param_count())
 
 
-def disk_init_predict(params, targets64, half_width):
+def net_workspace(B, device="cuda"):
+    return _workspace(lib().disk_net_workspace_size(int(B)), device)
+
+
+def disk_init_predict(params, targets64, half_width, ws=None):
+    """Theta [B][48][3] (offsets in target pixels) for prepared inputs."""
     B = int(targets64.shape[0])
     dev = params.device
     theta = torch.empty((B, 48, 3), dtype=torch.float32, device=dev)
     L = lib()
-    ws = _workspace(L.disk_net_workspace_size(B), dev)
+    nws = L.disk_net_predict_workspace_size(B)
+    if ws is None or ws.numel() < nws:
+        ws = _workspace(nws, dev)
     _check(L.disk_init_predict(_ptr(params), _ptr(targets64), _ptr(half_width), _ptr(theta), B, _ptr(ws),
                                ws.numel(), _stream()))
     return theta
 
 
-def disk_net_train_step(params, m, v, step, lr, targets64, theta_ref, ws=None):
+def disk_net_train_step(params, m, v, step, lr, targets64, half_width, theta_ref, ws=None, grad=None):
+    """One Adam step of the initialiser on a batch; returns the loss (device
+    tensor [1], before the update).  ``grad`` (optional) receives the gradient."""
     B = int(targets64.shape[0])
     dev = params.device
     loss = torch.empty(1, dtype=torch.float32, device=dev)
@@ -417,11 +427,13 @@ def disk_net_train_step(params, m, v, step, lr, targets64, theta_ref, ws=None):
     if ws is None or ws.numel() < nws:
         ws = _workspace(nws, dev)
     _check(L.disk_net_train_step(_ptr(params), _ptr(m), _ptr(v), int(step), float(lr), _ptr(targets64),
-                                 _ptr(theta_ref), B, _ptr(loss), _ptr(ws), ws.numel(), _stream()))
+                                 _ptr(half_width), _ptr(theta_ref), B, _ptr(loss), _ptr(grad), _ptr(ws), ws.numel(),
+                                 _stream()))
     return loss
 
 
 def disk_net_prepare_inputs(batch: Batch):
+    """(targets64 int16 [B][64][64] holding BF16 bits, half_width [B])."""
     dev = batch.desc.device
     x = torch.empty((batch.B, 64, 64), dtype=torch.int16, device=dev)
     hw = torch.empty(batch.B, dtype=torch.float32, device=dev)
@@ -434,8 +446,8 @@ def disk_net_scatter_theta(batch: Batch, theta48, theta=None):
     dev = batch.desc.device
     if theta is None:
         theta = torch.empty((batch.T_total, 3), dtype=torch.float32, device=dev)
-    _check(lib().disk_net_scatter_theta(ctypes.byref(batch.meta), _ptr(batch.desc), _ptr(theta48), _ptr(theta),
-                                        _stream()))
+    _check(lib().disk_net_scatter_theta(ctypes.byref(batch.meta), _ptr(batch.desc), _ptr(batch.taps), _ptr(theta48),
+                                        _ptr(theta), _stream()))
     return theta
 
 

@@ -515,4 +515,90 @@ disk_status disk_init_radial(const disk_batch_meta* meta, const disk_target* des
     return ok();
 }
 
+// ---------------------------------------------------------------------------
+// learned initialiser
+// ---------------------------------------------------------------------------
+static disk_status check_net_batch(int32_t B) {
+    if (B < 1 || B > DISK_NET_MAX_BATCH) return fail(DISK_BAD_SHAPE, "B=%d out of [1,%d]", B, DISK_NET_MAX_BATCH);
+    return DISK_OK;
+}
+
+int64_t disk_net_param_count(void) { return net_param_count(); }
+
+size_t disk_net_workspace_size(int32_t B) {
+    if (B < 1 || B > DISK_NET_MAX_BATCH) return 0;
+    return net_ws_layout(B, true).total;
+}
+
+size_t disk_net_predict_workspace_size(int32_t B) {
+    if (B < 1 || B > DISK_NET_MAX_BATCH) return 0;
+    return net_ws_layout(B, false).total;
+}
+
+disk_status disk_init_predict(const float* params, const uint16_t* targets64, const float* half_width, float* theta,
+                              int32_t B, void* ws, size_t ws_bytes, hipStream_t stream) {
+    DISK_TRY(check_net_batch(B));
+    DISK_TRY(check_ptr(params, "params"));
+    DISK_TRY(check_ptr(targets64, "targets64"));
+    DISK_TRY(check_ptr(half_width, "half_width"));
+    DISK_TRY(check_ptr(theta, "theta"));
+    const NetWs w = net_ws_layout(B, false);
+    if (!ws || ws_bytes < w.total) return fail(DISK_WORKSPACE_TOO_SMALL, "workspace %zu < %zu bytes", ws_bytes, w.total);
+    DISK_TRY(check_ptr(ws, "ws"));
+    DISK_HIP(net_forward(params, targets64, B, static_cast<char*>(ws), w, theta, half_width, stream), "net forward");
+    return ok();
+}
+
+disk_status disk_net_train_step(float* params, float* adam_m, float* adam_v, int32_t step, float lr,
+                                const uint16_t* targets64, const float* half_width, const float* theta_ref, int32_t B,
+                                float* loss_out, float* grad_out, void* ws, size_t ws_bytes, hipStream_t stream) {
+    DISK_TRY(check_net_batch(B));
+    DISK_TRY(check_ptr(params, "params"));
+    DISK_TRY(check_ptr(adam_m, "adam_m"));
+    DISK_TRY(check_ptr(adam_v, "adam_v"));
+    DISK_TRY(check_ptr(targets64, "targets64"));
+    DISK_TRY(check_ptr(half_width, "half_width"));
+    DISK_TRY(check_ptr(theta_ref, "theta_ref"));
+    DISK_TRY(check_ptr(loss_out, "loss_out"));
+    if (grad_out) DISK_TRY(check_ptr(grad_out, "grad_out"));
+    if (params == adam_m || params == adam_v || adam_m == adam_v || (grad_out && (grad_out == params ||
+                                                                                   grad_out == adam_m ||
+                                                                                   grad_out == adam_v)))
+        return fail(DISK_INVALID_ARG, "params, adam_m, adam_v and grad_out must be distinct");
+    if (step < 1) return fail(DISK_INVALID_ARG, "step=%d must be >= 1", step);
+    if (!std::isfinite(lr) || lr < 0.0f) return fail(DISK_INVALID_ARG, "lr must be finite and >= 0");
+    const NetWs w = net_ws_layout(B, true);
+    if (!ws || ws_bytes < w.total) return fail(DISK_WORKSPACE_TOO_SMALL, "workspace %zu < %zu bytes", ws_bytes, w.total);
+    DISK_TRY(check_ptr(ws, "ws"));
+    char* base = static_cast<char*>(ws);
+    float* grad = grad_out ? grad_out : reinterpret_cast<float*>(base + w.grad);
+    DISK_HIP(net_forward(params, targets64, B, base, w, reinterpret_cast<float*>(base + w.yhat), nullptr, stream),
+             "net forward");
+    DISK_HIP(net_backward(params, targets64, theta_ref, half_width, B, base, w, grad, loss_out, stream), "net backward");
+    DISK_HIP(net_adam(params, adam_m, adam_v, grad, step, lr, stream), "net adam");
+    return ok();
+}
+
+disk_status disk_net_prepare_inputs(const disk_batch_meta* meta, const disk_target* desc, const float* targets,
+                                    uint16_t* targets64, float* half_width, hipStream_t stream) {
+    DISK_TRY(check_meta(meta));
+    DISK_TRY(check_ptr(desc, "desc"));
+    DISK_TRY(check_ptr(targets, "targets"));
+    DISK_TRY(check_ptr(targets64, "targets64"));
+    DISK_TRY(check_ptr(half_width, "half_width"));
+    DISK_HIP(net_prepare(meta->B, desc, targets, targets64, half_width, meta->max_side, stream), "net prepare");
+    return ok();
+}
+
+disk_status disk_net_scatter_theta(const disk_batch_meta* meta, const disk_target* desc, const int32_t* taps,
+                                   const float* theta48, float* theta, hipStream_t stream) {
+    DISK_TRY(check_meta(meta));
+    DISK_TRY(check_ptr(desc, "desc"));
+    DISK_TRY(check_ptr(taps, "taps"));
+    DISK_TRY(check_ptr(theta48, "theta48"));
+    DISK_TRY(check_ptr(theta, "theta"));
+    DISK_HIP(net_scatter(meta->B, desc, taps, theta48, theta, stream), "net scatter");
+    return ok();
+}
+
 }  // extern "C"

@@ -84,4 +84,21 @@ hipError_t launch_continue(const disk_target* desc, const int* taps, float* thet
 hipError_t launch_init_radial(int B, const disk_target* desc, const int* taps, const float* targets, float* theta,
                               int max_side, int max_T, hipStream_t s);
 
+// ---- learned initialiser (net.hip) ----
+struct NetWs {   // byte offsets into the caller's workspace
+    size_t wp, act, yhat, g32[2], gq[2], dcol, part, cpart, grad, total;
+};
+long net_param_count();
+NetWs net_ws_layout(int B, bool train);
+void net_wgrad_splits(int cout, int Kp, int Mred, int* S, int* kchunk);
+hipError_t net_forward(const float* params, const uint16_t* x0, int B, char* ws, const NetWs& w, float* out,
+                       const float* hw, hipStream_t s);
+hipError_t net_backward(const float* params, const uint16_t* x0, const float* ref, const float* hw, int B, char* ws,
+                        const NetWs& w, float* grad, float* loss_out, hipStream_t s);
+hipError_t net_adam(float* params, float* m, float* v, const float* grad, int step, float lr, hipStream_t s);
+hipError_t net_prepare(int B, const disk_target* desc, const float* targets, uint16_t* x64, float* hw, int max_side,
+                       hipStream_t s);
+hipError_t net_scatter(int B, const disk_target* desc, const int* taps, const float* th48, float* theta,
+                       hipStream_t s);
+
 }  // namespace disk

@@ -1,0 +1,665 @@
+// Learned initialiser: conv encoder + MLP on MFMA (gfx950), forward, backward
+// and Adam.  Every contraction is one BF16 GEMM kernel with FP32 accumulation
+// (v_mfma_f32_16x16x32_bf16), fed by operand loaders that read the matrices
+// in whichever layout they live in (row-major, column-major, or the 3x3
+// stride-2 im2col view of an NHWC activation) and stage 64 x 32 tiles in LDS.
+#include <algorithm>
+#include <cmath>
+
+#include "common.hpp"
+#include "internal.hpp"
+
+namespace disk {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+namespace {
+
+constexpr int kConvWidth[6] = {32, 64, 128, 128, 256, 256};
+constexpr int kFc0 = 512, kOut = 144, kSide = 64;
+constexpr int kBM = 64, kBN = 64, kBK = 32;
+constexpr int kLds = 40;   // LDS row stride in BF16 elements (80 B: 16-B aligned, spreads banks)
+
+__device__ __forceinline__ uint4 zero4() { return make_uint4(0u, 0u, 0u, 0u); }
+
+// ---- operand loaders ------------------------------------------------------
+// A loader describes a matrix Op(row, k).  kContig loaders return the 8
+// elements (row, k..k+7); the others return (row..row+7, k).
+struct LdRow {   // Op(r, k) = p[r * ld + k]
+    const uint16_t* p;
+    int ld, rows, K;
+    static constexpr bool kContig = true;
+    __device__ uint4 fetch(int r, int k) const {
+        if (r >= rows || k >= K) return zero4();
+        return *reinterpret_cast<const uint4*>(p + static_cast<size_t>(r) * ld + k);
+    }
+};
+
+struct LdCol {   // Op(r, k) = p[k * ld + r]
+    const uint16_t* p;
+    int ld, rows, K;
+    static constexpr bool kContig = false;
+    __device__ uint4 fetch(int r, int k) const {
+        if (r >= rows || k >= K) return zero4();
+        return *reinterpret_cast<const uint4*>(p + static_cast<size_t>(k) * ld + r);
+    }
+};
+
+// im2col of a 3x3 / stride 2 / zero-padding 1 convolution over NHWC x:
+// Op(m, k) with m = (b, oy, ox) and k = (ky * 3 + kx) * Cin + ci.
+struct Im2col {
+    const uint16_t* x;
+    int H, W, Cin, Ho, Wo, M, K;   // K = 9 Cin
+    __device__ uint4 fetch8(int m, int k) const {
+        if (m >= M || k >= K) return zero4();
+        const int hw = Ho * Wo;
+        const int b = m / hw, r = m - b * hw, oy = r / Wo, ox = r - oy * Wo;
+        if (Cin >= 8) {   // 8 channels of one tap
+            const int tap = k / Cin, ci = k - tap * Cin;
+            const int ky = tap / 3, kx = tap - 3 * ky;
+            const int iy = 2 * oy + ky - 1, ix = 2 * ox + kx - 1;
+            if (iy < 0 || iy >= H || ix < 0 || ix >= W) return zero4();
+            return *reinterpret_cast<const uint4*>(x + ((static_cast<size_t>(b) * H + iy) * W + ix) * Cin + ci);
+        }
+        // Cin == 1: 8 consecutive taps
+        uint16_t e[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int tap = k + j;
+            const int ky = tap / 3, kx = tap - 3 * ky;
+            const int iy = 2 * oy + ky - 1, ix = 2 * ox + kx - 1;
+            e[j] = (tap < 9 && iy >= 0 && iy < H && ix >= 0 && ix < W)
+                       ? x[(static_cast<size_t>(b) * H + iy) * W + ix]
+                       : static_cast<uint16_t>(0);
+        }
+        uint4 v;
+        __builtin_memcpy(&v, e, 16);
+        return v;
+    }
+};
+struct LdIm2col : Im2col {   // Op(m, k)
+    static constexpr bool kContig = true;
+    __device__ uint4 fetch(int r, int k) const { return fetch8(r, k); }
+};
+struct LdIm2colT : Im2col {  // Op(j, m) = im2col(m, j): rows j..j+7 at reduction index m
+    static constexpr bool kContig = false;
+    __device__ uint4 fetch(int r, int k) const { return fetch8(k, r); }
+};
+
+template <class LD>
+__device__ __forceinline__ uint4 tile_fetch(const LD& ld, int row0, int k0, int t) {
+    if constexpr (LD::kContig)
+        return ld.fetch(row0 + (t >> 2), k0 + (t & 3) * 8);
+    else
+        return ld.fetch(row0 + (t & 7) * 8, k0 + (t >> 3));
+}
+
+template <class LD>
+__device__ __forceinline__ void tile_store(uint16_t* S, int t, uint4 v) {
+    if constexpr (LD::kContig) {
+        *reinterpret_cast<uint4*>(S + (t >> 2) * kLds + (t & 3) * 8) = v;
+    } else {
+        uint16_t e[8];
+        __builtin_memcpy(e, &v, 16);
+        const int r = (t & 7) * 8, k = t >> 3;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) S[(r + j) * kLds + k] = e[j];
+    }
+}
+
+// ---- epilogues ------------------------------------------------------------
+struct EpAct {   // hidden layer: out = bf16(ReLU(acc + bias))
+    uint16_t* out;
+    const float* bias;
+    int ld;
+    __device__ void put(int m, int n, float acc, int) const {
+        out[static_cast<size_t>(m) * ld + n] = f32_to_bf16(fmaxf(acc + bias[n], 0.0f));
+    }
+};
+struct EpOut {   // last layer: out = acc + bias, offsets times hw[m] when hw is given
+    float* out;
+    const float* bias;
+    const float* hw;
+    int ld;
+    __device__ void put(int m, int n, float acc, int) const {
+        float v = acc + bias[n];
+        if (hw && (n % 3) < 2) v *= hw[m];
+        out[static_cast<size_t>(m) * ld + n] = v;
+    }
+};
+struct EpStore {  // plain FP32 store; split z writes its own M x N slab
+    float* out;
+    int ld;
+    size_t slab;
+    __device__ void put(int m, int n, float acc, int z) const {
+        out[z * slab + static_cast<size_t>(m) * ld + n] = acc;
+    }
+};
+struct EpMaskGrad {  // FC input gradient: g = acc * [x > 0], kept in FP32 and BF16
+    float* g32;
+    uint16_t* gq;
+    const uint16_t* x;
+    int ld;
+    __device__ void put(int m, int n, float acc, int) const {
+        const size_t i = static_cast<size_t>(m) * ld + n;
+        const float g = (x[i] & 0x7fffu) != 0 && !(x[i] & 0x8000u) ? acc : 0.0f;
+        g32[i] = g;
+        gq[i] = f32_to_bf16(g);
+    }
+};
+
+// C[M][N] = sum_k A(m, k) B(k, n), B given as Op(n, k).  Block: 64 x 64 tile,
+// four waves of 32 x 32 (2 x 2 MFMA blocks of 16 x 16), k-steps of 32.
+// Grid: x = M tiles, y = N tiles, z = splits of the k range (kchunk each).
+template <class LA, class LB, class EP>
+__global__ __launch_bounds__(256) void gemm_kernel(LA la, LB lb, EP ep, int M, int N, int K, int kchunk) {
+    __shared__ __attribute__((aligned(16))) uint16_t As[kBM * kLds];
+    __shared__ __attribute__((aligned(16))) uint16_t Bs[kBN * kLds];
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int wm = w >> 1, wn = w & 1;
+    const int row0 = blockIdx.x * kBM, col0 = blockIdx.y * kBN;
+    const int kb = blockIdx.z * kchunk, ke = min(K, kb + kchunk);
+    f32x4 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    uint4 va = zero4(), vb = zero4();
+    if (kb < ke) {
+        va = tile_fetch(la, row0, kb, t);
+        vb = tile_fetch(lb, col0, kb, t);
+    }
+    for (int k0 = kb; k0 < ke; k0 += kBK) {
+        __syncthreads();
+        tile_store<LA>(As, t, va);
+        tile_store<LB>(Bs, t, vb);
+        __syncthreads();
+        if (k0 + kBK < ke) {   // next tile's loads in flight during the MFMAs
+            va = tile_fetch(la, row0, k0 + kBK, t);
+            vb = tile_fetch(lb, col0, k0 + kBK, t);
+        }
+        bf16x8 af[2], bf[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+            af[i] = *reinterpret_cast<const bf16x8*>(As + (wm * 32 + i * 16 + (lane & 15)) * kLds + 8 * (lane >> 4));
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+            bf[j] = *reinterpret_cast<const bf16x8*>(Bs + (wn * 32 + j * 16 + (lane & 15)) * kLds + 8 * (lane >> 4));
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bf[j], acc[i][j], 0, 0, 0);
+    }
+    // C block (i, j): lane holds rows 4 (lane >> 4) + r, column lane & 15
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int m = row0 + wm * 32 + i * 16 + 4 * (lane >> 4) + r;
+                const int n = col0 + wn * 32 + j * 16 + (lane & 15);
+                if (m < M && n < N) ep.put(m, n, acc[i][j][r], blockIdx.z);
+            }
+}
+
+template <class LA, class LB, class EP>
+hipError_t gemm(const LA& la, const LB& lb, const EP& ep, int M, int N, int K, int splits, int kchunk,
+                hipStream_t s) {
+    const dim3 grid((M + kBM - 1) / kBM, (N + kBN - 1) / kBN, splits);
+    hipLaunchKernelGGL((gemm_kernel<LA, LB, EP>), grid, dim3(256), 0, s, la, lb, ep, M, N, K, kchunk);
+    return hipGetLastError();
+}
+
+// ---- layer table ----------------------------------------------------------
+struct Layer {
+    int conv, cin, cout, hin, hout;   // fc: hin = hout = 1
+    int K, Kp;                        // reduction length (9 cin or fin), padded to 32
+    long w_off, b_off;                // in the parameter blob
+    long wp_off;                      // in the packed BF16 weights
+    long act_in;                      // activation (layer input) offset per sample, BF16 elements; -1: the input
+};
+struct Table {
+    Layer l[8];
+    long params, packed, act_per_sample;
+};
+
+Table make_table() {
+    Table T{};
+    long off = 0, wp = 0, act = 0;
+    int cin = 1, h = kSide;
+    for (int i = 0; i < 8; ++i) {
+        Layer& L = T.l[i];
+        L.conv = i < 6;
+        L.cin = cin;
+        L.cout = i < 6 ? kConvWidth[i] : (i == 6 ? kFc0 : kOut);
+        L.hin = L.conv ? h : 1;
+        L.hout = L.conv ? (h + 1) / 2 : 1;
+        L.K = L.conv ? 9 * cin : cin;
+        L.Kp = (L.K + kBK - 1) / kBK * kBK;
+        L.w_off = off;
+        off += static_cast<long>(L.cout) * L.K;
+        L.b_off = off;
+        off += L.cout;
+        L.wp_off = wp;
+        wp += static_cast<long>(L.cout) * L.Kp;
+        if (i == 0) {
+            L.act_in = -1;
+        } else {
+            L.act_in = act;
+            act += static_cast<long>(L.hin) * L.hin * L.cin;
+        }
+        cin = L.cout;
+        h = L.hout;
+    }
+    T.params = off;
+    T.packed = wp;
+    T.act_per_sample = act;
+    return T;
+}
+
+const Table& table() {
+    static const Table T = make_table();
+    return T;
+}
+
+// ---- small kernels ----------------------------------------------------------
+struct PackArgs {
+    Layer l[8];
+};
+
+// FP32 master weights (PyTorch layout) -> BF16, K-contiguous with conv taps
+// ordered (ky, kx, ci), rows padded with zeros to Kp.
+__global__ __launch_bounds__(256) void pack_kernel(PackArgs a, const float* __restrict__ params,
+                                                   uint16_t* __restrict__ wp, long total) {
+    for (long i = blockIdx.x * 256L + threadIdx.x; i < total; i += static_cast<long>(gridDim.x) * 256) {
+        int li = 0;
+        while (li < 7 && i >= a.l[li + 1].wp_off) ++li;
+        const Layer& L = a.l[li];
+        const long e = i - L.wp_off;
+        const int co = static_cast<int>(e / L.Kp), k = static_cast<int>(e - static_cast<long>(co) * L.Kp);
+        float v = 0.0f;
+        if (k < L.K) {
+            if (L.conv) {
+                const int tap = k / L.cin, ci = k - tap * L.cin;
+                v = params[L.w_off + (static_cast<long>(co) * L.cin + ci) * 9 + tap];
+            } else {
+                v = params[L.w_off + static_cast<long>(co) * L.K + k];
+            }
+        }
+        wp[i] = f32_to_bf16(v);
+    }
+}
+
+// Loss (before the update) and dL/dy_hat = 2 (y_hat - y) / (B 144), y the
+// reference in network units.  One work-group, fixed summation order.
+__global__ __launch_bounds__(1024) void loss_kernel(int B, const float* __restrict__ yhat,
+                                                    const float* __restrict__ ref, const float* __restrict__ hw,
+                                                    float* __restrict__ g32, uint16_t* __restrict__ gq,
+                                                    float* __restrict__ loss_out) {
+    __shared__ float red[16];
+    const long n = static_cast<long>(B) * kOut;
+    const float fn = static_cast<float>(n);
+    float s = 0.0f;
+    for (long i = threadIdx.x; i < n; i += 1024) {
+        const int b = static_cast<int>(i / kOut), c = static_cast<int>(i - static_cast<long>(b) * kOut);
+        const float y = (c % 3) < 2 ? ref[i] / hw[b] : ref[i];
+        const float d = yhat[i] - y;
+        s += d * d;
+        const float g = (2.0f * d) / fn;   // correctly rounded: exact whenever 2d/n is representable
+        g32[i] = g;
+        gq[i] = f32_to_bf16(g);
+    }
+    s = wave_sum(s);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        float t = 0.0f;
+        for (int i = 0; i < 16; ++i) t += red[i];
+        loss_out[0] = t / fn;
+    }
+}
+
+// Column sums of g [M][N] (FP32): stage 1 writes part[blk][N] for 256-row
+// slabs, stage 2 adds the slabs in order.
+constexpr int kColRows = 256;
+__global__ __launch_bounds__(256) void colsum_part_kernel(const float* __restrict__ g, int M, int N,
+                                                          float* __restrict__ part) {
+    const int r0 = blockIdx.x * kColRows, r1 = min(M, r0 + kColRows);
+    for (int n = threadIdx.x; n < N; n += 256) {
+        float s = 0.0f;
+        for (int r = r0; r < r1; ++r) s += g[static_cast<size_t>(r) * N + n];
+        part[static_cast<size_t>(blockIdx.x) * N + n] = s;
+    }
+}
+__global__ __launch_bounds__(256) void colsum_final_kernel(const float* __restrict__ part, int nblk, int N,
+                                                           float* __restrict__ out) {
+    const int n = blockIdx.x * 256 + threadIdx.x;
+    if (n >= N) return;
+    float s = 0.0f;
+    for (int b = 0; b < nblk; ++b) s += part[static_cast<size_t>(b) * N + n];
+    out[n] = s;
+}
+
+// Sum the split-K slabs of a weight gradient [S][cout][Kp] into the blob's
+// PyTorch layout.
+__global__ __launch_bounds__(256) void wgrad_reduce_kernel(Layer L, const float* __restrict__ part, int S,
+                                                           float* __restrict__ grad) {
+    const long n = static_cast<long>(L.cout) * L.K;
+    const size_t slab = static_cast<size_t>(L.cout) * L.Kp;
+    for (long i = blockIdx.x * 256L + threadIdx.x; i < n; i += static_cast<long>(gridDim.x) * 256) {
+        int co, k;
+        if (L.conv) {   // i = (co, ci, tap) in the blob; packed column k = tap * cin + ci
+            co = static_cast<int>(i / L.K);
+            const int rem = static_cast<int>(i - static_cast<long>(co) * L.K);
+            const int ci = rem / 9, tap = rem - 9 * ci;
+            k = tap * L.cin + ci;
+        } else {
+            co = static_cast<int>(i / L.K);
+            k = static_cast<int>(i - static_cast<long>(co) * L.K);
+        }
+        float s = 0.0f;
+        for (int z = 0; z < S; ++z) s += part[z * slab + static_cast<size_t>(co) * L.Kp + k];
+        grad[L.w_off + i] = s;
+    }
+}
+
+// Conv input gradient: transpose of im2col over dcol [M][Kp], times [x > 0].
+__global__ __launch_bounds__(256) void col2im_kernel(Layer L, int B, const float* __restrict__ dcol,
+                                                     const uint16_t* __restrict__ x, float* __restrict__ g32,
+                                                     uint16_t* __restrict__ gq) {
+    const long n = static_cast<long>(B) * L.hin * L.hin * L.cin;
+    for (long i = blockIdx.x * 256L + threadIdx.x; i < n; i += static_cast<long>(gridDim.x) * 256) {
+        const int ci = static_cast<int>(i % L.cin);
+        const long p = i / L.cin;
+        const int ix = static_cast<int>(p % L.hin);
+        const long q = p / L.hin;
+        const int iy = static_cast<int>(q % L.hin);
+        const int b = static_cast<int>(q / L.hin);
+        float s = 0.0f;
+        for (int ky = 0; ky < 3; ++ky) {
+            const int ty = iy + 1 - ky;
+            if (ty < 0 || (ty & 1)) continue;
+            const int oy = ty >> 1;
+            if (oy >= L.hout) continue;
+            for (int kx = 0; kx < 3; ++kx) {
+                const int tx = ix + 1 - kx;
+                if (tx < 0 || (tx & 1)) continue;
+                const int ox = tx >> 1;
+                if (ox >= L.hout) continue;
+                const long m = (static_cast<long>(b) * L.hout + oy) * L.hout + ox;
+                s += dcol[m * L.Kp + (ky * 3 + kx) * L.cin + ci];
+            }
+        }
+        const uint16_t xv = x[i];
+        const float g = ((xv & 0x7fffu) != 0 && !(xv & 0x8000u)) ? s : 0.0f;
+        g32[i] = g;
+        gq[i] = f32_to_bf16(g);
+    }
+}
+
+__global__ __launch_bounds__(256) void adam_kernel(long n, float* __restrict__ p, float* __restrict__ m,
+                                                   float* __restrict__ v, const float* __restrict__ g, float lr,
+                                                   float bc1, float bc2) {
+    for (long i = blockIdx.x * 256L + threadIdx.x; i < n; i += static_cast<long>(gridDim.x) * 256) {
+        const float gi = g[i];
+        const float mi = fmaf(0.9f, m[i], 0.1f * gi);
+        const float vi = fmaf(0.999f, v[i], 0.001f * gi * gi);
+        m[i] = mi;
+        v[i] = vi;
+        p[i] -= lr * (mi / bc1) / (sqrtf(vi / bc2) + 1e-8f);
+    }
+}
+
+// Network input of one target per work-group (exact area overlap onto 64 x 64
+// cells of side s centred on the target's centre, peak-normalised, BF16).
+__global__ __launch_bounds__(256) void prepare_kernel(int B, const disk_target* __restrict__ desc,
+                                                      const float* __restrict__ targets, uint16_t* __restrict__ x64,
+                                                      float* __restrict__ hw, int max_side) {
+    __shared__ float red[4];
+    const int tid = threadIdx.x;
+    for (int b = blockIdx.x; b < B; b += gridDim.x) {
+        const disk_target d = desc[b];
+        const int M = d.side;
+        uint16_t* out = x64 + static_cast<size_t>(b) * kSide * kSide;
+        if (M < 1 || (M & 1) == 0 || M > max_side || d.target_off < 0) {
+            for (int i = tid; i < kSide * kSide; i += 256) out[i] = 0;
+            if (tid == 0) hw[b] = 0.0f;
+            continue;
+        }
+        const float* K = targets + d.target_off;
+        const float s = fmaxf(1.0f, static_cast<float>(M) / kSide);
+        const float c = 0.5f * static_cast<float>(M - 1);
+        const float inv_s2 = 1.0f / (s * s);
+        float val[16];
+        float mx = 0.0f;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int idx = tid + 256 * q, i = idx >> 6, j = idx & 63;
+            const float lo_y = c + static_cast<float>(i - 32) * s, hi_y = lo_y + s;
+            const float lo_x = c + static_cast<float>(j - 32) * s, hi_x = lo_x + s;
+            const int y0 = max(0, static_cast<int>(floorf(lo_y + 0.5f))), y1 = min(M - 1, static_cast<int>(floorf(hi_y + 0.5f)));
+            const int x0 = max(0, static_cast<int>(floorf(lo_x + 0.5f))), x1 = min(M - 1, static_cast<int>(floorf(hi_x + 0.5f)));
+            float acc = 0.0f;
+            for (int y = y0; y <= y1; ++y) {
+                const float wy = fminf(hi_y, y + 0.5f) - fmaxf(lo_y, y - 0.5f);
+                if (wy <= 0.0f) continue;
+                float row = 0.0f;
+                for (int x = x0; x <= x1; ++x) {
+                    const float wx = fminf(hi_x, x + 0.5f) - fmaxf(lo_x, x - 0.5f);
+                    if (wx > 0.0f) row += wx * K[y * M + x];
+                }
+                acc += wy * row;
+            }
+            val[q] = acc * inv_s2;
+            mx = fmaxf(mx, val[q]);
+        }
+        mx = wave_max(mx);
+        __syncthreads();
+        if ((tid & 63) == 0) red[tid >> 6] = mx;
+        __syncthreads();
+        const float pk = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+#pragma unroll
+        for (int q = 0; q < 16; ++q) out[tid + 256 * q] = f32_to_bf16(pk > 0.0f ? val[q] / pk : 0.0f);
+        if (tid == 0) hw[b] = 0.5f * kSide * s;
+    }
+}
+
+__global__ __launch_bounds__(64) void scatter_kernel(int B, const disk_target* __restrict__ desc,
+                                                     const int* __restrict__ taps, const float* __restrict__ th48,
+                                                     float* __restrict__ theta) {
+    const int b = blockIdx.x;
+    if (b >= B) return;
+    const disk_target d = desc[b];
+    if (d.L != 4 || d.taps_off < 0 || d.theta_off < 0) return;
+    for (int l = 0; l < 4; ++l)
+        if (taps[d.taps_off + l] != 12) return;
+    for (int i = threadIdx.x; i < kOut; i += 64)
+        theta[3 * static_cast<size_t>(d.theta_off) + i] = th48[static_cast<size_t>(b) * kOut + i];
+}
+
+int grid_for(long n) { return static_cast<int>(std::min<long>((n + 255) / 256, 8192)); }
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+long net_param_count() { return table().params; }
+
+// Workspace layout (offsets in bytes, 256-aligned), for batch B.
+NetWs net_ws_layout(int B, bool train) {
+    const Table& T = table();
+    NetWs w{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        off = (off + 255) & ~size_t(255);
+        const size_t o = off;
+        off += bytes;
+        return o;
+    };
+    w.wp = take(T.packed * 2);
+    w.act = take(static_cast<size_t>(B) * T.act_per_sample * 2);
+    w.yhat = take(static_cast<size_t>(B) * kOut * 4);
+    if (!train) {
+        w.total = take(0);
+        return w;
+    }
+    // gradient buffers: the largest layer output (layer 1: 32 x 32 x 32 per sample)
+    size_t gmax = 0, dcol = 0, part = 0, cpart = 0;
+    for (int i = 0; i < 8; ++i) {
+        const Layer& L = T.l[i];
+        const size_t M = static_cast<size_t>(B) * L.hout * L.hout;
+        gmax = std::max(gmax, M * L.cout);
+        if (i > 0 && L.conv) dcol = std::max(dcol, M * L.Kp);
+        int S, kc;
+        net_wgrad_splits(L.cout, L.Kp, static_cast<int>(M), &S, &kc);
+        part = std::max(part, static_cast<size_t>(S) * L.cout * L.Kp);
+        cpart = std::max(cpart, ((M + kColRows - 1) / kColRows) * L.cout);
+    }
+    w.g32[0] = take(gmax * 4);
+    w.g32[1] = take(gmax * 4);
+    w.gq[0] = take(gmax * 2);
+    w.gq[1] = take(gmax * 2);
+    w.dcol = take(dcol * 4);
+    w.part = take(part * 4);
+    w.cpart = take(cpart * 4);
+    w.grad = take(T.params * 4);
+    w.total = take(0);
+    return w;
+}
+
+void net_wgrad_splits(int cout, int Kp, int Mred, int* S, int* kchunk) {
+    const int tiles = ((cout + kBM - 1) / kBM) * ((Kp + kBN - 1) / kBN);
+    int s = std::max(1, 512 / tiles);
+    const int steps = (Mred + kBK - 1) / kBK;
+    s = std::min(s, steps);
+    const int per = (steps + s - 1) / s;
+    *kchunk = per * kBK;
+    *S = (Mred + *kchunk - 1) / *kchunk;
+}
+
+static uint16_t* act_ptr(char* ws, const NetWs& w, int B, const Layer& L, const uint16_t* x0) {
+    if (L.act_in < 0) return const_cast<uint16_t*>(x0);
+    return reinterpret_cast<uint16_t*>(ws + w.act) + static_cast<size_t>(B) * L.act_in;
+}
+
+hipError_t net_forward(const float* params, const uint16_t* x0, int B, char* ws, const NetWs& w,
+                       float* out, const float* hw, hipStream_t s) {
+    const Table& T = table();
+    PackArgs pa;
+    for (int i = 0; i < 8; ++i) pa.l[i] = T.l[i];
+    uint16_t* wp = reinterpret_cast<uint16_t*>(ws + w.wp);
+    hipLaunchKernelGGL(pack_kernel, dim3(grid_for(T.packed)), dim3(256), 0, s, pa, params, wp, T.packed);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    for (int i = 0; i < 8; ++i) {
+        const Layer& L = T.l[i];
+        const uint16_t* xin = act_ptr(ws, w, B, L, x0);
+        const int M = B * L.hout * L.hout;
+        const float* bias = params + L.b_off;
+        LdRow wb{wp + L.wp_off, L.Kp, L.cout, L.Kp};
+        if (i < 7) {
+            EpAct ep{act_ptr(ws, w, B, T.l[i + 1], x0), bias, L.cout};
+            if (L.conv) {
+                LdIm2col a;
+                a.x = xin; a.H = L.hin; a.W = L.hin; a.Cin = L.cin; a.Ho = L.hout; a.Wo = L.hout; a.M = M; a.K = L.K;
+                e = gemm(a, wb, ep, M, L.cout, L.Kp, 1, L.Kp, s);
+            } else {
+                LdRow a{xin, L.K, M, L.K};
+                e = gemm(a, wb, ep, M, L.cout, L.Kp, 1, L.Kp, s);
+            }
+        } else {
+            LdRow a{xin, L.K, M, L.K};
+            EpOut ep{out, bias, hw, kOut};
+            e = gemm(a, wb, ep, M, L.cout, L.Kp, 1, L.Kp, s);
+        }
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t net_backward(const float* params, const uint16_t* x0, const float* ref, const float* hw, int B, char* ws,
+                        const NetWs& w, float* grad, float* loss_out, hipStream_t s) {
+    const Table& T = table();
+    const uint16_t* wp = reinterpret_cast<const uint16_t*>(ws + w.wp);
+    const float* yhat = reinterpret_cast<const float*>(ws + w.yhat);
+    float* g32[2] = {reinterpret_cast<float*>(ws + w.g32[0]), reinterpret_cast<float*>(ws + w.g32[1])};
+    uint16_t* gq[2] = {reinterpret_cast<uint16_t*>(ws + w.gq[0]), reinterpret_cast<uint16_t*>(ws + w.gq[1])};
+    float* dcol = reinterpret_cast<float*>(ws + w.dcol);
+    float* part = reinterpret_cast<float*>(ws + w.part);
+    float* cpart = reinterpret_cast<float*>(ws + w.cpart);
+    hipLaunchKernelGGL(loss_kernel, dim3(1), dim3(1024), 0, s, B, yhat, ref, hw, g32[0], gq[0], loss_out);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    int cur = 0;
+    for (int i = 7; i >= 0; --i) {
+        const Layer& L = T.l[i];
+        const int M = B * L.hout * L.hout;
+        const uint16_t* xin = act_ptr(ws, w, B, L, x0);
+        // bias gradient: column sums of g (FP32)
+        const int nblk = (M + kColRows - 1) / kColRows;
+        hipLaunchKernelGGL(colsum_part_kernel, dim3(nblk), dim3(256), 0, s, g32[cur], M, L.cout, cpart);
+        hipLaunchKernelGGL(colsum_final_kernel, dim3((L.cout + 255) / 256), dim3(256), 0, s, cpart, nblk, L.cout,
+                           grad + L.b_off);
+        // weight gradient: dW(co, j) = sum_m g(m, co) x_col(m, j), split over m
+        int S, kc;
+        net_wgrad_splits(L.cout, L.Kp, M, &S, &kc);
+        LdCol ga{gq[cur], L.cout, L.cout, M};
+        EpStore ps{part, L.Kp, static_cast<size_t>(L.cout) * L.Kp};
+        if (L.conv) {
+            LdIm2colT xb;
+            xb.x = xin; xb.H = L.hin; xb.W = L.hin; xb.Cin = L.cin; xb.Ho = L.hout; xb.Wo = L.hout; xb.M = M; xb.K = L.K;
+            e = gemm(ga, xb, ps, L.cout, L.Kp, M, S, kc, s);
+        } else {
+            LdCol xb{xin, L.K, L.K, M};
+            e = gemm(ga, xb, ps, L.cout, L.Kp, M, S, kc, s);
+        }
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(wgrad_reduce_kernel, dim3(grid_for(static_cast<long>(L.cout) * L.K)), dim3(256), 0, s, L,
+                           part, S, grad);
+        if (i == 0) break;
+        // input gradient, masked by the layer input's ReLU, into the other buffer
+        const int nxt = cur ^ 1;
+        LdRow gr{gq[cur], L.cout, M, L.cout};
+        LdCol wc{wp + L.wp_off, L.Kp, L.Kp, L.cout};
+        if (L.conv) {
+            EpStore dc{dcol, L.Kp, 0};
+            e = gemm(gr, wc, dc, M, L.Kp, L.cout, 1, L.cout, s);
+            if (e != hipSuccess) return e;
+            const long n = static_cast<long>(B) * L.hin * L.hin * L.cin;
+            hipLaunchKernelGGL(col2im_kernel, dim3(grid_for(n)), dim3(256), 0, s, L, B, dcol, xin, g32[nxt], gq[nxt]);
+        } else {
+            EpMaskGrad ep{g32[nxt], gq[nxt], xin, L.K};
+            e = gemm(gr, wc, ep, M, L.K, L.cout, 1, L.cout, s);
+        }
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        cur = nxt;
+    }
+    return hipGetLastError();
+}
+
+hipError_t net_adam(float* params, float* m, float* v, const float* grad, int step, float lr, hipStream_t s) {
+    const long n = table().params;
+    const float bc1 = static_cast<float>(1.0 - std::pow(0.9, step));
+    const float bc2 = static_cast<float>(1.0 - std::pow(0.999, step));
+    hipLaunchKernelGGL(adam_kernel, dim3(grid_for(n)), dim3(256), 0, s, n, params, m, v, grad, lr, bc1, bc2);
+    return hipGetLastError();
+}
+
+hipError_t net_prepare(int B, const disk_target* desc, const float* targets, uint16_t* x64, float* hw, int max_side,
+                       hipStream_t s) {
+    hipLaunchKernelGGL(prepare_kernel, dim3(std::min(B, 8192)), dim3(256), 0, s, B, desc, targets, x64, hw, max_side);
+    return hipGetLastError();
+}
+
+hipError_t net_scatter(int B, const disk_target* desc, const int* taps, const float* th48, float* theta,
+                       hipStream_t s) {
+    hipLaunchKernelGGL(scatter_kernel, dim3(B), dim3(64), 0, s, B, desc, taps, th48, theta);
+    return hipGetLastError();
+}
+
+}  // namespace disk

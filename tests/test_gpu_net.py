@@ -1,0 +1,226 @@
+"""GPU parity of the learned initialiser (conv encoder + MLP on MFMA) against
+the FP64 oracle evaluated on the same BF16-rounded operands (oracle/net.py),
+through the C ABI: input preparation, inference, one training step
+(loss, gradient, Adam) and the scatter into a batch's Theta layout."""
+import numpy as np
+import pytest
+import torch
+
+import paper_2512_04556_amd as disk
+from oracle import net as N
+from synth import mixed_batch, pack_targets
+from tests.gpu_util import say
+
+pytestmark = pytest.mark.gpu
+
+
+def _bf16_bits(x):
+    """float array -> (int16 BF16 bits as a torch tensor, the BF16 values as float64)."""
+    t = torch.as_tensor(np.asarray(x, np.float32)).to(torch.bfloat16)
+    return t.view(torch.int16).contiguous(), t.to(torch.float64).numpy()
+
+
+def _params(seed):
+    p = N.init_params(seed) + 0.01 * np.random.default_rng(seed + 1).standard_normal(N.param_count())
+    return p.astype(np.float32)
+
+
+def _bf16_ulp(v):
+    a = np.maximum(np.abs(v), 2.0 ** -126)
+    return 2.0 ** (np.floor(np.log2(a)) - 7)
+
+
+def test_prepare_inputs_matches_area_resampling(dev):
+    batch = mixed_batch(48, seed=21, side=(15, 127))
+    desc, taps, tg = pack_targets(batch)
+    bt = disk.make_batch(desc, taps, tg)
+    say("net prepare", batch.B)
+    x, hw = disk.disk_net_prepare_inputs(bt)
+    got = x.cpu().view(torch.bfloat16).to(torch.float64).numpy()
+    hw = hw.cpu().numpy()
+    worst = 0.0
+    for b in range(batch.B):
+        want, whw = N.prepare_input(batch.kernels[b].astype(np.float64))
+        assert hw[b] == whw, (b, hw[b], whw)
+        # both round to BF16 from their own sums: at most one BF16 step apart
+        d = np.abs(got[b] - want) / _bf16_ulp(want)
+        worst = max(worst, float(d.max()))
+        assert d.max() <= 1.0, (b, batch.kernels[b].shape[0], d.max())
+    print(f"prepare: worst difference {worst:.2f} BF16 steps")
+
+
+def test_prepare_inputs_invalid_descriptor(dev):
+    batch = mixed_batch(4, seed=22, side=(15, 31))
+    desc, taps, tg = pack_targets(batch)
+    desc = desc.copy()
+    desc[2, 0] = 20           # even side
+    bt = disk.make_batch(desc, taps, tg)
+    bt.meta.max_side = 31
+    x, hw = disk.disk_net_prepare_inputs(bt)
+    assert float(hw[2]) == 0.0 and int(x[2].abs().sum()) == 0
+    assert float(hw[1]) == 32.0
+
+
+@pytest.mark.parametrize("B", [1, 70])
+def test_predict_matches_oracle(dev, B):
+    rng = np.random.default_rng(30 + B)
+    bits, xval = _bf16_bits(rng.uniform(0, 1, (B, 64, 64)) ** 3)
+    hw = rng.uniform(32, 64, B).astype(np.float32)
+    p = _params(3)
+    say("net predict", B)
+    th = disk.disk_init_predict(torch.as_tensor(p).cuda(), bits.cuda(), torch.as_tensor(hw).cuda())
+    got = th.cpu().numpy().astype(np.float64)
+    y, _ = N.forward(p.astype(np.float64), xval)
+    want = np.stack([N.theta_of(y[b], float(hw[b])) for b in range(B)])
+    # Per sample, relative to that sample's largest |theta|.  Both sides round
+    # each hidden activation to BF16 from their own FP32 / FP64 sums; where a
+    # sum lies within its accumulation error of a BF16 rounding boundary the two
+    # roundings differ by one BF16 step (2^-8 relative), which then propagates.
+    # Samples without such a split agree to accumulation error.
+    err = np.abs(got - want).reshape(B, -1).max(axis=1) / np.abs(want).reshape(B, -1).max(axis=1)
+    print(f"predict B={B}: per-sample max err median {np.median(err):.2e}, max {err.max():.2e}, "
+          f"samples above 1e-5: {int(np.sum(err > 1e-5))}")
+    assert np.median(err) <= 1e-5
+    assert err.max() <= 1e-2
+
+
+def test_train_step_matches_oracle(dev):
+    B = 37
+    rng = np.random.default_rng(40)
+    bits, xval = _bf16_bits(rng.uniform(0, 1, (B, 64, 64)) ** 2)
+    hw = rng.uniform(32, 64, B).astype(np.float32)
+    ref = (rng.standard_normal((B, 48, 3)) * [8.0, 8.0, 0.05] + [0, 0, 0.08]).astype(np.float32)
+    p0 = _params(5)
+    P = p0.size
+    prm = torch.as_tensor(p0).cuda()
+    m = torch.zeros(P, device="cuda")
+    v = torch.zeros(P, device="cuda")
+    g = torch.empty(P, device="cuda")
+    lr = 1e-3
+    say("net train step", B)
+    loss = disk.disk_net_train_step(prm, m, v, 1, lr, bits.cuda(), torch.as_tensor(hw).cuda(),
+                                    torch.as_tensor(ref).cuda(), grad=g)
+    torch.cuda.synchronize()
+    # oracle: same operands, labels in network units
+    y = np.stack([N.label(ref[b].astype(np.float64), float(hw[b])) for b in range(B)])
+    yh, cache = N.forward(p0.astype(np.float64), xval)
+    want_loss = N.loss(yh, y)
+    want_g = N.backward(p0.astype(np.float64), cache, yh, y)
+    got_g = g.cpu().numpy().astype(np.float64)
+    assert abs(float(loss) - want_loss) <= 1e-4 * want_loss, (float(loss), want_loss)
+    o = 0
+    worst = 0.0
+    for ws, bs in N.param_shapes():
+        for sh in (ws, bs):
+            n = int(np.prod(sh))
+            e = np.abs(got_g[o:o + n] - want_g[o:o + n]).max() / np.abs(want_g[o:o + n]).max()
+            worst = max(worst, e)
+            assert e <= 3e-2, (sh, e)
+            o += n
+    print(f"train step: loss {float(loss):.6e} vs {want_loss:.6e}; worst per-tensor grad err {worst:.2e}")
+    # Adam (step 1) from the oracle's gradient: the update is -lr g / (|g| + eps);
+    # entries whose gradient is tiny may differ in sign, by at most 2 lr
+    want_p, _, _ = N.adam(p0.astype(np.float64), want_g, np.zeros(P), np.zeros(P), 1, lr)
+    dp = np.abs(prm.cpu().numpy() - want_p)
+    assert dp.max() <= 2 * lr * 1.001
+    assert np.mean(dp > 0.05 * lr) < 2e-3, np.mean(dp > 0.05 * lr)
+
+
+def _exact_params(seed):
+    """Weights in {-1, 0, 1} (about three non-zeros per output), integer
+    biases: with integer inputs every sum below is an exactly representable
+    integer (or quarter-integer in the backward pass), so FP32 accumulation in
+    any order equals the FP64 value and every BF16 rounding decision agrees."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for ws, bs in N.param_shapes():
+        K = int(np.prod(ws[1:]))
+        d = min(1.0, 3.0 / K)
+        out.append(rng.choice([-1.0, 0.0, 1.0], size=ws, p=[d / 2, 1 - d, d / 2]))
+        out.append(rng.integers(-1, 3, size=bs).astype(np.float64))
+    return np.concatenate([o.reshape(-1) for o in out]).astype(np.float32)
+
+
+def _exact_inputs(B, seed):
+    return np.random.default_rng(seed).integers(0, 16, (B, 64, 64)).astype(np.float32)
+
+
+def test_predict_exact_integer_network_bitwise(dev):
+    """Integer-valued network (exact arithmetic on both sides): the GPU output
+    equals the oracle's bit for bit; hw = 32 keeps the offset scaling exact."""
+    B = 67
+    p = _exact_params(50)
+    x = _exact_inputs(B, 51)
+    bits, xval = _bf16_bits(x)
+    assert np.array_equal(xval, x)
+    yo, cache = N.forward(p.astype(np.float64), xval)
+    zmax = max(np.abs(a).max() for a in cache["inputs"])
+    assert zmax < 2 ** 20 and np.abs(yo).max() < 2 ** 20      # precondition: exact in FP32
+    say("net predict exact", B)
+    th = disk.disk_init_predict(torch.as_tensor(p).cuda(), bits.cuda(), torch.full((B,), 32.0, device="cuda"))
+    want = np.stack([N.theta_of(yo[b], 32.0) for b in range(B)])
+    np.testing.assert_array_equal(th.cpu().numpy().astype(np.float64), want)
+
+
+def test_train_step_exact_integer_network_bitwise(dev):
+    """Same integer network; labels chosen (from the oracle's own forward) so
+    that dL/dy_hat = r / 4 with small integers r: loss gradient, every weight
+    and bias gradient match the oracle bit for bit, and the Adam update agrees
+    to FP32 rounding."""
+    B = 37
+    n = B * 144
+    p = _exact_params(52)
+    x = _exact_inputs(B, 53)
+    bits, xval = _bf16_bits(x)
+    yo, cache = N.forward(p.astype(np.float64), xval)
+    r = np.random.default_rng(54).integers(-8, 9, (B, 144)).astype(np.float64)
+    y = yo - r * n / 8.0                                       # 2 (y_hat - y) / n = r / 4
+    ref = y.reshape(B, 48, 3).copy()
+    ref[:, :, :2] *= 32.0
+    assert np.array_equal(ref.astype(np.float32).astype(np.float64), ref)
+    want_g = N.backward(p.astype(np.float64), cache, yo, y)
+    assert np.array_equal(want_g.astype(np.float32).astype(np.float64), want_g)
+    P = p.size
+    prm = torch.as_tensor(p).cuda()
+    m = torch.zeros(P, device="cuda")
+    v = torch.zeros(P, device="cuda")
+    g = torch.empty(P, device="cuda")
+    say("net train exact", B)
+    loss = disk.disk_net_train_step(prm, m, v, 1, 1e-3, bits.cuda(), torch.full((B,), 32.0, device="cuda"),
+                                    torch.as_tensor(ref.astype(np.float32)).cuda(), grad=g)
+    np.testing.assert_array_equal(g.cpu().numpy().astype(np.float64), want_g)
+    assert abs(float(loss) - N.loss(yo, y)) <= 1e-5 * N.loss(yo, y)
+    want_p, want_m, want_v = N.adam(p.astype(np.float64), want_g, np.zeros(P), np.zeros(P), 1, 1e-3)
+    np.testing.assert_allclose(prm.cpu().numpy(), want_p, rtol=0, atol=1e-3 * 1e-5 + 1e-7 * np.abs(want_p).max())
+    np.testing.assert_allclose(m.cpu().numpy(), want_m, rtol=1e-6, atol=0)
+
+
+def test_train_step_is_deterministic(dev):
+    B = 16
+    rng = np.random.default_rng(41)
+    bits, _ = _bf16_bits(rng.uniform(0, 1, (B, 64, 64)))
+    hw = torch.full((B,), 40.0, device="cuda")
+    ref = torch.as_tensor(rng.standard_normal((B, 48, 3)).astype(np.float32)).cuda()
+    outs = []
+    for _ in range(2):
+        prm = torch.as_tensor(_params(7)).cuda()
+        m = torch.zeros_like(prm)
+        v = torch.zeros_like(prm)
+        for s in range(1, 4):
+            disk.disk_net_train_step(prm, m, v, s, 1e-3, bits.cuda(), hw, ref)
+        outs.append(prm.cpu().numpy())
+    np.testing.assert_array_equal(outs[0], outs[1])
+
+
+def test_scatter_theta(dev):
+    batch = mixed_batch(6, seed=23, side=(15, 31), fixed_L=4, fixed_N=12)
+    desc, taps, tg = pack_targets(batch)
+    desc = desc.copy()
+    bt = disk.make_batch(desc, taps, tg)
+    th48 = torch.arange(6 * 144, dtype=torch.float32, device="cuda").view(6, 48, 3)
+    theta = torch.full((bt.T_total, 3), -1.0, device="cuda")
+    disk.disk_net_scatter_theta(bt, th48, theta)
+    got = theta.cpu().numpy()
+    for b in range(6):
+        o = int(desc[b, 3])
+        np.testing.assert_array_equal(got[o:o + 48], th48[b].cpu().numpy())
