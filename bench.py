@@ -33,6 +33,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--basis", choices=["fitted", "random"], default="fitted")
+    ap.add_argument("--no-time-to-40db", action="store_true")
     return ap.parse_args()
 
 
@@ -69,6 +70,59 @@ def cpu_baseline(basis_np, img, P):
     dt = time.perf_counter() - t
     return {"value": H * W / dt / 1e6, "unit": "Mpix/s", "cores": 1, "kind": "oracle",
             "sample": f"the full frame ({H}x{W}x{C}), 4 passes, FP64 numpy, {dt:.1f} s single-threaded"}
+
+
+def time_to_40db(torch, disk, n=4096):
+    """Batched optimisation of n fresh targets (odd sides 15..127, the shape
+    families of the batching workload, 4 layers x 12 taps, seed 7) to 40 dB or
+    1000 Adam steps, from the radial initialisation and from the learned one
+    (its inference included).  Times come from the device clock stamped at
+    each target's finish, plus the initialisation time."""
+    from synth import mixed_batch, pack_targets
+    from paper_2512_04556_amd import train_init
+    b = mixed_batch(n, seed=7, fixed_L=4, fixed_N=12)
+    bt = disk.make_batch(*pack_targets(b))
+    prm = disk.OptParams(max_steps=1000, lr0=1e-2, lr1=1e-3, psnr_stop_db=40.0)
+    rate = disk.clock_rate_khz() * 1e3
+    res = {"targets": n, "max_steps": 1000, "stop_db": 40.0}
+    try:
+        weights = train_init.load()
+    except (OSError, ValueError) as e:
+        weights = None
+        res["learned_missing"] = str(e)
+    for kind in ("radial", "learned"):
+        if kind == "learned" and weights is None:
+            continue
+        stream = torch.cuda.current_stream()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ticks = torch.zeros(n + 1, dtype=torch.int64, device="cuda")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        e0.record(stream)
+        if kind == "radial":
+            th = disk.disk_init_radial(bt)
+        else:
+            x, hw = disk.disk_net_prepare_inputs(bt)
+            th = disk.disk_net_scatter_theta(bt, disk.disk_init_predict(weights, x, hw))
+        e1.record(stream)
+        ps, st, status = disk.disk_optimize_batch(bt, th, prm, ticks)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        init_s = e0.elapsed_time(e1) * 1e-3
+        tk = ticks.cpu().numpy()
+        fin = init_s + (tk[:n] - tk[n]) / rate
+        ps, st = ps.cpu().numpy(), st.cpu().numpy()
+        ok = np.sort(fin[ps >= 40.0])
+
+        def t_frac(f):
+            k = int(np.ceil(f * n))
+            return round(float(ok[k - 1]), 4) if len(ok) >= k else None
+
+        res[kind] = {"wall_s": round(wall, 3), "init_ms": round(init_s * 1e3, 3),
+                     "reached_40db": int(np.sum(ps >= 40.0)), "median_steps": float(np.median(st)),
+                     "t50_s": t_frac(0.5), "t90_s": t_frac(0.9), "t_last_40db_s": round(float(ok[-1]), 4) if len(ok) else None,
+                     "median_psnr_db": round(float(np.median(ps)), 2), "mean_psnr_db": round(float(np.mean(ps)), 2)}
+    return res
 
 
 def main():
@@ -137,6 +191,8 @@ def main():
     }
     if fit_info:
         res["config"]["basis_fit"] = fit_info
+    if not a.no_time_to_40db:
+        res["time_to_40db"] = time_to_40db(torch, disk)
     if not a.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(basis_t.cpu().numpy(), img, P)
     print(json.dumps(res), flush=True)

@@ -65,6 +65,9 @@ typedef struct {
 } disk_complex;
 
 const char* disk_status_string(disk_status s);
+/* Rate of the constant device clock that finish_ticks counts, in kHz, for the
+ * current device (0 if it cannot be queried). */
+int64_t disk_clock_rate_khz(void);
 /* Message of the last failing call on this thread ("" if none). */
 const char* disk_last_error(void);
 /* Library version string. */
@@ -152,6 +155,9 @@ typedef struct {
  *            field); that target is skipped, its Theta untouched, psnr_db 0
  *            and steps 0.  Offsets past the ends of the arrays cannot be
  *            detected: they are the caller's responsibility.
+ *   finish_ticks  device uint64 [B + 1] or NULL: the device's constant-rate
+ *            clock (disk_clock_rate_khz) when each target finished; entry B
+ *            holds the clock at the start of the launch.
  *   meta     host: B, the maximum side and total taps, used to size the launch.
  * Loss: normalised MSE, mean((K_syn - K)^2) / max(K)^2, or Charbonnier.
  */
@@ -164,8 +170,8 @@ size_t disk_optimize_workspace_size(const disk_batch_meta* meta);
 disk_status disk_optimize_batch(const disk_batch_meta* meta, const disk_target* desc,
                                 const int32_t* taps, const float* targets, float* theta,
                                 float* psnr_db, int32_t* steps, int32_t* status,
-                                const disk_opt_params* params, void* ws, size_t ws_bytes,
-                                hipStream_t stream);
+                                uint64_t* finish_ticks, const disk_opt_params* params, void* ws,
+                                size_t ws_bytes, hipStream_t stream);
 
 /*
  * Basis precompute (the offline stage of Sec. 4.3): fits the B targets in

@@ -18,7 +18,7 @@ __all__ = [
     "disk_forward", "disk_backward", "disk_sv_filter", "disk_sv_prepare", "disk_sv_apply", "Basis", "make_basis",
     "disk_optimize_batch", "disk_init_radial", "disk_fit_basis", "pack_targets", "fit_basis", "disk_init_shape", "OptParams", "Batch", "make_batch",
     "disk_init_predict", "disk_net_train_step", "disk_net_prepare_inputs", "disk_net_scatter_theta",
-    "disk_net_param_count", "net_workspace",
+    "disk_net_param_count", "net_workspace", "clock_rate_khz",
 ]
 
 ZERO, CLAMP = 0, 1
@@ -71,7 +71,9 @@ def lib():
         "disk_backward_workspace_size": (c_size_t, [POINTER(DiskComplex), c_int32, c_int32, c_int32]),
         "disk_backward": (c_int32, [POINTER(DiskComplex), P, P, P, P, P, P, c_int32, c_int32, c_int32, c_int32, P, c_size_t, P]),
         "disk_optimize_workspace_size": (c_size_t, [POINTER(DiskBatchMeta)]),
-        "disk_optimize_batch": (c_int32, [POINTER(DiskBatchMeta), P, P, P, P, P, P, P, POINTER(DiskOptParams), P, c_size_t, P]),
+        "disk_optimize_batch": (c_int32, [POINTER(DiskBatchMeta), P, P, P, P, P, P, P, P, POINTER(DiskOptParams), P,
+                                          c_size_t, P]),
+        "disk_clock_rate_khz": (c_int64, []),
         "disk_init_radial": (c_int32, [POINTER(DiskBatchMeta), P, P, P, P, P]),
         "disk_fit_basis_workspace_size": (c_size_t, [POINTER(DiskBatchMeta)]),
         "disk_fit_basis": (c_int32, [POINTER(DiskBatchMeta), P, P, P, P, P, P, P, POINTER(c_float),
@@ -307,9 +309,11 @@ def make_batch(desc, taps, targets, device="cuda"):
     return bt
 
 
-def disk_optimize_batch(batch: Batch, theta, params: OptParams):
+def disk_optimize_batch(batch: Batch, theta, params: OptParams, ticks=None):
     """Optimise every target of ``batch`` in place on ``theta`` [*][3].
-    Returns (psnr_db [B], steps [B], status [B])."""
+    Returns (psnr_db [B], steps [B], status [B]).  ``ticks`` (optional,
+    int64 [B + 1]) receives the device clock at each target's finish and, in
+    entry B, at the launch's start."""
     dev = theta.device
     B = batch.B
     psnr = torch.empty(B, dtype=torch.float32, device=dev)
@@ -318,9 +322,13 @@ def disk_optimize_batch(batch: Batch, theta, params: OptParams):
     L = lib()
     ws = _workspace(L.disk_optimize_workspace_size(ctypes.byref(batch.meta)), dev)
     _check(L.disk_optimize_batch(ctypes.byref(batch.meta), _ptr(batch.desc), _ptr(batch.taps), _ptr(batch.targets),
-                                 _ptr(theta), _ptr(psnr), _ptr(steps), _ptr(status), ctypes.byref(params.c),
-                                 _ptr(ws), ws.numel(), _stream()))
+                                 _ptr(theta), _ptr(psnr), _ptr(steps), _ptr(status), _ptr(ticks),
+                                 ctypes.byref(params.c), _ptr(ws), ws.numel(), _stream()))
     return psnr, steps, status
+
+
+def clock_rate_khz():
+    return int(lib().disk_clock_rate_khz())
 
 
 def disk_fit_basis(batch: Batch, theta, scale, params: OptParams):

@@ -104,6 +104,13 @@ const char* disk_status_string(disk_status s) {
 const char* disk_last_error(void) { return g_err.c_str(); }
 const char* disk_version(void) { return "libdisk 0.1 gfx950"; }
 
+int64_t disk_clock_rate_khz(void) {
+    int dev = 0, khz = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess) return 0;
+    return khz;
+}
+
 // ---------------------------------------------------------------------------
 // forward
 // ---------------------------------------------------------------------------
@@ -434,7 +441,8 @@ size_t disk_optimize_workspace_size(const disk_batch_meta* meta) {
 
 disk_status disk_optimize_batch(const disk_batch_meta* meta, const disk_target* desc, const int32_t* taps,
                                 const float* targets, float* theta, float* psnr_db, int32_t* steps, int32_t* status,
-                                const disk_opt_params* params, void* ws, size_t ws_bytes, hipStream_t stream) {
+                                uint64_t* finish_ticks, const disk_opt_params* params, void* ws, size_t ws_bytes,
+                                hipStream_t stream) {
     DISK_TRY(check_meta(meta));
     DISK_TRY(check_ptr(desc, "desc"));
     DISK_TRY(check_ptr(taps, "taps"));
@@ -452,8 +460,10 @@ disk_status disk_optimize_batch(const disk_batch_meta* meta, const disk_target* 
     optimize_ws(meta, cv, &order, &queue, &scratch, &slot, &nwg);
     if (!ws || cv.used > ws_bytes)
         return fail(DISK_WORKSPACE_TOO_SMALL, "workspace %zu < %zu bytes", ws_bytes, cv.used);
+    DISK_TRY(check_ptr(finish_ticks, "finish_ticks", true));
     DISK_HIP(launch_optimize(meta->B, desc, taps, targets, theta, psnr_db, steps, status, p, order, queue, scratch,
-                             slot, nwg, meta->max_side, meta->max_T, stream),
+                             slot, nwg, meta->max_side, meta->max_T,
+                             reinterpret_cast<unsigned long long*>(finish_ticks), stream),
              "optimize");
     return ok();
 }
@@ -486,7 +496,7 @@ disk_status disk_fit_basis(const disk_batch_meta* meta, const disk_target* desc,
     for (int k = 0; k < meta->B; ++k) {
         if (k > 0) DISK_HIP(launch_continue(desc, taps, theta, k, scale[k], stream), "continuation start");
         DISK_HIP(launch_optimize(1, desc + k, taps, targets, theta, psnr_db + k, steps + k, status + k, *params,
-                                 order, queue, scratch, slot, nwg, meta->max_side, meta->max_T, stream),
+                                 order, queue, scratch, slot, nwg, meta->max_side, meta->max_T, nullptr, stream),
                  "optimize");
     }
     return ok();

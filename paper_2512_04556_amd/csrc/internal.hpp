@@ -78,7 +78,8 @@ int opt_workgroups(int B);
 size_t opt_slot_floats(int max_side, int max_L);
 hipError_t launch_optimize(int B, const disk_target* desc, const int* taps, const float* targets, float* theta,
                            float* psnr, int* steps, int* status, const disk_opt_params& p, int* order, int* queue,
-                           float* scratch, size_t slot_floats, int nwg, int max_side, int max_T, hipStream_t s);
+                           float* scratch, size_t slot_floats, int nwg, int max_side, int max_T,
+                           unsigned long long* ticks, hipStream_t s);
 hipError_t launch_continue(const disk_target* desc, const int* taps, float* theta, int k, float scale,
                            hipStream_t s);
 hipError_t launch_init_radial(int B, const disk_target* desc, const int* taps, const float* targets, float* theta,

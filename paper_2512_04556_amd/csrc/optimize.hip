@@ -48,6 +48,7 @@ struct OptArgs {
     float* scratch;
     size_t slot_floats;
     int max_side, max_T;
+    unsigned long long* ticks;   // optional: device clock when each target finished
 };
 
 struct TapO {
@@ -187,6 +188,7 @@ __global__ __launch_bounds__(kOptThreads) void opt_kernel(OptArgs a) {
                 a.psnr[b] = 0.0f;
                 a.steps[b] = 0;
                 a.status[b] = 3;
+                if (a.ticks) a.ticks[b] = wall_clock64();
             }
             __syncthreads();
             continue;
@@ -410,6 +412,7 @@ __global__ __launch_bounds__(kOptThreads) void opt_kernel(OptArgs a) {
             a.psnr[b] = psnr;
             a.steps[b] = step;
             a.status[b] = status;
+            if (a.ticks) a.ticks[b] = wall_clock64();
         }
         __syncthreads();
     }
@@ -420,7 +423,8 @@ __global__ __launch_bounds__(kOptThreads) void opt_kernel(OptArgs a) {
 constexpr int kOrderBuckets = 4096;
 __global__ __launch_bounds__(1024) void opt_order_kernel(int B, const disk_target* __restrict__ desc,
                                                          const int* __restrict__ taps, int* __restrict__ order,
-                                                         int* __restrict__ queue) {
+                                                         int* __restrict__ queue, unsigned long long* ticks) {
+    if (ticks && threadIdx.x == 0) ticks[B] = wall_clock64();   // the launch's start
     __shared__ int hist[kOrderBuckets];
     for (int i = threadIdx.x; i < kOrderBuckets; i += blockDim.x) hist[i] = 0;
     __syncthreads();
@@ -490,9 +494,11 @@ size_t opt_slot_floats(int max_side, int max_L) {
 
 hipError_t launch_optimize(int B, const disk_target* desc, const int* taps, const float* targets, float* theta,
                            float* psnr, int* steps, int* status, const disk_opt_params& p, int* order, int* queue,
-                           float* scratch, size_t slot_floats, int nwg, int max_side, int max_T, hipStream_t s) {
-    hipLaunchKernelGGL(opt_order_kernel, dim3(1), dim3(1024), 0, s, B, desc, taps, order, queue);
-    OptArgs a{B, desc, taps, targets, theta, psnr, steps, status, p, order, queue, scratch, slot_floats, max_side, max_T};
+                           float* scratch, size_t slot_floats, int nwg, int max_side, int max_T,
+                           unsigned long long* ticks, hipStream_t s) {
+    hipLaunchKernelGGL(opt_order_kernel, dim3(1), dim3(1024), 0, s, B, desc, taps, order, queue, ticks);
+    OptArgs a{B,     desc,  taps,    targets,     theta,    psnr,  steps, status, p,
+              order, queue, scratch, slot_floats, max_side, max_T, ticks};
     hipLaunchKernelGGL(opt_kernel, dim3(nwg), dim3(kOptThreads), 0, s, a);
     return hipGetLastError();
 }

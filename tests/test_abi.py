@@ -121,7 +121,7 @@ def test_optimiser_and_basis_fit_validation():
     args = (ctypes.byref(meta), fake, fake, fake, fake, fake, fake, fake)
     # even max_side, B < 1
     bad = disk.DiskBatchMeta(4, 30, 24)
-    assert L.disk_optimize_batch(ctypes.byref(bad), *args[1:], ctypes.byref(prm), fake, ws, None) == -2
+    assert L.disk_optimize_batch(ctypes.byref(bad), *args[1:], None, ctypes.byref(prm), fake, ws, None) == -2
     assert L.disk_fit_basis(ctypes.byref(disk.DiskBatchMeta(0, 31, 24)), *args[1:], sc, ctypes.byref(prm),
                             fake, ws, None) == -2
     # scale missing or not positive
@@ -132,7 +132,9 @@ def test_optimiser_and_basis_fit_validation():
     # Adam hyper-parameters
     bad_p = disk.OptParams(max_steps=10, beta1=1.0).c
     assert L.disk_fit_basis(*args, sc, ctypes.byref(bad_p), fake, ws, None) == -1
-    assert L.disk_optimize_batch(*args, ctypes.byref(bad_p), fake, ws, None) == -1
+    assert L.disk_optimize_batch(*args, None, ctypes.byref(bad_p), fake, ws, None) == -1
+    # misaligned finish_ticks
+    assert L.disk_optimize_batch(*args, P(0x1008), ctypes.byref(prm), fake, ws, None) == -1
     # workspace too small
     need = L.disk_fit_basis_workspace_size(ctypes.byref(meta))
     assert need > 0
