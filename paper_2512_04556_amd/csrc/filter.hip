@@ -138,6 +138,13 @@ __device__ __forceinline__ const lds_float* lds_ptr(int byte_offset) {
     return reinterpret_cast<const lds_float*>(static_cast<uintptr_t>(static_cast<uint32_t>(byte_offset)));
 }
 
+// base + a 32-bit byte offset (lets a load take a scalar base and a 32-bit
+// vector offset)
+template <typename T>
+__device__ __forceinline__ const T* byte_at(const T* base, uint32_t byte_off) {
+    return reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + byte_off);
+}
+
 // Single-instruction VALU helpers (arithmetic only).
 __device__ __forceinline__ int cvt_flr(float x) {
     int r;
@@ -209,8 +216,15 @@ __device__ __forceinline__ void gather_tap4(float* acc, float basef, float rowBf
 // Staged-tile row stride in dwords: (64 + 2 halo) pixels of C channels, padded
 // so that the four 16-lane rows of a wave fall in disjoint LDS banks
 // (row stride = 16, 33, 48, 1 mod 64 for C = 1..4).
+// LDS row stride of the staged tile.  The LDS has 128 four-byte banks and a
+// 128-bit read serves 32 lanes per cycle: two 16-pixel lane rows.  With float4
+// pixels the two rows of a pass are conflict-free when their starts are 256 B
+// apart modulo 512 B, so the C >= 3 stride is padded to 64 dwords mod 128.
 __host__ __device__ __forceinline__ int sv_row_dwords(int halo, int C) {
-    if (C >= 3) return (kTW + 2 * halo) * 4;  // float4 per pixel; 16-lane groups never conflict
+    if (C >= 3) {
+        const int raw = (kTW + 2 * halo) * 4;
+        return raw + ((64 - raw % 128) + 128) % 128;
+    }
     const int raw = (kTW + 2 * halo) * C;
     const int target = C == 1 ? 16 : C == 2 ? 33 : C == 3 ? 48 : 1;
     return raw + ((target - raw % 64) + 64) % 64;
@@ -398,9 +412,13 @@ __device__ __forceinline__ void sv_store(TOut* __restrict__ Y, size_t plane, int
 #pragma unroll
     for (int j = 0; j < PY; ++j) {
         const int y = y0 + 4 * j;
-        if (y < H)
+        if (y < H) {
+            const uint32_t off = (static_cast<uint32_t>(y) * static_cast<uint32_t>(W) + static_cast<uint32_t>(x)) *
+                                 static_cast<uint32_t>(sizeof(TOut));
 #pragma unroll
-            for (int c = 0; c < C; ++c) IO<TOut>::store(Y, c * plane + static_cast<size_t>(y) * W + x, acc[j][c]);
+            for (int c = 0; c < C; ++c)
+                IO<TOut>::store(const_cast<TOut*>(byte_at(Y + c * plane, off)), 0, acc[j][c]);
+        }
     }
 }
 
@@ -486,19 +504,27 @@ __global__ __launch_bounds__(64 * NW) void sv_pass_kernel(
 // flight into registers, so HBM/L2 latency overlaps the gather.  16 waves,
 // 2 row-steps per wave: a 64 x 32 tile.
 constexpr int kPipeHalo = 24;
-constexpr int kPipeNW = 16;
+#ifndef DISK_SV_HALO8
+#define DISK_SV_HALO8 12
+#endif
+constexpr int kPipeHalo8 = DISK_SV_HALO8;   // 8-wave variant
 constexpr int kPipePY = 2;
-constexpr int kPipeRPW = (4 * kPipePY * (kPipeNW / 4) + 2 * kPipeHalo + kPipeNW - 1) / kPipeNW;  // staged rows/wave
-constexpr int kPipeNQ = (kTW + 2 * kPipeHalo + 63) / 64;                                        // column chunks
+template <int NW, int HMAX>
+struct PipeShape {
+    static constexpr int TH = 4 * kPipePY * (NW / 4);                     // tile rows
+    static constexpr int RPW = (TH + 2 * HMAX + NW - 1) / NW;              // staged rows per wave
+    static constexpr int NQ = (kTW + 2 * HMAX + 63) / 64;                  // 64-column chunks
+};
 
-template <int C, int DIMS, typename TIn, typename TOut>
-__global__ __launch_bounds__(64 * kPipeNW) void sv_pass_pipe_kernel(
+template <int C, int DIMS, typename TIn, typename TOut, int NW, int HMAX>
+__global__ __launch_bounds__(64 * NW) void sv_pass_pipe_kernel(
     const TIn* __restrict__ X, TOut* __restrict__ Y, const float* __restrict__ P,
     const float* __restrict__ table, int tap0, int N, int T, int G0, int G1, int H, int W, int halo,
     int tiles_x, int per, int ntiles, const int* __restrict__ flag) {
     extern __shared__ float lds[];
-    constexpr int PY = kPipePY, NW = kPipeNW;
-    constexpr int TH = 4 * PY * (NW / 4);
+    constexpr int PY = kPipePY;
+    constexpr int TH = PipeShape<NW, HMAX>::TH;
+    constexpr int kPipeRPW = PipeShape<NW, HMAX>::RPW, kPipeNQ = PipeShape<NW, HMAX>::NQ;
     const int xcd = blockIdx.x & 7, nwg = gridDim.x >> 3;
     const int tend = min((xcd + 1) * per, ntiles);
     int tile = xcd * per + (blockIdx.x >> 3);
@@ -521,34 +547,46 @@ __global__ __launch_bounds__(64 * kPipeNW) void sv_pass_pipe_kernel(
     const int rowB = rowW * 4;
     constexpr int PXB = C >= 3 ? 16 : 4 * C;
     const int base0 = lds_offset(lds) + (lyb + halo) * rowB + (lx + halo) * PXB;
+    const int wv = uniform(wave);                // the wave index, in a scalar register
     const int nq = (SX + 63) >> 6;               // <= kPipeNQ
-    const int nr = (SY - wave + NW - 1) / NW;    // staged rows of this wave, <= kPipeRPW
+    const int nr = (SY - wv + NW - 1) / NW;      // staged rows of this wave, <= kPipeRPW
+    // one base pointer per plane and 32-bit element offsets inside a plane
+    // (H W <= 2^30): the loads take a scalar base plus one vector offset
+    const TIn* Xc[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) Xc[c] = X + c * plane;
+    const float* Pd[DIMS];
+#pragma unroll
+    for (int d = 0; d < DIMS; ++d) Pd[d] = P + d * plane;
 
     float stg[kPipeRPW][kPipeNQ][C];
     float pv[PY][DIMS];
     auto issue = [&](int t) {
         const int tx0 = (t % tiles_x) * kTW, ty0 = (t / tiles_x) * TH;
+        uint32_t gx[kPipeNQ];
+#pragma unroll
+        for (int q = 0; q < kPipeNQ; ++q) gx[q] = static_cast<uint32_t>(min(max(tx0 - halo + lane + 64 * q, 0), W - 1));
 #pragma unroll
         for (int rr = 0; rr < kPipeRPW; ++rr) {
             if (rr < nr) {
-                const int gy = min(max(ty0 - halo + wave + NW * rr, 0), H - 1);
-                const size_t grow = static_cast<size_t>(gy) * W;
+                const uint32_t grow = static_cast<uint32_t>(min(max(ty0 - halo + wv + NW * rr, 0), H - 1)) *
+                                      static_cast<uint32_t>(W);
 #pragma unroll
                 for (int q = 0; q < kPipeNQ; ++q) {
                     if (q < nq) {
-                        const int gx = min(max(tx0 - halo + lane + 64 * q, 0), W - 1);
+                        const uint32_t off = (grow + gx[q]) * static_cast<uint32_t>(sizeof(TIn));   // bytes
 #pragma unroll
-                        for (int c = 0; c < C; ++c) stg[rr][q][c] = IO<TIn>::load(X, c * plane + grow + gx);
+                        for (int c = 0; c < C; ++c) stg[rr][q][c] = IO<TIn>::load(byte_at(Xc[c], off), 0);
                     }
                 }
             }
         }
-        const int xc = min(tx0 + lx, W - 1);
+        const uint32_t xc = static_cast<uint32_t>(min(tx0 + lx, W - 1));
 #pragma unroll
         for (int j = 0; j < PY; ++j) {
-            const size_t pi = static_cast<size_t>(min(ty0 + 4 * j + lyb, H - 1)) * W + xc;
+            const uint32_t pi = (static_cast<uint32_t>(min(ty0 + 4 * j + lyb, H - 1)) * static_cast<uint32_t>(W) + xc) * 4u;
 #pragma unroll
-            for (int d = 0; d < DIMS; ++d) pv[j][d] = P[d * plane + pi];
+            for (int d = 0; d < DIMS; ++d) pv[j][d] = *byte_at(Pd[d], pi);
         }
     };
 
@@ -557,7 +595,7 @@ __global__ __launch_bounds__(64 * kPipeNW) void sv_pass_pipe_kernel(
         // the staged registers of `tile` -> LDS
 #pragma unroll
         for (int rr = 0; rr < kPipeRPW; ++rr) {
-            const int ly = wave + NW * rr;
+            const int ly = wv + NW * rr;
 #pragma unroll
             for (int q = 0; q < kPipeNQ; ++q) {
                 const int cx = lane + 64 * q;
@@ -610,24 +648,24 @@ static int cu_count() {
     return n;
 }
 
-template <int C, int DIMS, typename TIn, typename TOut>
+template <int C, int DIMS, typename TIn, typename TOut, int NW, int HMAX>
 static hipError_t launch_pipe(const void* src, void* dst, const float* pmap, const float* table, int tap0, int N,
                               int T, int G0, int G1, int H, int W, int halo, const int* flag, hipStream_t s) {
-    constexpr int TH = 4 * kPipePY * (kPipeNW / 4);
+    constexpr int TH = PipeShape<NW, HMAX>::TH;
     const int tiles_x = (W + kTW - 1) / kTW, tiles_y = (H + TH - 1) / TH;
     const int ntiles = tiles_x * tiles_y;
     const int per = (ntiles + 7) / 8;
-    const size_t lds = sv_lds_bytes(halo, C, kPipePY * (kPipeNW / 4));
-    auto fn = sv_pass_pipe_kernel<C, DIMS, TIn, TOut>;
+    const size_t lds = sv_lds_bytes(halo, C, kPipePY * (NW / 4));
+    auto fn = sv_pass_pipe_kernel<C, DIMS, TIn, TOut, NW, HMAX>;
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
     if (e != hipSuccess) return e;
     int occ = 0;
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, reinterpret_cast<const void*>(fn), 64 * kPipeNW, lds);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, reinterpret_cast<const void*>(fn), 64 * NW, lds);
     if (e != hipSuccess || occ < 1) occ = 1;
     int per_xcd = (cu_count() * occ) / 8;                 // work-groups per XCD
     per_xcd = std::max(1, std::min(per_xcd, per));
-    hipLaunchKernelGGL(fn, dim3(8 * per_xcd), dim3(64 * kPipeNW), lds, s, static_cast<const TIn*>(src),
+    hipLaunchKernelGGL(fn, dim3(8 * per_xcd), dim3(64 * NW), lds, s, static_cast<const TIn*>(src),
                        static_cast<TOut*>(dst), pmap, table, tap0, N, T, G0, G1, H, W, halo, tiles_x, per, ntiles,
                        flag);
     return hipGetLastError();
@@ -655,8 +693,14 @@ template <int C, int DIMS, typename TIn, typename TOut>
 static hipError_t launch_typed(const void* src, void* dst, const float* pmap, const float* table, int tap0, int N,
                                int T, int G0, int G1, int H, int W, int halo, const int* flag, hipStream_t s) {
     static const int pipe = env_int("DISK_SV_PIPE", 1);
-    if (pipe && halo <= kPipeHalo && sv_lds_bytes(halo, C, kPipePY * (kPipeNW / 4)) <= 160 * 1024)
-        return launch_pipe<C, DIMS, TIn, TOut>(src, dst, pmap, table, tap0, N, T, G0, G1, H, W, halo, flag, s);
+    // small halos: 8-wave work-groups of 64 x 16 tiles, two per CU, whose
+    // staging and gather phases drift apart and overlap
+    if (pipe && halo <= kPipeHalo8 && sv_lds_bytes(halo, C, kPipePY * 2) <= 80 * 1024)
+        return launch_pipe<C, DIMS, TIn, TOut, 8, kPipeHalo8>(src, dst, pmap, table, tap0, N, T, G0, G1, H, W, halo,
+                                                              flag, s);
+    if (pipe && halo <= kPipeHalo && sv_lds_bytes(halo, C, kPipePY * 4) <= 160 * 1024)
+        return launch_pipe<C, DIMS, TIn, TOut, 16, kPipeHalo>(src, dst, pmap, table, tap0, N, T, G0, G1, H, W, halo,
+                                                              flag, s);
     if (sv_rows_per_wave(halo, C) == 4)
         return launch_tiles<C, DIMS, TIn, TOut, 4, 8>(src, dst, pmap, table, tap0, N, T, G0, G1, H, W, halo, flag, s);
     return launch_tiles<C, DIMS, TIn, TOut, 2, 4>(src, dst, pmap, table, tap0, N, T, G0, G1, H, W, halo, flag, s);
