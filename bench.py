@@ -34,6 +34,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--basis", choices=["fitted", "random"], default="fitted")
     ap.add_argument("--no-time-to-40db", action="store_true")
+    ap.add_argument("--copy-reference", type=int, default=0, metavar="MIB",
+                    help="only run 5 plain device copies of MIB MiB (the scale for HBM byte counters) and exit")
     return ap.parse_args()
 
 
@@ -70,6 +72,26 @@ def cpu_baseline(basis_np, img, P):
     dt = time.perf_counter() - t
     return {"value": H * W / dt / 1e6, "unit": "Mpix/s", "cores": 1, "kind": "oracle",
             "sample": f"the full frame ({H}x{W}x{C}), 4 passes, FP64 numpy, {dt:.1f} s single-threaded"}
+
+
+def measured_traffic():
+    """HBM bytes per pass launch from the committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE summary, or None when the kernel source has changed since."""
+    import hashlib
+    root = os.path.dirname(os.path.abspath(__file__))
+    src = os.path.join(root, "paper_2512_04556_amd", "csrc", "filter.hip")
+    prof = os.path.join(root, "profiles", "sv_pass_kernel_1080p.md")
+    try:
+        text = open(prof).read()
+        digest = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    except OSError:
+        return None
+    if f"sha256 prefix `{digest}`" not in text:
+        return None
+    for line in text.splitlines():
+        if line.startswith("traffic_per_launch_bytes:"):
+            return int(line.split(":")[1])
+    return None
 
 
 def time_to_40db(torch, disk, n=4096):
@@ -132,6 +154,15 @@ def main():
               file=sys.stderr)
         sys.exit(2)
     import torch
+    if a.copy_reference:
+        n = a.copy_reference * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_reference_bytes": 4 * n, "copies": 5}), flush=True)
+        return
     import paper_2512_04556_amd as disk
     from synth import noise_image, param_map
 
@@ -185,9 +216,9 @@ def main():
                    "halo": basis.halo},
         "hbm_frac_frame": round(frame_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
         "event_ms_per_step": round(ev_ms, 5),
-        "roofline": {"bound": "hbm", "kernel": "sv_pass_kernel", "achieved": round(achieved, 1),
+        "roofline": {"bound": "hbm", "kernel": "sv_pass_pipe_kernel", "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": None, "pass_ms": round(pass_ms, 5), "bytes_per_launch": pass_bytes},
+                     "traffic": measured_traffic(), "pass_ms": round(pass_ms, 5), "bytes_per_launch": pass_bytes},
     }
     if fit_info:
         res["config"]["basis_fit"] = fit_info
