@@ -94,6 +94,32 @@ def measured_traffic():
     return None
 
 
+def dense_reference(torch, disk, x, p, sparse_out, sparse_ms):
+    """The dense per-pixel disk convolution the basis interpolates (r = 2 + 30 P,
+    window 67 x 67): its frame time, the sparse filter's speedup over it, and
+    the sparse output's PSNR against it on four seeded 128 x 128 crops."""
+    args = (x, p, disk.DENSE_DISK, 2.0, 32.0, 33)
+    dense = disk.disk_dense_sv(*args)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    stream = torch.cuda.current_stream()
+    e0.record(stream)
+    for _ in range(3):
+        disk.disk_dense_sv(*args, out=dense)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    dense_ms = e0.elapsed_time(e1) / 3
+    rng = np.random.default_rng(5)
+    se, n = 0.0, 0
+    for _ in range(4):
+        y0, x0 = int(rng.integers(0, H - 128)), int(rng.integers(0, W - 128))
+        d = (sparse_out[:, y0:y0 + 128, x0:x0 + 128].double() - dense[:, y0:y0 + 128, x0:x0 + 128].double())
+        se += float((d * d).sum())
+        n += d.numel()
+    return {"ms": round(dense_ms, 4), "speedup_sparse_vs_dense": round(dense_ms / sparse_ms, 2),
+            "psnr_db_sparse_vs_dense": round(10.0 * np.log10(1.0 / (se / n)), 2), "crops": "4 x 128x128, seed 5"}
+
+
 def time_to_40db(torch, disk, n=4096):
     """Batched optimisation of n fresh targets (odd sides 15..127, the shape
     families of the batching workload, 4 layers x 12 taps, seed 7) to 40 dB or
@@ -222,6 +248,7 @@ def main():
     }
     if fit_info:
         res["config"]["basis_fit"] = fit_info
+    res["dense_reference"] = dense_reference(torch, disk, x, p, out, ms)
     if not a.no_time_to_40db:
         res["time_to_40db"] = time_to_40db(torch, disk)
     if not a.no_cpu_baseline:

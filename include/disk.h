@@ -276,6 +276,33 @@ disk_status disk_sv_apply(const disk_basis* b, const void* table, const void* im
                           disk_dtype io, void* ws, size_t ws_bytes, hipStream_t stream);
 
 /* ------------------------------------------------------------------------- */
+/* Dense reference: the per-pixel kernel the sparse filter approximates.       */
+/* ------------------------------------------------------------------------- */
+/*
+ * Spatially varying dense convolution (Eq. 1 with a kernel per output pixel,
+ * the ground truth of Sec. 4.3's filter-space interpolation), CLAMP boundary:
+ *   out[p] = sum_q K_p[q] I[clamp(p - q)] / sum_q K_p[q],  |qx|, |qy| <= half,
+ *   DISK_DENSE_DISK:    K_p[q] = clamp(r + 1/2 - |q|, 0, 1),
+ *                       r = r0 + (r1 - r0) clamp(P0(p), 0, 1);
+ *   DISK_DENSE_ELLIPSE: axis-aligned ellipse with semi-axes (r sqrt(a), r / sqrt(a)),
+ *                       a = a0 (a1 / a0)^clamp(P1(p), 0, 1),
+ *                       K_p[q] = clamp(1/2 - (rho - 1) |q| / rho, 0, 1) with
+ *                       rho = |(qx / ax, qy / ay)| (clamp(1/2 + min(ax, ay), 0, 1) at q = 0).
+ *   image, out  device [C][H][W] of dtype io;  pmap device float [1 or 2][H][W].
+ * Each pixel visits at most (2 half + 1)^2 taps; half should cover the
+ * largest semi-axis + 1/2 (larger kernels are cut at half).
+ */
+typedef enum { DISK_DENSE_DISK = 0, DISK_DENSE_ELLIPSE = 1 } disk_dense_kind;
+typedef struct {
+    int32_t kind;       /* disk_dense_kind */
+    float r0, r1;       /* radius at P0 = 0 and P0 = 1 (pixels, >= 0) */
+    float a0, a1;       /* aspect at P1 = 0 and P1 = 1 (ellipse only, > 0) */
+    int32_t half;       /* 0 <= half <= 127 */
+} disk_dense_params;
+disk_status disk_dense_sv(const disk_dense_params* p, const void* image, const float* pmap, void* out,
+                          int32_t C, int32_t H, int32_t W, disk_dtype io, hipStream_t stream);
+
+/* ------------------------------------------------------------------------- */
 /* Learned initialiser (not in the paper): a conv encoder + MLP that predicts  */
 /* a starting Theta for the optimiser; BF16 operands, FP32 accumulation on     */
 /* MFMA.                                                                      */

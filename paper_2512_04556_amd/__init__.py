@@ -19,6 +19,7 @@ __all__ = [
     "disk_optimize_batch", "disk_init_radial", "disk_fit_basis", "pack_targets", "fit_basis", "disk_init_shape", "OptParams", "Batch", "make_batch",
     "disk_init_predict", "disk_net_train_step", "disk_net_prepare_inputs", "disk_net_scatter_theta",
     "disk_net_param_count", "net_workspace", "clock_rate_khz",
+    "disk_dense_sv", "DENSE_DISK", "DENSE_ELLIPSE",
 ]
 
 ZERO, CLAMP = 0, 1
@@ -48,6 +49,11 @@ class DiskOptParams(ctypes.Structure):
                 ("charb_eps", c_float)]
 
 
+class DiskDenseParams(ctypes.Structure):
+    _fields_ = [("kind", c_int32), ("r0", c_float), ("r1", c_float), ("a0", c_float), ("a1", c_float),
+                ("half", c_int32)]
+
+
 class DiskBatchMeta(ctypes.Structure):
     _fields_ = [("B", c_int32), ("max_side", c_int32), ("max_T", c_int32)]
 
@@ -74,6 +80,7 @@ def lib():
         "disk_optimize_batch": (c_int32, [POINTER(DiskBatchMeta), P, P, P, P, P, P, P, P, POINTER(DiskOptParams), P,
                                           c_size_t, P]),
         "disk_clock_rate_khz": (c_int64, []),
+        "disk_dense_sv": (c_int32, [POINTER(DiskDenseParams), P, P, P, c_int32, c_int32, c_int32, c_int32, P]),
         "disk_init_radial": (c_int32, [POINTER(DiskBatchMeta), P, P, P, P, P]),
         "disk_fit_basis_workspace_size": (c_size_t, [POINTER(DiskBatchMeta)]),
         "disk_fit_basis": (c_int32, [POINTER(DiskBatchMeta), P, P, P, P, P, P, P, POINTER(c_float),
@@ -325,6 +332,24 @@ def disk_optimize_batch(batch: Batch, theta, params: OptParams, ticks=None):
                                  _ptr(theta), _ptr(psnr), _ptr(steps), _ptr(status), _ptr(ticks),
                                  ctypes.byref(params.c), _ptr(ws), ws.numel(), _stream()))
     return psnr, steps, status
+
+
+DENSE_DISK, DENSE_ELLIPSE = 0, 1
+
+
+def disk_dense_sv(image, pmap, kind, r0, r1, half, a0=1.0, a1=1.0, out=None):
+    """Dense spatially varying convolution (the reference the sparse filter
+    approximates); image [C][H][W] float32 or bfloat16, pmap [dims][H][W]."""
+    _dev(image, "image")
+    _dev(pmap, "pmap")
+    C, H, W = (int(v) for v in image.shape)
+    io = BF16 if image.dtype == torch.bfloat16 else F32
+    if out is None:
+        out = torch.empty_like(image)
+    prm = DiskDenseParams(int(kind), float(r0), float(r1), float(a0), float(a1), int(half))
+    _check(lib().disk_dense_sv(ctypes.byref(prm), _ptr(image), _ptr(pmap.contiguous()), _ptr(out), C, H, W, io,
+                               _stream()))
+    return out
 
 
 def clock_rate_khz():

@@ -526,6 +526,30 @@ disk_status disk_init_radial(const disk_batch_meta* meta, const disk_target* des
 }
 
 // ---------------------------------------------------------------------------
+// dense reference
+// ---------------------------------------------------------------------------
+disk_status disk_dense_sv(const disk_dense_params* p, const void* image, const float* pmap, void* out, int32_t C,
+                          int32_t H, int32_t W, disk_dtype io, hipStream_t stream) {
+    if (!p) return fail(DISK_INVALID_ARG, "params is NULL");
+    DISK_TRY(check_image(C, H, W));
+    if (p->kind != DISK_DENSE_DISK && p->kind != DISK_DENSE_ELLIPSE) return fail(DISK_INVALID_ARG, "bad kind %d", p->kind);
+    if (p->half < 0 || p->half > 127) return fail(DISK_BAD_SHAPE, "half=%d out of [0,127]", p->half);
+    if (!(std::isfinite(p->r0) && std::isfinite(p->r1) && p->r0 >= 0.0f && p->r1 >= 0.0f))
+        return fail(DISK_INVALID_ARG, "radii must be finite and >= 0");
+    if (p->kind == DISK_DENSE_ELLIPSE && !(p->a0 > 0.0f && p->a1 > 0.0f && std::isfinite(p->a0) && std::isfinite(p->a1)))
+        return fail(DISK_INVALID_ARG, "aspects must be finite and > 0");
+    if (io != DISK_F32 && io != DISK_BF16) return fail(DISK_INVALID_ARG, "bad dtype %d", int(io));
+    DISK_TRY(check_ptr(image, "image"));
+    DISK_TRY(check_ptr(pmap, "pmap"));
+    DISK_TRY(check_ptr(out, "out"));
+    if (image == out) return fail(DISK_INVALID_ARG, "out must not alias image");
+    DISK_HIP(launch_dense_sv(p->kind, p->r0, p->r1, p->a0, p->a1, p->half, image, pmap, out, C, H, W,
+                             io == DISK_BF16 ? 1 : 0, stream),
+             "dense sv");
+    return ok();
+}
+
+// ---------------------------------------------------------------------------
 // learned initialiser
 // ---------------------------------------------------------------------------
 static disk_status check_net_batch(int32_t B) {

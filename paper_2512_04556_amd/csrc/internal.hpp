@@ -85,6 +85,10 @@ hipError_t launch_continue(const disk_target* desc, const int* taps, float* thet
 hipError_t launch_init_radial(int B, const disk_target* desc, const int* taps, const float* targets, float* theta,
                               int max_side, int max_T, hipStream_t s);
 
+// ---- dense reference (dense.hip) ----
+hipError_t launch_dense_sv(int kind, float r0, float r1, float a0, float a1, int half, const void* image,
+                           const float* pmap, void* out, int C, int H, int W, int bf16, hipStream_t s);
+
 // ---- learned initialiser (net.hip) ----
 struct NetWs {   // byte offsets into the caller's workspace
     size_t wp, act, yhat, g32[2], gq[2], dcol, part, cpart, grad, total;
