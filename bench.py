@@ -34,6 +34,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--basis", choices=["fitted", "random"], default="fitted")
     ap.add_argument("--no-time-to-40db", action="store_true")
+    ap.add_argument("--no-2d", action="store_true")
     ap.add_argument("--copy-reference", type=int, default=0, metavar="MIB",
                     help="only run 5 plain device copies of MIB MiB (the scale for HBM byte counters) and exit")
     return ap.parse_args()
@@ -118,6 +119,45 @@ def dense_reference(torch, disk, x, p, sparse_out, sparse_ms):
         n += d.numel()
     return {"ms": round(dense_ms, 4), "speedup_sparse_vs_dense": round(dense_ms / sparse_ms, 2),
             "psnr_db_sparse_vs_dense": round(10.0 * np.log10(1.0 / (se / n)), 2), "crops": "4 x 128x128, seed 5"}
+
+
+def sv2d_4k(torch, disk, steps=20):
+    """The 2-D workload: 3840x2160x3 BF16 I/O, an 8 x 8 basis of elliptical
+    disks (r = 2 + 46 P_r, aspect 0.5 * 4^P_a, 4 x 12 taps) built by the
+    learned initialiser plus 300 Adam steps, 2-D parameter map."""
+    from synth import ellipse_kernel, noise_image, param_map
+    from paper_2512_04556_amd import train_init
+    taps = [12, 12, 12, 12]
+    ks = [ellipse_kernel(2.0 + 46.0 * i / 7.0, 0.5 * 4.0 ** (j / 7.0)) for i in range(8) for j in range(8)]
+    bt = disk.make_batch(*disk.pack_targets(ks, taps))
+    t = time.perf_counter()
+    xin, hw = disk.disk_net_prepare_inputs(bt)
+    theta = disk.disk_net_scatter_theta(bt, disk.disk_init_predict(train_init.load(), xin, hw))
+    ps, _, _ = disk.disk_optimize_batch(bt, theta, disk.OptParams(max_steps=300, lr0=1e-2, lr1=1e-3))
+    torch.cuda.synchronize()
+    build_s = time.perf_counter() - t
+    basis = disk.make_basis(theta.view(64, 48, 3).contiguous(), taps, [8, 8])
+    h, w = 2160, 3840
+    x = torch.as_tensor(noise_image(h, w, 3, seed=2)).to(torch.bfloat16).cuda()
+    p = torch.as_tensor(param_map(h, w, seed=3, dims=2)).cuda()
+    out = torch.empty_like(x)
+    ws = disk.sv_filter_workspace(basis, 3, h, w, disk.BF16)
+    for _ in range(3):
+        disk.disk_sv_filter(basis, x, p, out=out, ws=ws)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        disk.disk_sv_filter(basis, x, p, out=out, ws=ws)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    # algorithmic bytes: first pass reads 6 B, middle 12 B, last writes 6 B, plus 8 B of map per pass
+    frame_bytes = h * w * (6 + 12 + 8 + (12 + 12 + 8) * 2 + 12 + 6 + 8)
+    return {"workload": "sv_filter_2160p_bf16_2d", "ms_per_frame": round(ms, 4), "mpix_s": round(h * w / ms / 1e3, 1),
+            "hbm_frac": round(frame_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4), "halo": basis.halo,
+            "basis_build_s": round(build_s, 3), "basis_psnr_db_mean": round(float(ps.mean()), 2)}
 
 
 def time_to_40db(torch, disk, n=4096):
@@ -249,6 +289,8 @@ def main():
     if fit_info:
         res["config"]["basis_fit"] = fit_info
     res["dense_reference"] = dense_reference(torch, disk, x, p, out, ms)
+    if not a.no_2d:
+        res["sv2d_4k_bf16"] = sv2d_4k(torch, disk)
     if not a.no_time_to_40db:
         res["time_to_40db"] = time_to_40db(torch, disk)
     if not a.no_cpu_baseline:

@@ -357,9 +357,6 @@ disk_status disk_sv_apply(const disk_basis* b, const void* table, const void* im
     DISK_TRY(check_ptr(ws, "ws", true));
     if (io != DISK_F32 && io != DISK_BF16) return fail(DISK_INVALID_ARG, "bad dtype %d", int(io));
     if (image == out) return fail(DISK_INVALID_ARG, "image and out must not alias");
-    for (int l = 0; l < b->cx.L; ++l)
-        if (sv_lds_bytes(b->halo[l], C, 2) > 160 * 1024)
-            return fail(DISK_UNSUPPORTED, "halo[%d]=%d too large for C=%d", l, b->halo[l], C);
     Carve cv(ws, ws_bytes);
     float *b0, *b1;
     sv_apply_ws(b, C, H, W, cv, &b0, &b1);

@@ -623,6 +623,72 @@ __global__ __launch_bounds__(64 * NW) void sv_pass_pipe_kernel(
     }
 }
 
+// Fallback for halos whose staged tile does not fit in LDS: one pixel per
+// thread, corners read straight from the (clamped) source planes through L1/L2.
+// Same decode, coefficients, corner weights and accumulation order as the
+// staged kernels, so the results are identical.
+template <int C, int DIMS, typename TIn, typename TOut>
+__global__ __launch_bounds__(256) void sv_pass_global_kernel(const TIn* __restrict__ X, TOut* __restrict__ Y,
+                                                             const float* __restrict__ P,
+                                                             const float* __restrict__ table, int tap0, int N, int T,
+                                                             int G0, int G1, int H, int W,
+                                                             const int* __restrict__ flag) {
+    constexpr int RW = DIMS == 1 ? kRow1D : kRow2D;
+    const long idx = static_cast<long>(blockIdx.x) * 256 + threadIdx.x;
+    if (idx >= static_cast<long>(H) * W) return;
+    const int y = static_cast<int>(idx / W), x = static_cast<int>(idx - static_cast<long>(y) * W);
+    const size_t plane = static_cast<size_t>(H) * W;
+    float acc[C];
+    if (*flag) {
+#pragma unroll
+        for (int c = 0; c < C; ++c) IO<TOut>::store(Y, c * plane + idx, __builtin_nanf(""));
+        return;
+    }
+    float pv[1][DIMS];
+#pragma unroll
+    for (int d = 0; d < DIMS; ++d) pv[0][d] = P[d * plane + idx];
+    float ta[1], tb[1];
+    int kk[1];
+    sv_decode<DIMS, 1>(pv, G0, G1, ta, tb, kk);
+#pragma unroll
+    for (int c = 0; c < C; ++c) acc[c] = 0.0f;
+    for (int i = 0; i < N; ++i) {
+        const float* r = table + (static_cast<size_t>(kk[0]) * T + tap0 + i) * RW;
+        float nx, ny, w;
+        if (DIMS == 1) {
+            nx = fmaf(ta[0], r[1], r[0]);
+            ny = fmaf(ta[0], r[3], r[2]);
+            w = fmaf(ta[0], r[5], r[4]);
+        } else {
+            const float st = ta[0] * tb[0];
+            nx = fmaf(st, r[3], fmaf(tb[0], r[2], fmaf(ta[0], r[1], r[0])));
+            ny = fmaf(st, r[7], fmaf(tb[0], r[6], fmaf(ta[0], r[5], r[4])));
+            w = fmaf(st, r[11], fmaf(tb[0], r[10], fmaf(ta[0], r[9], r[8])));
+        }
+        const float flx = floorf(nx), fly = floorf(ny);
+        const float fx = nx - flx, fy = ny - fly;
+        const float wy1 = w * fy, wy0 = w - wy1;
+        const float c01 = wy0 * fx, c00 = wy0 - c01;
+        const float c11 = wy1 * fx, c10 = wy1 - c11;
+        const int x0 = x + static_cast<int>(flx), y0 = y + static_cast<int>(fly);
+        const int xa = min(max(x0, 0), W - 1), xb = min(max(x0 + 1, 0), W - 1);
+        const size_t ra = static_cast<size_t>(min(max(y0, 0), H - 1)) * W;
+        const size_t rb = static_cast<size_t>(min(max(y0 + 1, 0), H - 1)) * W;
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            const size_t o = c * plane;
+            float a = acc[c];
+            a = fmaf(c00, IO<TIn>::load(X, o + ra + xa), a);
+            a = fmaf(c01, IO<TIn>::load(X, o + ra + xb), a);
+            a = fmaf(c10, IO<TIn>::load(X, o + rb + xa), a);
+            a = fmaf(c11, IO<TIn>::load(X, o + rb + xb), a);
+            acc[c] = a;
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < C; ++c) IO<TOut>::store(Y, c * plane + idx, acc[c]);
+}
+
 // Tile choice.  DISK_SV_PIPE=0 forces the one-tile-per-work-group kernel (a
 // tuning override, read once).
 static int env_int(const char* name, int dflt) {
@@ -703,7 +769,13 @@ static hipError_t launch_typed(const void* src, void* dst, const float* pmap, co
                                                               flag, s);
     if (sv_rows_per_wave(halo, C) == 4)
         return launch_tiles<C, DIMS, TIn, TOut, 4, 8>(src, dst, pmap, table, tap0, N, T, G0, G1, H, W, halo, flag, s);
-    return launch_tiles<C, DIMS, TIn, TOut, 2, 4>(src, dst, pmap, table, tap0, N, T, G0, G1, H, W, halo, flag, s);
+    if (sv_lds_bytes(halo, C, 2) <= 160 * 1024)
+        return launch_tiles<C, DIMS, TIn, TOut, 2, 4>(src, dst, pmap, table, tap0, N, T, G0, G1, H, W, halo, flag, s);
+    const long px = static_cast<long>(H) * W;
+    hipLaunchKernelGGL((sv_pass_global_kernel<C, DIMS, TIn, TOut>), dim3(static_cast<unsigned>((px + 255) / 256)),
+                       dim3(256), 0, s, static_cast<const TIn*>(src), static_cast<TOut*>(dst), pmap, table, tap0, N,
+                       T, G0, G1, H, W, flag);
+    return hipGetLastError();
 }
 
 template <int C, int DIMS>

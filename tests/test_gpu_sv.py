@@ -108,3 +108,71 @@ def test_sv_full_1080p_parity(dev):
     e = rel_err(got, want)
     print(f"sv 1080p halo={b.halo}: max-abs/peak {e:.2e}")
     assert e <= TOL_F32
+
+
+def test_sv_bench_configuration_full_frame(dev):
+    """Exactly the benchmark's workload: the fitted 16-disk basis (continuation
+    fit from the radial init, 4 x 8 taps; halos span both pass variants),
+    1920x1080x3 FP32; the whole frame against the oracle."""
+    from synth import disk_kernel
+    taps = [8, 8, 8, 8]
+    radii = [2.0 * (k + 1) for k in range(16)]
+    th, _, _, _ = disk.fit_basis([disk_kernel(r) for r in radii], taps,
+                                 [1.0] + [radii[k] / radii[k - 1] for k in range(1, 16)])
+    basis = th.cpu().numpy()
+    H, W = 1080, 1920
+    img = noise_image(H, W, 3, seed=2)
+    P = param_map(H, W, seed=3)
+    say("sv bench configuration")
+    out, b = _run(basis, taps, [16], img, P)
+    want = SV.sv_chain(img.astype(np.float64), P.astype(np.float64), basis.astype(np.float64), [16], taps)
+    e = rel_err(to_np(out), want)
+    print(f"sv bench config halo={b.halo}: max-abs/peak {e:.2e}")
+    assert max(b.halo) > 12 and min(b.halo) <= 12
+    assert e <= TOL_F32
+
+
+def test_sv_2d_4k_bf16_sampled(dev):
+    """The 2-D workload at full size: 3840x2160x3 BF16 I/O, 8 x 8 basis of
+    4 x 12 taps with halos above the pipelined kernels' range, 2-D map.  Two
+    seeded 32 x 32 output crops against the oracle run on the crop plus a
+    margin of the summed halos (the margin's own clamping cannot reach the
+    crop)."""
+    taps = [12, 12, 12, 12]
+    basis = _basis(64, taps, seed=400, r0=4.0, dr=0.4)
+    H, W = 2160, 3840
+    img = noise_image(H, W, 3, seed=2)
+    P = param_map(H, W, seed=3, dims=2)
+    say("sv 2d 4k bf16")
+    out, b = _run(basis, taps, [8, 8], img, P, io=torch.bfloat16)
+    got = to_np(out)
+    assert max(b.halo) > 24
+    m = int(sum(b.halo))
+    xb = bf16_round(img)
+    rng = np.random.default_rng(4)
+    for _ in range(2):
+        y0, x0 = int(rng.integers(m, H - 32 - m)), int(rng.integers(m, W - 32 - m))
+        win = (slice(y0 - m, y0 + 32 + m), slice(x0 - m, x0 + 32 + m))
+        want = SV.sv_chain(xb[:, win[0], win[1]], P[:, win[0], win[1]].astype(np.float64),
+                           basis.astype(np.float64), [8, 8], taps)[:, m:m + 32, m:m + 32]
+        e = rel_err(got[:, y0:y0 + 32, x0:x0 + 32], want)
+        print(f"sv 2d 4k bf16 crop ({y0},{x0}) halo={b.halo}: {e:.2e}")
+        assert e <= TOL_BF16
+
+
+@pytest.mark.parametrize("C,dims", [(3, 1), (4, 2), (1, 1)])
+def test_sv_large_halo_global_path(dev, C, dims):
+    """Halos whose staged tile exceeds the LDS (offsets up to ~45 px for C = 3, 4)
+    take the one-pixel-per-thread kernel; same results."""
+    taps = [5, 6]
+    G = 6 if dims == 1 else 9
+    basis = _basis(G, taps, seed=500 + C, r0=30.0, dr=3.0)
+    H, W = 96, 150
+    img = noise_image(H, W, C, seed=C, n_rects=8)
+    P = param_map(H, W, seed=7, period=64.0, dims=dims)
+    grid = [G] if dims == 1 else [3, 3]
+    say("sv large halo", C, dims)
+    out, b = _run(basis, taps, grid, img, P)
+    assert max(b.halo) > 33
+    want = SV.sv_chain(img.astype(np.float64), P.astype(np.float64), basis.astype(np.float64), grid, taps)
+    assert rel_err(to_np(out), want) <= TOL_F32
