@@ -35,6 +35,8 @@ def parse():
     ap.add_argument("--basis", choices=["fitted", "random"], default="fitted")
     ap.add_argument("--no-time-to-40db", action="store_true")
     ap.add_argument("--no-2d", action="store_true")
+    ap.add_argument("--time-to-40db-only", action="store_true",
+                    help="only run the batched-optimisation comparison (for profiling it)")
     ap.add_argument("--copy-reference", type=int, default=0, metavar="MIB",
                     help="only run 5 plain device copies of MIB MiB (the scale for HBM byte counters) and exit")
     return ap.parse_args()
@@ -160,6 +162,48 @@ def sv2d_4k(torch, disk, steps=20):
             "basis_build_s": round(build_s, 3), "basis_psnr_db_mean": round(float(ps.mean()), 2)}
 
 
+def small_workloads(torch, disk):
+    """The two small optimisation workloads.  tiny: one 31 x 31 Gaussian
+    (sigma 6), 3 x 8 taps, radial init, 300 Adam steps at lr 1e-2, then the
+    fitted filter on a 256 x 256 U[0,1) image (CLAMP).  shapes: 256 polygon /
+    ring / star targets of 63 x 63, 4 x 12 taps, shape-aware init (host), 500
+    steps, lr 1e-2 -> 1e-3."""
+    from synth import gaussian_kernel, shape_batch, uniform_image
+    out = {}
+    taps = [8, 8, 8]
+    bt = disk.make_batch(*disk.pack_targets([gaussian_kernel(31, 6.0)], taps))
+    th = disk.disk_init_radial(bt)
+    prm = disk.OptParams(max_steps=300, lr0=1e-2, lr1=1e-2)
+    disk.disk_optimize_batch(bt, th.clone(), prm)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    ps, st, _ = disk.disk_optimize_batch(bt, th, prm)
+    torch.cuda.synchronize()
+    opt_s = time.perf_counter() - t
+    img = torch.as_tensor(uniform_image(256, 256, 1, seed=1)).cuda()
+    y, _ = disk.disk_forward(th, taps, img, boundary=disk.CLAMP)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(100):
+        disk.disk_forward(th, taps, img, boundary=disk.CLAMP, out=y)
+    torch.cuda.synchronize()
+    out["tiny_31x31_3x8"] = {"us_per_step": round(opt_s / 300 * 1e6, 2), "total_ms": round(opt_s * 1e3, 3),
+                             "psnr_db": round(float(ps[0]), 2), "apply_256x256_us": round((time.perf_counter() - t) * 1e4, 2)}
+    b = shape_batch(256, 63, 4, 12, seed=4)
+    th = torch.cat([disk.disk_init_shape(k, [12] * 4, seed=4, index=i)[0] for i, k in enumerate(b.kernels)])
+    bt = disk.make_batch(*disk.pack_targets(b.kernels, [12] * 4))
+    th = th.cuda().contiguous()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    ps, st, _ = disk.disk_optimize_batch(bt, th, disk.OptParams(max_steps=500, lr0=1e-2, lr1=1e-3))
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t
+    ps = ps.cpu().numpy()
+    out["shapes_63x63_x256_4x12"] = {"seconds": round(sec, 3), "us_per_target_step": round(sec / (256 * 500) * 1e6, 3),
+                                      "median_psnr_db": round(float(np.median(ps)), 2)}
+    return out
+
+
 def time_to_40db(torch, disk, n=4096):
     """Batched optimisation of n fresh targets (odd sides 15..127, the shape
     families of the batching workload, 4 layers x 12 taps, seed 7) to 40 dB or
@@ -231,6 +275,9 @@ def main():
         return
     import paper_2512_04556_amd as disk
     from synth import noise_image, param_map
+    if a.time_to_40db_only:
+        print(json.dumps(time_to_40db(torch, disk)), flush=True)
+        return
 
     img = noise_image(H, W, C, seed=2)
     P = param_map(H, W, seed=3)
@@ -289,6 +336,7 @@ def main():
     if fit_info:
         res["config"]["basis_fit"] = fit_info
     res["dense_reference"] = dense_reference(torch, disk, x, p, out, ms)
+    res["small_workloads"] = small_workloads(torch, disk)
     if not a.no_2d:
         res["sv2d_4k_bf16"] = sv2d_4k(torch, disk)
     if not a.no_time_to_40db:

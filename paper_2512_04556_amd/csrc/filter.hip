@@ -220,10 +220,10 @@ __device__ __forceinline__ void gather_tap4(float* acc, float basef, float rowBf
 // 128-bit read serves 32 lanes per cycle: two 16-pixel lane rows.  With float4
 // pixels the two rows of a pass are conflict-free when their starts are 256 B
 // apart modulo 512 B, so the C >= 3 stride is padded to 64 dwords mod 128.
-__host__ __device__ __forceinline__ int sv_row_dwords(int halo, int C) {
+__host__ __device__ __forceinline__ int sv_row_dwords(int halo, int C, bool pad = true) {
     if (C >= 3) {
         const int raw = (kTW + 2 * halo) * 4;
-        return raw + ((64 - raw % 128) + 128) % 128;
+        return pad ? raw + ((64 - raw % 128) + 128) % 128 : raw;
     }
     const int raw = (kTW + 2 * halo) * C;
     const int target = C == 1 ? 16 : C == 2 ? 33 : C == 3 ? 48 : 1;
@@ -427,7 +427,7 @@ template <int C, int DIMS, typename TIn, typename TOut, int PY, int NW>
 __global__ __launch_bounds__(64 * NW) void sv_pass_kernel(
     const TIn* __restrict__ X, TOut* __restrict__ Y, const float* __restrict__ P,
     const float* __restrict__ table, int tap0, int N, int T, int G0, int G1, int H, int W, int halo,
-    int tiles_x, int per, int ntiles, const int* __restrict__ flag) {
+    int tiles_x, int per, int ntiles, const int* __restrict__ flag, int rowW) {
     extern __shared__ float lds[];
     constexpr int TH = 4 * PY * (NW / 4);
     const int tile = xcd_tile(blockIdx.x, per);
@@ -447,7 +447,6 @@ __global__ __launch_bounds__(64 * NW) void sv_pass_kernel(
     }
 
     const int SX = kTW + 2 * halo, SY = TH + 2 * halo;
-    const int rowW = sv_row_dwords(halo, C);
     // decode loads first: their latency overlaps the staging below
     const int xc = min(x, W - 1);
     float pv[PY][DIMS];
@@ -520,7 +519,7 @@ template <int C, int DIMS, typename TIn, typename TOut, int NW, int HMAX>
 __global__ __launch_bounds__(64 * NW) void sv_pass_pipe_kernel(
     const TIn* __restrict__ X, TOut* __restrict__ Y, const float* __restrict__ P,
     const float* __restrict__ table, int tap0, int N, int T, int G0, int G1, int H, int W, int halo,
-    int tiles_x, int per, int ntiles, const int* __restrict__ flag) {
+    int tiles_x, int per, int ntiles, const int* __restrict__ flag, int rowW) {
     extern __shared__ float lds[];
     constexpr int PY = kPipePY;
     constexpr int TH = PipeShape<NW, HMAX>::TH;
@@ -543,7 +542,6 @@ __global__ __launch_bounds__(64 * NW) void sv_pass_pipe_kernel(
     }
 
     const int SX = kTW + 2 * halo, SY = TH + 2 * halo;
-    const int rowW = sv_row_dwords(halo, C);
     const int rowB = rowW * 4;
     constexpr int PXB = C >= 3 ? 16 : 4 * C;
     const int base0 = lds_offset(lds) + (lyb + halo) * rowB + (lx + halo) * PXB;
@@ -697,8 +695,8 @@ static int env_int(const char* name, int dflt) {
 }
 
 // LDS bytes of a tile of 4*rows rows.
-size_t sv_lds_bytes(int halo, int C, int rows) {
-    return static_cast<size_t>(sv_row_dwords(halo, C)) * (4 * rows + 2 * halo) * sizeof(float);
+size_t sv_lds_bytes(int halo, int C, int rows, bool pad) {
+    return static_cast<size_t>(sv_row_dwords(halo, C, pad)) * (4 * rows + 2 * halo) * sizeof(float);
 }
 
 int sv_rows_per_wave(int halo, int C) { return sv_lds_bytes(halo, C, 8) <= 160 * 1024 ? 4 : 2; }
@@ -722,6 +720,7 @@ static hipError_t launch_pipe(const void* src, void* dst, const float* pmap, con
     const int ntiles = tiles_x * tiles_y;
     const int per = (ntiles + 7) / 8;
     const size_t lds = sv_lds_bytes(halo, C, kPipePY * (NW / 4));
+    const int rowW = sv_row_dwords(halo, C);
     auto fn = sv_pass_pipe_kernel<C, DIMS, TIn, TOut, NW, HMAX>;
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
@@ -733,25 +732,27 @@ static hipError_t launch_pipe(const void* src, void* dst, const float* pmap, con
     per_xcd = std::max(1, std::min(per_xcd, per));
     hipLaunchKernelGGL(fn, dim3(8 * per_xcd), dim3(64 * NW), lds, s, static_cast<const TIn*>(src),
                        static_cast<TOut*>(dst), pmap, table, tap0, N, T, G0, G1, H, W, halo, tiles_x, per, ntiles,
-                       flag);
+                       flag, rowW);
     return hipGetLastError();
 }
 
 template <int C, int DIMS, typename TIn, typename TOut, int PY, int NW>
 static hipError_t launch_tiles(const void* src, void* dst, const float* pmap, const float* table, int tap0, int N,
-                               int T, int G0, int G1, int H, int W, int halo, const int* flag, hipStream_t s) {
+                               int T, int G0, int G1, int H, int W, int halo, const int* flag, hipStream_t s,
+                               bool pad = true) {
     constexpr int TH = 4 * PY * (NW / 4);
     const int tiles_x = (W + kTW - 1) / kTW, tiles_y = (H + TH - 1) / TH;
     const int ntiles = tiles_x * tiles_y;
     const int per = (ntiles + 7) / 8;
-    const size_t lds = sv_lds_bytes(halo, C, PY * (NW / 4));
+    const size_t lds = sv_lds_bytes(halo, C, PY * (NW / 4), pad);
+    const int rowW = sv_row_dwords(halo, C, pad);
     auto fn = sv_pass_kernel<C, DIMS, TIn, TOut, PY, NW>;
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(fn, dim3(8 * per), dim3(64 * NW), lds, s, static_cast<const TIn*>(src),
                        static_cast<TOut*>(dst), pmap, table, tap0, N, T, G0, G1, H, W, halo, tiles_x, per,
-                       ntiles, flag);
+                       ntiles, flag, rowW);
     return hipGetLastError();
 }
 
@@ -771,6 +772,10 @@ static hipError_t launch_typed(const void* src, void* dst, const float* pmap, co
         return launch_tiles<C, DIMS, TIn, TOut, 4, 8>(src, dst, pmap, table, tap0, N, T, G0, G1, H, W, halo, flag, s);
     if (sv_lds_bytes(halo, C, 2) <= 160 * 1024)
         return launch_tiles<C, DIMS, TIn, TOut, 2, 4>(src, dst, pmap, table, tap0, N, T, G0, G1, H, W, halo, flag, s);
+    // without the bank padding the staged tile fits for a few more halo values
+    if (sv_lds_bytes(halo, C, 2, false) <= 160 * 1024)
+        return launch_tiles<C, DIMS, TIn, TOut, 2, 4>(src, dst, pmap, table, tap0, N, T, G0, G1, H, W, halo, flag, s,
+                                                      false);
     const long px = static_cast<long>(H) * W;
     hipLaunchKernelGGL((sv_pass_global_kernel<C, DIMS, TIn, TOut>), dim3(static_cast<unsigned>((px + 255) / 256)),
                        dim3(256), 0, s, static_cast<const TIn*>(src), static_cast<TOut*>(dst), pmap, table, tap0, N,

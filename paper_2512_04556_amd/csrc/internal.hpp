@@ -68,7 +68,7 @@ size_t sv_table_floats(int dims, int G, int T);
 hipError_t launch_sv_prep(int dims, int G0, int G1, const LayerSpec& spec, const int* halo,
                           const float* basis, float* table, int* flag, hipStream_t s);
 int sv_rows_per_wave(int halo, int C);
-size_t sv_lds_bytes(int halo, int C, int py);
+size_t sv_lds_bytes(int halo, int C, int py, bool pad = true);
 hipError_t launch_sv_pass(int C, int dims, int src_bf16, const void* src, int dst_bf16, void* dst,
                           const float* pmap, const float* table, int tap0, int N, int T, int G0,
                           int G1, int H, int W, int halo, const int* flag, hipStream_t s);

@@ -21,6 +21,7 @@
 // stays high from M = 15 to M = 255.  All reductions are fixed-order wave
 // butterflies plus an ordered LDS combine: results are bitwise reproducible.
 #include <algorithm>
+#include <cstdlib>
 #include <cmath>
 
 #include "common.hpp"
@@ -479,12 +480,19 @@ hipError_t launch_continue(const disk_target* desc, const int* taps, float* thet
     return hipGetLastError();
 }
 
+// Resident work-groups: `per_cu` per compute unit (DISK_OPT_WGS_PER_CU, a
+// tuning override read once; default 2).
 int opt_workgroups(int B) {
     int dev = 0, n = 0;
     if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
         n <= 0)
         n = 256;
-    return std::max(1, std::min(B, 2 * n));
+    static const int per_cu = [] {
+        const char* e = std::getenv("DISK_OPT_WGS_PER_CU");
+        const int v = e ? std::atoi(e) : 2;
+        return v >= 1 && v <= 16 ? v : 2;
+    }();
+    return std::max(1, std::min(B, per_cu * n));
 }
 
 size_t opt_slot_floats(int max_side, int max_L) {

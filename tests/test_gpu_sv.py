@@ -176,3 +176,18 @@ def test_sv_large_halo_global_path(dev, C, dims):
     assert max(b.halo) > 33
     want = SV.sv_chain(img.astype(np.float64), P.astype(np.float64), basis.astype(np.float64), grid, taps)
     assert rel_err(to_np(out), want) <= TOL_F32
+
+
+def test_sv_halo_just_beyond_padded_tile(dev):
+    """C = 3 with halos 31..33: the staged tile only fits the LDS without the
+    bank padding (one-tile kernel, unpadded stride)."""
+    taps = [6, 6]
+    basis = _basis(6, taps, seed=610, r0=29.6, dr=0.38)
+    H, W = 80, 170
+    img = noise_image(H, W, 3, seed=3, n_rects=8)
+    P = param_map(H, W, seed=8, period=64.0)
+    say("sv halo 31-33")
+    out, b = _run(basis, taps, [6], img, P)
+    assert 31 <= max(b.halo) <= 33
+    want = SV.sv_chain(img.astype(np.float64), P.astype(np.float64), basis.astype(np.float64), [6], taps)
+    assert rel_err(to_np(out), want) <= TOL_F32
