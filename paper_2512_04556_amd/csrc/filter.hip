@@ -768,14 +768,12 @@ static hipError_t launch_typed(const void* src, void* dst, const float* pmap, co
     if (pipe && halo <= kPipeHalo && sv_lds_bytes(halo, C, kPipePY * 4) <= 160 * 1024)
         return launch_pipe<C, DIMS, TIn, TOut, 16, kPipeHalo>(src, dst, pmap, table, tap0, N, T, G0, G1, H, W, halo,
                                                               flag, s);
+    // A staged tile pays for its halo only when it is tall: 64 x 32 tiles while
+    // they fit; below that the halo rows dominate (measured: an 8-row tile at
+    // halo 33 is slower than reading the corners through L1), so larger halos
+    // take the one-pixel-per-thread kernel.
     if (sv_rows_per_wave(halo, C) == 4)
         return launch_tiles<C, DIMS, TIn, TOut, 4, 8>(src, dst, pmap, table, tap0, N, T, G0, G1, H, W, halo, flag, s);
-    if (sv_lds_bytes(halo, C, 2) <= 160 * 1024)
-        return launch_tiles<C, DIMS, TIn, TOut, 2, 4>(src, dst, pmap, table, tap0, N, T, G0, G1, H, W, halo, flag, s);
-    // without the bank padding the staged tile fits for a few more halo values
-    if (sv_lds_bytes(halo, C, 2, false) <= 160 * 1024)
-        return launch_tiles<C, DIMS, TIn, TOut, 2, 4>(src, dst, pmap, table, tap0, N, T, G0, G1, H, W, halo, flag, s,
-                                                      false);
     const long px = static_cast<long>(H) * W;
     hipLaunchKernelGGL((sv_pass_global_kernel<C, DIMS, TIn, TOut>), dim3(static_cast<unsigned>((px + 255) / 256)),
                        dim3(256), 0, s, static_cast<const TIn*>(src), static_cast<TOut*>(dst), pmap, table, tap0, N,

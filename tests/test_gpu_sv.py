@@ -179,8 +179,8 @@ def test_sv_large_halo_global_path(dev, C, dims):
 
 
 def test_sv_halo_just_beyond_padded_tile(dev):
-    """C = 3 with halos 31..33: the staged tile only fits the LDS without the
-    bank padding (one-tile kernel, unpadded stride)."""
+    """C = 3 with halos 31..33, just beyond the staged kernels (the
+    one-pixel-per-thread kernel)."""
     taps = [6, 6]
     basis = _basis(6, taps, seed=610, r0=29.6, dr=0.38)
     H, W = 80, 170
