@@ -111,49 +111,78 @@ __device__ __forceinline__ float masked(const float* buf, int x, int y, int dx, 
     return buf[(yy + P) * S + xx + P];
 }
 
+__device__ __forceinline__ bool tap_inside(const TapO& t, int P) {
+    return t.ix >= -P && t.ix <= P - 1 && t.iy >= -P && t.iy <= P - 1;
+}
+
+// One tap's contribution at a pixel: forward p + (ix+a, iy+b); transpose q - (ix+a, iy+b).
+template <int SGN>
+__device__ __forceinline__ float gather_tap(float acc, const TapO& t, const float* __restrict__ src, int base, int x,
+                                            int y, const Walk& wk) {
+    const int M = wk.M, S = wk.S, P = wk.P;
+    if (tap_inside(t, P)) {
+        const float* q = src + base + SGN * (t.iy * S + t.ix);
+        acc = fmaf(t.c00, q[0], acc);
+        acc = fmaf(t.c01, q[SGN], acc);
+        acc = fmaf(t.c10, q[SGN * S], acc);
+        acc = fmaf(t.c11, q[SGN * (S + 1)], acc);
+    } else {
+        const int xc = min(x, M - 1), yc = min(y, M - 1);
+        acc = fmaf(t.c00, masked(src, xc, yc, SGN * t.ix, SGN * t.iy, M, S, P), acc);
+        acc = fmaf(t.c01, masked(src, xc, yc, SGN * (t.ix + 1), SGN * t.iy, M, S, P), acc);
+        acc = fmaf(t.c10, masked(src, xc, yc, SGN * t.ix, SGN * (t.iy + 1), M, S, P), acc);
+        acc = fmaf(t.c11, masked(src, xc, yc, SGN * (t.ix + 1), SGN * (t.iy + 1), M, S, P), acc);
+    }
+    return acc;
+}
+
 // dst[p] = sum_taps sum_ab c_ab src[p + sgn * d_ab] over the interior (sgn = +1:
-// forward gather; sgn = -1: the transpose, used for G_{l-1}).
+// forward gather; sgn = -1: the transpose, used for G_{l-1}).  Taps go four at
+// a time: when all four stay inside the zero frame their 16 reads are issued
+// together before the FMAs (same accumulation order as one tap at a time).
 template <int SGN>
 __device__ void gather_layer(const float* __restrict__ src, float* __restrict__ dst, const TapO* tp, int N,
                              const Walk& wk) {
     const int wave = threadIdx.x >> 6;
-    const int M = wk.M, S = wk.S, P = wk.P;
+    const int S = wk.S, P = wk.P;
     for (int blk = wave; blk < wk.nblk; blk += kOptWaves) {
         int x, y;
         bool act;
         const int base = wk.pixel(blk, x, y, act);
         float acc = 0.0f;
-        for (int i = 0; i < N; ++i) {
-            const TapO t = tp[i];
-            // corner offsets: forward p + (ix+a, iy+b); transpose q - (ix+a, iy+b)
-            const bool inside = t.ix >= -P && t.ix <= P - 1 && t.iy >= -P && t.iy <= P - 1;
-            if (inside) {
-                if (SGN > 0) {
-                    const float* q = src + base + t.iy * S + t.ix;
-                    acc = fmaf(t.c00, q[0], acc);
-                    acc = fmaf(t.c01, q[1], acc);
-                    acc = fmaf(t.c10, q[S], acc);
-                    acc = fmaf(t.c11, q[S + 1], acc);
-                } else {
-                    const float* q = src + base - t.iy * S - t.ix;
-                    acc = fmaf(t.c00, q[0], acc);
-                    acc = fmaf(t.c01, q[-1], acc);
-                    acc = fmaf(t.c10, q[-S], acc);
-                    acc = fmaf(t.c11, q[-S - 1], acc);
+        int i = 0;
+        for (; i + 4 <= N; i += 4) {
+            TapO t[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) t[k] = tp[i + k];
+            if (tap_inside(t[0], P) && tap_inside(t[1], P) && tap_inside(t[2], P) && tap_inside(t[3], P)) {
+                float v[4][4];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const float* q = src + base + SGN * (t[k].iy * S + t[k].ix);
+                    v[k][0] = q[0];
+                    v[k][1] = q[SGN];
+                    v[k][2] = q[SGN * S];
+                    v[k][3] = q[SGN * (S + 1)];
+                }
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    acc = fmaf(t[k].c00, v[k][0], acc);
+                    acc = fmaf(t[k].c01, v[k][1], acc);
+                    acc = fmaf(t[k].c10, v[k][2], acc);
+                    acc = fmaf(t[k].c11, v[k][3], acc);
                 }
             } else {
-                const int xc = min(x, M - 1), yc = min(y, M - 1);
-                acc = fmaf(t.c00, masked(src, xc, yc, SGN * t.ix, SGN * t.iy, M, S, P), acc);
-                acc = fmaf(t.c01, masked(src, xc, yc, SGN * (t.ix + 1), SGN * t.iy, M, S, P), acc);
-                acc = fmaf(t.c10, masked(src, xc, yc, SGN * t.ix, SGN * (t.iy + 1), M, S, P), acc);
-                acc = fmaf(t.c11, masked(src, xc, yc, SGN * (t.ix + 1), SGN * (t.iy + 1), M, S, P), acc);
+#pragma unroll
+                for (int k = 0; k < 4; ++k) acc = gather_tap<SGN>(acc, t[k], src, base, x, y, wk);
             }
         }
+        for (; i < N; ++i) acc = gather_tap<SGN>(acc, tp[i], src, base, x, y, wk);
         if (act) dst[base] = acc;
     }
 }
 
-__global__ __launch_bounds__(kOptThreads) void opt_kernel(OptArgs a) {
+__global__ __launch_bounds__(kOptThreads, 4) void opt_kernel(OptArgs a) {
     __shared__ float th[kMaxT * 3], am[kMaxT * 3], av[kMaxT * 3], gr[kMaxT * 3];
     __shared__ TapO tap[kMaxT];
     __shared__ float sS[kMaxT][4];
@@ -322,6 +351,44 @@ __global__ __launch_bounds__(kOptThreads) void opt_kernel(OptArgs a) {
                         for (int k = 0; k < kChunk; ++k)
 #pragma unroll
                             for (int ab = 0; ab < 4; ++ab) s[k][ab] = 0.0f;
+                        // the chunk's canvas offsets (wave-uniform); when all taps stay
+                        // inside the zero frame the 4 kChunk reads of a pixel go out together
+                        int off[kChunk];
+                        bool all_in = nc == kChunk;
+#pragma unroll
+                        for (int k = 0; k < kChunk; ++k) {
+                            off[k] = 0;
+                            if (k < nc) {
+                                const TapO t = tp[i0 + k];
+                                off[k] = uniform(t.iy * S + t.ix);
+                                all_in = all_in && tap_inside(t, P);
+                            }
+                        }
+                        if (all_in) {
+                            for (int blk = wave; blk < wk.nblk; blk += kOptWaves) {
+                                int x, y;
+                                bool act;
+                                const int base = wk.pixel(blk, x, y, act);
+                                const float g = act ? G[base] : 0.0f;
+#pragma unroll
+                                for (int k0 = 0; k0 < kChunk; k0 += 4) {
+                                    float v[4][4];
+#pragma unroll
+                                    for (int k = 0; k < 4; ++k) {
+                                        const float* q = X + base + off[k0 + k];
+                                        v[k][0] = q[0];
+                                        v[k][1] = q[1];
+                                        v[k][2] = q[S];
+                                        v[k][3] = q[S + 1];
+                                    }
+#pragma unroll
+                                    for (int k = 0; k < 4; ++k)
+#pragma unroll
+                                        for (int ab = 0; ab < 4; ++ab)
+                                            s[k0 + k][ab] = fmaf(g, v[k][ab], s[k0 + k][ab]);
+                                }
+                            }
+                        } else {
                         for (int blk = wave; blk < wk.nblk; blk += kOptWaves) {
                             int x, y;
                             bool act;
@@ -332,7 +399,7 @@ __global__ __launch_bounds__(kOptThreads) void opt_kernel(OptArgs a) {
                                 if (k < nc) {
                                     const TapO t = tp[i0 + k];
                                     float v00, v01, v10, v11;
-                                    if (t.ix >= -P && t.ix <= P - 1 && t.iy >= -P && t.iy <= P - 1) {
+                                    if (tap_inside(t, P)) {
                                         const float* q = X + base + t.iy * S + t.ix;
                                         v00 = q[0];
                                         v01 = q[1];
@@ -351,6 +418,7 @@ __global__ __launch_bounds__(kOptThreads) void opt_kernel(OptArgs a) {
                                     s[k][3] = fmaf(g, v11, s[k][3]);
                                 }
                             }
+                        }
                         }
                         // fixed-order reduction of the chunk's 4 * nc sums
 #pragma unroll
