@@ -87,16 +87,17 @@ __device__ __forceinline__ float wg_max(float v, float* red) {
 
 // Lane geometry of an 8 x 8 block walk.
 struct Walk {
-    int M, S, P, nbx, nblk;
+    int M, S, P, nbx, nblk, inv;
     __device__ Walk(int M_, int S_, int P_) : M(M_), S(S_), P(P_) {
         nbx = (M + 7) >> 3;
         nblk = nbx * nbx;
+        inv = (65536 + nbx - 1) / nbx;   // blk / nbx == (blk * inv) >> 16 for nbx <= 32, blk < 1024
     }
     // pixel of block `blk` for this lane; `act` false for lanes past the edge
     // (their index is clamped onto the canvas so every read stays in bounds)
     __device__ __forceinline__ int pixel(int blk, int& x, int& y, bool& act) const {
         const int lane = threadIdx.x & 63;
-        const int by = blk / nbx, bx = blk - by * nbx;
+        const int by = (blk * inv) >> 16, bx = blk - by * nbx;
         x = (bx << 3) + (lane & 7);
         y = (by << 3) + (lane >> 3);
         act = x < M && y < M;
