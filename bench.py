@@ -35,6 +35,7 @@ def parse():
     ap.add_argument("--basis", choices=["fitted", "random"], default="fitted")
     ap.add_argument("--no-time-to-40db", action="store_true")
     ap.add_argument("--no-2d", action="store_true")
+    ap.add_argument("--no-ablations", action="store_true")
     ap.add_argument("--time-to-40db-only", action="store_true",
                     help="only run the batched-optimisation comparison (for profiling it)")
     ap.add_argument("--copy-reference", type=int, default=0, metavar="MIB",
@@ -204,6 +205,50 @@ def small_workloads(torch, disk):
     return out
 
 
+def ablations(torch, disk):
+    """Initialisation and structure ablations on procedural kernels (the
+    paper's init comparison and its layers x samples trade-off), and the
+    paper's own optimisation recipe.  Targets: 256 hexagon / pentagon / ring /
+    star kernels of 63 x 63 (seed 4), 4 x 12 taps, 500 Adam steps at lr
+    1e-2 -> 1e-3, normalised MSE, unless stated."""
+    from synth import shape_batch
+    from paper_2512_04556_amd import train_init
+    taps = [12, 12, 12, 12]
+    b = shape_batch(256, 63, 4, 12, seed=4)
+    bt = disk.make_batch(*disk.pack_targets(b.kernels, taps))
+    prm = disk.OptParams(max_steps=500, lr0=1e-2, lr1=1e-3)
+
+    def run(theta, p=prm, batch=bt):
+        th = theta.cuda().contiguous()
+        ps, st, _ = disk.disk_optimize_batch(batch, th, p)
+        ps = ps.cpu().numpy()
+        return {"median_psnr_db": round(float(np.median(ps)), 2), "mean_psnr_db": round(float(np.mean(ps)), 2)}
+
+    out = {"targets": "256 shapes 63x63, 4x12 taps, 500 steps"}
+    inits = {
+        "random": torch.cat([disk.disk_init_random(k, taps, seed=4, index=i)[0] for i, k in enumerate(b.kernels)]),
+        "radial": disk.disk_init_radial(bt),
+        "shape_aware": torch.cat([disk.disk_init_shape(k, taps, seed=4, index=i)[0] for i, k in enumerate(b.kernels)]),
+    }
+    try:
+        x, hw = disk.disk_net_prepare_inputs(bt)
+        inits["learned"] = disk.disk_net_scatter_theta(bt, disk.disk_init_predict(train_init.load(), x, hw))
+    except (OSError, ValueError):
+        pass
+    out["init"] = {k: run(v) for k, v in inits.items()}
+    # the paper's recipe: Charbonnier loss, lr 1e-3 -> 1e-4 over 1000 steps (shape-aware init)
+    paper = disk.OptParams(max_steps=1000, lr0=1e-3, lr1=1e-4, loss=disk.LOSS_CHARBONNIER, charb_eps=1e-3)
+    out["paper_recipe_charbonnier_1e-3"] = run(inits["shape_aware"], paper)
+    # layers x samples at a fixed budget of 48 taps, rings (radial init)
+    rings = shape_batch(64, 63, 4, 12, seed=9, kinds=("ring",))
+    lxn = {}
+    for L, N in ((2, 24), (3, 16), (4, 12), (6, 8)):
+        rb = disk.make_batch(*disk.pack_targets(rings.kernels, [N] * L))
+        lxn[f"{L}x{N}"] = run(disk.disk_init_radial(rb), prm, rb)
+    out["rings_layers_x_taps"] = lxn
+    return out
+
+
 def time_to_40db(torch, disk, n=4096):
     """Batched optimisation of n fresh targets (odd sides 15..127, the shape
     families of the batching workload, 4 layers x 12 taps, seed 7) to 40 dB or
@@ -337,6 +382,8 @@ def main():
         res["config"]["basis_fit"] = fit_info
     res["dense_reference"] = dense_reference(torch, disk, x, p, out, ms)
     res["small_workloads"] = small_workloads(torch, disk)
+    if not a.no_ablations:
+        res["ablations"] = ablations(torch, disk)
     if not a.no_2d:
         res["sv2d_4k_bf16"] = sv2d_4k(torch, disk)
     if not a.no_time_to_40db:

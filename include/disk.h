@@ -219,6 +219,18 @@ disk_status disk_init_radial(const disk_batch_meta* meta, const disk_target* des
 disk_status disk_init_shape(const float* target, int32_t M, int32_t L, const int32_t* taps,
                             uint64_t seed, int32_t index, float* theta, double* r_out);
 
+/*
+ * Random-position initialisation (the baseline the shape-aware init is
+ * compared with, Sec. 4.2), on the host in FP64: tap i of layer l uniform in
+ * [-r_l, r_l]^2 with r_l = l dr the radial rule's radius (Eq. 6), weights
+ * 1/N_l; two draws per tap (x, then y) from the SplitMix64 stream keyed by
+ * (seed, index) as in disk_init_shape.
+ *   target host float [M][M];  taps host int32 [L];  theta host float [T][3];
+ *   R_out (the extent R) or NULL.
+ */
+disk_status disk_init_random(const float* target, int32_t M, int32_t L, const int32_t* taps,
+                             uint64_t seed, int32_t index, float* theta, double* R_out);
+
 /* ------------------------------------------------------------------------- */
 /* Spatially varying filtering by filter-space interpolation (Sec. 4.3).      */
 /* ------------------------------------------------------------------------- */

@@ -16,7 +16,7 @@ import torch
 __all__ = [
     "lib", "DiskError", "ZERO", "CLAMP", "F32", "BF16", "LOSS_NMSE", "LOSS_CHARBONNIER",
     "disk_forward", "disk_backward", "disk_sv_filter", "disk_sv_prepare", "disk_sv_apply", "Basis", "make_basis",
-    "disk_optimize_batch", "disk_init_radial", "disk_fit_basis", "pack_targets", "fit_basis", "disk_init_shape", "OptParams", "Batch", "make_batch",
+    "disk_optimize_batch", "disk_init_radial", "disk_init_random", "disk_fit_basis", "pack_targets", "fit_basis", "disk_init_shape", "OptParams", "Batch", "make_batch",
     "disk_init_predict", "disk_net_train_step", "disk_net_prepare_inputs", "disk_net_scatter_theta",
     "disk_net_param_count", "net_workspace", "clock_rate_khz",
     "disk_dense_sv", "DENSE_DISK", "DENSE_ELLIPSE",
@@ -86,6 +86,7 @@ def lib():
         "disk_fit_basis": (c_int32, [POINTER(DiskBatchMeta), P, P, P, P, P, P, P, POINTER(c_float),
                                      POINTER(DiskOptParams), P, c_size_t, P]),
         "disk_init_shape": (c_int32, [P, c_int32, c_int32, P, c_uint64, c_int32, P, POINTER(c_double)]),
+        "disk_init_random": (c_int32, [P, c_int32, c_int32, P, c_uint64, c_int32, P, POINTER(c_double)]),
         "disk_basis_set_halo": (c_int32, [POINTER(DiskBasis), P]),
         "disk_sv_filter_workspace_size": (c_size_t, [POINTER(DiskBasis), c_int32, c_int32, c_int32, c_int32]),
         "disk_sv_filter": (c_int32, [POINTER(DiskBasis), P, P, P, P, c_int32, c_int32, c_int32, c_int32, P, c_size_t, P]),
@@ -421,6 +422,18 @@ def disk_init_shape(target, taps, seed, index=0):
     r = c_double(0.0)
     _check(lib().disk_init_shape(_ptr(t), int(t.shape[0]), int(tp.numel()), _ptr(tp), c_uint64(int(seed)),
                                  int(index), _ptr(out), ctypes.byref(r)))
+    return out, r.value
+
+
+def disk_init_random(target, taps, seed, index=0):
+    """Host FP64 random-position init of one target.  Returns (theta float32
+    [T][3] CPU tensor, extent R)."""
+    t = torch.as_tensor(target, dtype=torch.float32).contiguous()
+    tp = torch.as_tensor([int(x) for x in taps], dtype=torch.int32).contiguous()
+    out = torch.empty((int(tp.sum()), 3), dtype=torch.float32)
+    r = c_double(0.0)
+    _check(lib().disk_init_random(_ptr(t), int(t.shape[0]), int(tp.numel()), _ptr(tp), c_uint64(int(seed)),
+                                  int(index), _ptr(out), ctypes.byref(r)))
     return out, r.value
 
 

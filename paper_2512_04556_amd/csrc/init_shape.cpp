@@ -11,6 +11,7 @@
 // of key k is mix64(k + (n + 1) * 0x9E3779B97F4A7C15); the key of target b
 // under seed s is output b of key s; a uniform double is (z >> 11) * 2^-53.
 // Compiled with FP contraction off so each double operation rounds as written.
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <vector>
@@ -123,5 +124,62 @@ extern "C" disk_status disk_init_shape(const float* target, int32_t M, int32_t L
     }
     if (L > 1) radial(r, taps + 1, L - 1, 1, theta + 3 * Ns);
     if (r_out) *r_out = r;
+    return DISK_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Random-position initialisation (the baseline of Sec. 4.2): tap i of layer l
+// uniform in [-r_l, r_l]^2 with r_l = l dr the radial rule's radius (Eq. 6,
+// dr = 2R / (L (L + 1)), R = min((M-1)/2, r99)), w = 1 / N_l.  Two draws per
+// tap (x, then y) from the same counter stream as the shape-aware init.
+// ---------------------------------------------------------------------------
+namespace {
+
+// Smallest pixel-centre distance whose closed disk holds >= 99% of the mass:
+// pixels ordered by squared distance (stable), masses accumulated in that order.
+double r99(const float* K, int M) {
+    const int h = (M - 1) / 2;
+    std::vector<std::pair<int, int>> d2i;   // (d2, row-major index)
+    d2i.reserve(static_cast<size_t>(M) * M);
+    for (int y = 0; y < M; ++y)
+        for (int x = 0; x < M; ++x) d2i.emplace_back((x - h) * (x - h) + (y - h) * (y - h), y * M + x);
+    std::stable_sort(d2i.begin(), d2i.end(),
+                     [](const std::pair<int, int>& a, const std::pair<int, int>& b) { return a.first < b.first; });
+    double total = 0.0;
+    for (const auto& p : d2i) total += static_cast<double>(K[p.second]);
+    double cum = 0.0;
+    const size_t n = d2i.size();
+    for (size_t i = 0; i < n; ++i) {
+        cum += static_cast<double>(K[d2i[i].second]);
+        const bool last = i + 1 == n || d2i[i + 1].first != d2i[i].first;
+        if (last && cum >= 0.99 * total) return std::sqrt(static_cast<double>(d2i[i].first));
+    }
+    return std::sqrt(static_cast<double>(d2i.back().first));
+}
+
+}  // namespace
+
+extern "C" disk_status disk_init_random(const float* target, int32_t M, int32_t L, const int32_t* taps, uint64_t seed,
+                                        int32_t index, float* theta, double* R_out) {
+    if (!target || !taps || !theta) return DISK_INVALID_ARG;
+    if (M < 1 || (M & 1) == 0 || M > DISK_MAX_SIDE || L < 1 || L > DISK_MAX_LAYERS) return DISK_BAD_SHAPE;
+    for (int l = 0; l < L; ++l)
+        if (taps[l] < 1 || taps[l] > DISK_MAX_TAPS) return DISK_BAD_SHAPE;
+    const double R = std::fmin(0.5 * (M - 1), r99(target, M));
+    const double dr = 2.0 * R / (static_cast<double>(L) * (L + 1));
+    Counter st{mix64(seed + (static_cast<uint64_t>(index) + 1) * kGolden)};
+    int o = 0;
+    for (int l = 0; l < L; ++l) {
+        const double r = (l + 1) * dr;
+        for (int i = 0; i < taps[l]; ++i) {
+            const double ox = (2.0 * st.uniform() - 1.0) * r;
+            const double oy = (2.0 * st.uniform() - 1.0) * r;
+            theta[3 * o + 0] = static_cast<float>(ox);
+            theta[3 * o + 1] = static_cast<float>(oy);
+            theta[3 * o + 2] = static_cast<float>(1.0 / taps[l]);
+            ++o;
+        }
+    }
+    if (R_out) *R_out = R;
     return DISK_OK;
 }

@@ -35,3 +35,22 @@ def test_shape_init_rejects_bad_shapes():
     K = np.ones((9, 9), np.float32)
     with pytest.raises(disk.DiskError):
         disk.disk_init_shape(K, [40], 1)         # too many taps
+
+
+@pytest.mark.parametrize("kind,M,taps,seed,index", [
+    ("ring", 63, [12, 12, 12, 12], 4, 0),
+    ("hex", 41, [8, 6], 9, 17),
+    ("gauss", 31, [8, 8, 8], 2, 5),
+    ("star", 127, [16, 12], 3, 2),
+])
+def test_random_init_matches_oracle(kind, M, taps, seed, index):
+    """The host random-position initialiser against the oracle's: same extent
+    R (r99 over pixel-centre distances) and the same counter stream."""
+    K = {"ring": lambda: ring_kernel(M, 0.9 * (M - 1) / 2, 0.6),
+         "hex": lambda: polygon_kernel(M, 6, 0.9 * (M - 1) / 2, 0.3),
+         "star": lambda: star_kernel(M, 5, 0.9 * (M - 1) / 2, 0.45, 0.2),
+         "gauss": lambda: gaussian_kernel(M, 4.0)}[kind]().astype(np.float32)
+    got, R = disk.disk_init_random(K, taps, seed, index)
+    assert R == I.radial_extent(K.astype(np.float64))
+    want = I.random_init(K.astype(np.float64), taps, seed, index)
+    np.testing.assert_array_equal(got.numpy(), want.astype(np.float32))
