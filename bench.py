@@ -249,6 +249,44 @@ def ablations(torch, disk):
     return out
 
 
+def angle_effects(torch, disk, steps=20):
+    """Angle-driven 2-D effects at 1920x1080x3 FP32: a basis of motion-blur
+    segments (lengths 4, 12, 20, 28 px, 3 x 8 taps, fitted by continuation)
+    rotated to 9 directions over [0, pi] on the device; blur length grows with
+    the distance from the centre; direction along the ray (radial motion blur)
+    or across it (rotational blur)."""
+    from synth import line_kernel, noise_image, direction_map
+    taps = [8, 8, 8]
+    lengths = [4.0, 12.0, 20.0, 28.0]
+    t = time.perf_counter()
+    base, ps, _, _ = disk.fit_basis([line_kernel(l) for l in lengths], taps,
+                                    [1.0] + [lengths[k] / lengths[k - 1] for k in range(1, 4)],
+                                    disk.OptParams(max_steps=500, lr0=1e-2, lr1=1e-3))
+    theta = disk.disk_basis_rotate(base.contiguous(), [np.pi * j / 8 for j in range(9)])
+    torch.cuda.synchronize()
+    build_s = time.perf_counter() - t
+    basis = disk.make_basis(theta, taps, [4, 9])
+    x = torch.as_tensor(noise_image(H, W, C, seed=2)).cuda()
+    out = torch.empty_like(x)
+    ws = disk.sv_filter_workspace(basis, C, H, W)
+    res = {"basis_build_s": round(build_s, 3), "basis_psnr_db": [round(float(v), 2) for v in ps], "halo": basis.halo}
+    stream = torch.cuda.current_stream()
+    for kind in ("radial", "rotational"):
+        p = torch.as_tensor(direction_map(H, W, kind)).cuda()
+        for _ in range(3):
+            disk.disk_sv_filter(basis, x, p, out=out, ws=ws)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(steps):
+            disk.disk_sv_filter(basis, x, p, out=out, ws=ws)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        res[kind] = {"ms_per_frame": round(ms, 4), "mpix_s": round(H * W / ms / 1e3, 1)}
+    return res
+
+
 def time_to_40db(torch, disk, n=4096):
     """Batched optimisation of n fresh targets (odd sides 15..127, the shape
     families of the batching workload, 4 layers x 12 taps, seed 7) to 40 dB or
@@ -382,6 +420,8 @@ def main():
         res["config"]["basis_fit"] = fit_info
     res["dense_reference"] = dense_reference(torch, disk, x, p, out, ms)
     res["small_workloads"] = small_workloads(torch, disk)
+    if not a.no_2d:
+        res["angle_effects_1080p"] = angle_effects(torch, disk)
     if not a.no_ablations:
         res["ablations"] = ablations(torch, disk)
     if not a.no_2d:

@@ -269,6 +269,18 @@ disk_status disk_sv_filter(const disk_basis* b, const float* basis_theta, const 
                            disk_dtype io, void* ws, size_t ws_bytes, hipStream_t stream);
 
 /*
+ * Angle axis for a 2-D basis (the angle-driven effects, rotational bokeh and
+ * radial motion blur, of the paper's spatially varying examples): entry
+ * (i0, i1), stored at i0 * G1 + i1, is base entry i0 with every offset
+ * rotated counter-clockwise by angles[i1]: (ox cos a - oy sin a,
+ * ox sin a + oy cos a); weights copied.  Tap i keeps its role across angles.
+ *   base   device float [G0][T][3];   angles host double [G1] (radians), 1 <= G1 <= 64;
+ *   out    device float [G0 * G1][T][3] (written; must not overlap base).
+ */
+disk_status disk_basis_rotate(const float* base, int32_t G0, int32_t T, const double* angles, int32_t G1,
+                              float* out, hipStream_t stream);
+
+/*
  * The same filter in two steps, for a basis that serves many frames (the
  * offline/runtime split of Sec. 4.3): disk_sv_prepare turns the basis into the
  * per-(entry, tap) coefficient table the passes read (and checks the halos);

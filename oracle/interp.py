@@ -80,3 +80,19 @@ def tap_field(basis, P, grid, tap):
              + ((1 - s) * t)[..., None] * basis[k0 * G1 + k1b, tap]
              + (s * t)[..., None] * basis[k0b * G1 + k1b, tap])
     return v[..., 0], v[..., 1], v[..., 2]
+
+
+def rotate_basis(base, angles):
+    """Angle axis of a 2-D basis (angle-driven effects of Sec. 5): entry
+    (i0, i1) is base entry i0 with every offset rotated by angles[i1]
+    (counter-clockwise in (x, y)); weights unchanged.  Returns [G0 * G1][T][3]."""
+    base = np.asarray(base, dtype=np.float64)
+    out = []
+    for b in base:
+        for a in angles:
+            c, s = np.cos(a), np.sin(a)
+            r = b.copy()
+            r[:, 0] = c * b[:, 0] - s * b[:, 1]
+            r[:, 1] = s * b[:, 0] + c * b[:, 1]
+            out.append(r)
+    return np.stack(out)

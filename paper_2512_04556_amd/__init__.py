@@ -19,7 +19,7 @@ __all__ = [
     "disk_optimize_batch", "disk_init_radial", "disk_init_random", "disk_fit_basis", "pack_targets", "fit_basis", "disk_init_shape", "OptParams", "Batch", "make_batch",
     "disk_init_predict", "disk_net_train_step", "disk_net_prepare_inputs", "disk_net_scatter_theta",
     "disk_net_param_count", "net_workspace", "clock_rate_khz",
-    "disk_dense_sv", "DENSE_DISK", "DENSE_ELLIPSE",
+    "disk_dense_sv", "DENSE_DISK", "DENSE_ELLIPSE", "disk_basis_rotate",
 ]
 
 ZERO, CLAMP = 0, 1
@@ -80,6 +80,7 @@ def lib():
         "disk_optimize_batch": (c_int32, [POINTER(DiskBatchMeta), P, P, P, P, P, P, P, P, POINTER(DiskOptParams), P,
                                           c_size_t, P]),
         "disk_clock_rate_khz": (c_int64, []),
+        "disk_basis_rotate": (c_int32, [P, c_int32, c_int32, POINTER(c_double), c_int32, P, P]),
         "disk_dense_sv": (c_int32, [POINTER(DiskDenseParams), P, P, P, c_int32, c_int32, c_int32, c_int32, P]),
         "disk_init_radial": (c_int32, [POINTER(DiskBatchMeta), P, P, P, P, P]),
         "disk_fit_basis_workspace_size": (c_size_t, [POINTER(DiskBatchMeta)]),
@@ -333,6 +334,18 @@ def disk_optimize_batch(batch: Batch, theta, params: OptParams, ticks=None):
                                  _ptr(theta), _ptr(psnr), _ptr(steps), _ptr(status), _ptr(ticks),
                                  ctypes.byref(params.c), _ptr(ws), ws.numel(), _stream()))
     return psnr, steps, status
+
+
+def disk_basis_rotate(base, angles):
+    """Angle axis: base [G0][T][3] (device) -> [G0 * len(angles)][T][3] with
+    every offset rotated by each angle (radians)."""
+    _dev(base, "base")
+    G0, T = int(base.shape[0]), int(base.shape[1])
+    G1 = len(angles)
+    out = torch.empty((G0 * G1, T, 3), dtype=torch.float32, device=base.device)
+    ang = (c_double * G1)(*[float(a) for a in angles])
+    _check(lib().disk_basis_rotate(_ptr(base.contiguous()), G0, T, ang, G1, _ptr(out), _stream()))
+    return out
 
 
 DENSE_DISK, DENSE_ELLIPSE = 0, 1

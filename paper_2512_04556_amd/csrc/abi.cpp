@@ -522,6 +522,23 @@ disk_status disk_init_radial(const disk_batch_meta* meta, const disk_target* des
     return ok();
 }
 
+disk_status disk_basis_rotate(const float* base, int32_t G0, int32_t T, const double* angles, int32_t G1,
+                              float* out, hipStream_t stream) {
+    if (G0 < 1 || G1 < 1 || G1 > 64 || T < 1 || T > DISK_MAX_LAYERS * DISK_MAX_TAPS)
+        return fail(DISK_BAD_SHAPE, "G0=%d G1=%d T=%d out of range", G0, G1, T);
+    DISK_TRY(check_ptr(base, "base"));
+    DISK_TRY(check_ptr(out, "out"));
+    if (!angles) return fail(DISK_INVALID_ARG, "angles is NULL");
+    for (int j = 0; j < G1; ++j)
+        if (!std::isfinite(angles[j])) return fail(DISK_INVALID_ARG, "angles[%d] is not finite", j);
+    const char* b = reinterpret_cast<const char*>(base);
+    const char* o = reinterpret_cast<const char*>(out);
+    if (o < b + static_cast<size_t>(G0) * T * 12 && b < o + static_cast<size_t>(G0) * G1 * T * 12)
+        return fail(DISK_INVALID_ARG, "out overlaps base");
+    DISK_HIP(launch_rotate_basis(G0, G1, T, angles, base, out, stream), "rotate basis");
+    return ok();
+}
+
 // ---------------------------------------------------------------------------
 // dense reference
 // ---------------------------------------------------------------------------

@@ -27,6 +27,7 @@
 #include "internal.hpp"
 
 #include <algorithm>
+#include <cmath>
 #include <cstdlib>
 #include <type_traits>
 
@@ -685,6 +686,44 @@ __global__ __launch_bounds__(256) void sv_pass_global_kernel(const TIn* __restri
     }
 #pragma unroll
     for (int c = 0; c < C; ++c) IO<TOut>::store(Y, c * plane + idx, acc[c]);
+}
+
+// Angle axis of a 2-D basis: out[(i0 G1 + i1)][t] = base[i0][t] with its offset
+// rotated by angle i1 (cos, sin given), weight copied.
+struct RotArgs {
+    int G0, G1, T;
+    float cs[2 * 64];
+};
+__global__ __launch_bounds__(256) void rotate_basis_kernel(RotArgs a, const float* __restrict__ base,
+                                                           float* __restrict__ out) {
+    const long n = static_cast<long>(a.G0) * a.G1 * a.T;
+    for (long i = blockIdx.x * 256L + threadIdx.x; i < n; i += static_cast<long>(gridDim.x) * 256) {
+        const int t = static_cast<int>(i % a.T);
+        const long e = i / a.T;
+        const int i1 = static_cast<int>(e % a.G1), i0 = static_cast<int>(e / a.G1);
+        const float* b = base + (static_cast<size_t>(i0) * a.T + t) * 3;
+        const float c = a.cs[2 * i1], s = a.cs[2 * i1 + 1];
+        float* o = out + static_cast<size_t>(i) * 3;
+        o[0] = fmaf(c, b[0], -s * b[1]);
+        o[1] = fmaf(s, b[0], c * b[1]);
+        o[2] = b[2];
+    }
+}
+
+hipError_t launch_rotate_basis(int G0, int G1, int T, const double* angles, const float* base, float* out,
+                               hipStream_t s) {
+    RotArgs a{};
+    a.G0 = G0;
+    a.G1 = G1;
+    a.T = T;
+    for (int j = 0; j < G1; ++j) {
+        a.cs[2 * j] = static_cast<float>(std::cos(angles[j]));
+        a.cs[2 * j + 1] = static_cast<float>(std::sin(angles[j]));
+    }
+    const long n = static_cast<long>(G0) * G1 * T;
+    hipLaunchKernelGGL(rotate_basis_kernel, dim3(static_cast<unsigned>(std::min<long>((n + 255) / 256, 1024))),
+                       dim3(256), 0, s, a, base, out);
+    return hipGetLastError();
 }
 
 // Tile choice.  DISK_SV_PIPE=0 forces the one-tile-per-work-group kernel (a

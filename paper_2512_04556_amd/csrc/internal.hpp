@@ -85,6 +85,9 @@ hipError_t launch_continue(const disk_target* desc, const int* taps, float* thet
 hipError_t launch_init_radial(int B, const disk_target* desc, const int* taps, const float* targets, float* theta,
                               int max_side, int max_T, hipStream_t s);
 
+hipError_t launch_rotate_basis(int G0, int G1, int T, const double* angles, const float* base, float* out,
+                               hipStream_t s);
+
 // ---- dense reference (dense.hip) ----
 hipError_t launch_dense_sv(int kind, float r0, float r1, float a0, float a1, int half, const void* image,
                            const float* pmap, void* out, int C, int H, int W, int bf16, hipStream_t s);

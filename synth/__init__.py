@@ -180,6 +180,29 @@ def ellipse_kernel(r: float, aspect: float, M: int | None = None) -> np.ndarray:
     return _normalise(_aa((rho - 1.0) * scale))
 
 
+def line_kernel(length: float, width: float = 1.0, M: int | None = None) -> np.ndarray:
+    """Horizontal motion-blur segment of the given length (capsule of the given
+    width around the centre line), anti-aliased, unit sum."""
+    h = length / 2.0
+    if M is None:
+        M = 2 * int(math.ceil(h + width)) + 1
+    x, y = _grid(M)
+    dx = np.maximum(np.abs(x) - h, 0.0)
+    return _normalise(_aa(np.hypot(dx, y) - width / 2.0))
+
+
+def direction_map(H: int, W: int, kind: str = "radial") -> np.ndarray:
+    """Two-channel parameter map for angle-driven blur: P0 = distance from the
+    image centre / the corner distance; P1 = the blur direction mod pi, over
+    pi: along the ray from the centre ("radial", zoom blur) or across it
+    ("rotational")."""
+    y, x = np.mgrid[0:H, 0:W].astype(np.float64)
+    dy, dx = y - (H - 1) / 2.0, x - (W - 1) / 2.0
+    r = np.hypot(dx, dy)
+    a = np.arctan2(dy, dx) + (0.0 if kind == "radial" else math.pi / 2.0)
+    return np.stack([r / r.max(), np.mod(a, math.pi) / math.pi]).astype(np.float32)
+
+
 def _polygon_sdf(x, y, n: int, R: float, rot: float):
     """Signed distance to a regular n-gon with circumradius R."""
     ang = np.arctan2(y, x) - rot

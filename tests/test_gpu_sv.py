@@ -191,3 +191,24 @@ def test_sv_halo_just_beyond_padded_tile(dev):
     assert 31 <= max(b.halo) <= 33
     want = SV.sv_chain(img.astype(np.float64), P.astype(np.float64), basis.astype(np.float64), [6], taps)
     assert rel_err(to_np(out), want) <= TOL_F32
+
+
+def test_basis_rotate_and_angle_effect(dev):
+    """Angle axis built on the device (offsets rotated per angle, FP32)
+    against the FP64 oracle's rotation, then a rotational-blur filter with
+    that 2-D basis (blur length x direction) against the oracle."""
+    from oracle import interp as IP
+    from synth import direction_map
+    taps = [6, 6, 6]
+    base = np.stack([random_theta(taps, 1.0 + 2.0 * k, seed=700 + k) for k in range(4)]).astype(np.float32)
+    angles = [np.pi * j / 8 for j in range(9)]
+    say("basis rotate")
+    got = disk.disk_basis_rotate(to_dev(base), angles)
+    want = IP.rotate_basis(base.astype(np.float64), angles)
+    assert np.abs(to_np(got) - want).max() <= 2e-6 * np.abs(want).max()
+    H, W = 70, 120
+    img = noise_image(H, W, 3, seed=9, n_rects=10)
+    P = direction_map(H, W, "rotational")
+    out, b = _run(to_np(got).astype(np.float32), taps, [4, 9], img, P)
+    ref = SV.sv_chain(img.astype(np.float64), P.astype(np.float64), want, [4, 9], taps)
+    assert rel_err(to_np(out), ref) <= TOL_F32

@@ -185,3 +185,21 @@ def test_sv_constant_image_stays_constant_with_unit_layer_sums():
     P = param_map(16, 16, seed=9, period=8.0)
     img = np.full((1, 16, 16), 0.625)
     np.testing.assert_allclose(SV.sv_chain(img, P, basis, [4], taps), 0.625, rtol=1e-14)
+
+
+def test_rotate_basis_quarter_turn_rotates_the_response():
+    """Rotating every offset by +90 degrees rotates the chain's impulse
+    response by a quarter turn (bilinear reads commute with 90-degree grid
+    rotations); angle 0 is the identity and rotations compose."""
+    from oracle import interp as IP
+    from oracle import sparse as S
+    from synth import random_theta
+    taps = [5, 4]
+    th = random_theta(taps, 3.0, seed=41).astype(np.float64)
+    r = IP.rotate_basis(th[None], [0.0, np.pi / 2, np.pi / 3, np.pi / 6])
+    np.testing.assert_array_equal(r[0], th)
+    K = S.impulse_response(17, th, taps)
+    Kq = S.impulse_response(17, r[1], taps)
+    np.testing.assert_allclose(Kq, np.rot90(K, k=-1), atol=1e-15)
+    twice = IP.rotate_basis(r[3][None], [np.pi / 6])[0]
+    np.testing.assert_allclose(twice, r[2], atol=1e-13)
