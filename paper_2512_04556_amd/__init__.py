@@ -132,6 +132,12 @@ def _dev(t, name):
         raise DiskError(f"{name} must be a GPU tensor")
 
 
+def _f32(t, name):
+    """The C entry points read these as float*: refuse any other dtype."""
+    if t is not None and t.dtype != torch.float32:
+        raise DiskError(f"{name} must be float32 (got {t.dtype})")
+
+
 def _stream():
     return c_void_p(torch.cuda.current_stream().cuda_stream)
 
@@ -165,6 +171,7 @@ def disk_forward(theta, taps, inp=None, *, H=None, W=None, boundary=CLAMP, save=
     response on an H x W canvas.  Returns (out, saved) with saved the
     intermediates [(L-1)][C][H][W] when ``save``."""
     _dev(theta, "theta")
+    _f32(theta, "theta")
     dev = theta.device
     cx = _complex(taps)
     if inp is None:
@@ -210,6 +217,7 @@ class Basis:
     """A filter-space basis: device tensor [G][T][3] plus its C descriptor."""
 
     def __init__(self, theta, taps, grid):
+        _f32(theta, "basis theta")
         self.theta = theta.contiguous()
         self.taps = [int(t) for t in taps]
         self.grid = [int(g) for g in grid]
@@ -236,6 +244,7 @@ def disk_sv_filter(basis: Basis, image, pmap, out=None, ws=None):
     per-pixel parameters ``pmap`` [dims][H][W] (f32)."""
     _dev(image, "image")
     _dev(pmap, "pmap")
+    _f32(pmap, "pmap")
     C, H, W = image.shape
     io = _io_dtype(image)
     if out is None:
@@ -268,6 +277,7 @@ def disk_sv_apply(basis: Basis, table, image, pmap, out=None, ws=None):
     """The L passes of the SV filter with a prepared table."""
     _dev(image, "image")
     _dev(pmap, "pmap")
+    _f32(pmap, "pmap")
     C, H, W = image.shape
     io = _io_dtype(image)
     if out is None:
@@ -356,6 +366,7 @@ def disk_dense_sv(image, pmap, kind, r0, r1, half, a0=1.0, a1=1.0, out=None):
     approximates); image [C][H][W] float32 or bfloat16, pmap [dims][H][W]."""
     _dev(image, "image")
     _dev(pmap, "pmap")
+    _f32(pmap, "pmap")
     C, H, W = (int(v) for v in image.shape)
     io = BF16 if image.dtype == torch.bfloat16 else F32
     if out is None:

@@ -248,13 +248,13 @@ disk_status disk_backward(const disk_complex* cx, const float* theta, const floa
             DISK_HIP(launch_adjoint_taps(C, boundary, src_kind, X, G, tapu + sp.tap0[l], sp.taps[l], H, W, partial,
                                          stream),
                      "adjoint taps");
-            DISK_HIP(launch_adjoint_finish(partial, nblk, theta + 3 * sp.tap0[l], tapu + sp.tap0[l], sp.taps[l],
+            DISK_HIP(launch_adjoint_finish(partial, nblk, theta + 3 * sp.tap0[l], sp.taps[l],
                                            grad_theta + 3 * sp.tap0[l], stream),
                      "adjoint finish");
         }
         if (l > 0 || grad_in) {
             float* Gn = l == 0 ? grad_in : (G == g0 ? g1 : g0);
-            DISK_HIP(launch_adjoint_input(C, boundary, G, tapu + sp.tap0[l], sp.taps[l], H, W, 0, nullptr, Gn, stream),
+            DISK_HIP(launch_adjoint_input(C, boundary, G, tapu + sp.tap0[l], sp.taps[l], H, W, Gn, stream),
                      "adjoint input");
             G = Gn;
         }

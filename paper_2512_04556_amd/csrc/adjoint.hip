@@ -178,11 +178,11 @@ hipError_t launch_adjoint_taps(int C, int boundary, int src_kind, const void* X,
     }
 }
 
-hipError_t launch_adjoint_finish(const float* partial, int nblk, const float* theta_layer, const TapU* taps,
-                                 int N, float* dtheta_layer, hipStream_t s) {
-    (void)taps;
-    // sums live right after the partials
-    float* sums = const_cast<float*>(partial) + static_cast<size_t>(nblk) * N * 4;
+// `partial` holds nblk * N * 4 block partials followed by room for the N * 4
+// per-tap sums (the workspace carving reserves both).
+hipError_t launch_adjoint_finish(float* partial, int nblk, const float* theta_layer, int N, float* dtheta_layer,
+                                 hipStream_t s) {
+    float* sums = partial + static_cast<size_t>(nblk) * N * 4;
     hipLaunchKernelGGL(adjoint_reduce_kernel, dim3(4 * N), dim3(256), 0, s, partial, nblk, N, sums);
     hipLaunchKernelGGL(adjoint_finish_kernel, dim3((N + 63) / 64), dim3(64), 0, s, sums, theta_layer, N,
                        dtheta_layer);
@@ -260,9 +260,7 @@ static hipError_t input_bound(int boundary, const float* G, const TapU* taps, in
 }
 
 hipError_t launch_adjoint_input(int C, int boundary, const float* G, const TapU* taps, int N, int H, int W,
-                                int R, float* pad, float* Gprev, hipStream_t s) {
-    (void)R;
-    (void)pad;
+                                float* Gprev, hipStream_t s) {
     switch (C) {
         case 1: return input_bound<1>(boundary, G, taps, N, H, W, Gprev, s);
         case 2: return input_bound<2>(boundary, G, taps, N, H, W, Gprev, s);
@@ -270,7 +268,5 @@ hipError_t launch_adjoint_input(int C, int boundary, const float* G, const TapU*
         default: return input_bound<4>(boundary, G, taps, N, H, W, Gprev, s);
     }
 }
-
-hipError_t launch_halo_of_taps(const TapU*, int, int*, hipStream_t) { return hipSuccess; }
 
 }  // namespace disk

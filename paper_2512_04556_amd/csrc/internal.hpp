@@ -54,13 +54,12 @@ hipError_t launch_adjoint_taps(int C, int boundary, int src_kind, const void* X,
                                const TapU* taps, int N, int H, int W, float* partial,
                                hipStream_t s);
 // Reduces partials (fixed order) and writes dtheta rows [N][3] of this layer.
-hipError_t launch_adjoint_finish(const float* partial, int nblk, const float* theta_layer,
-                                 const TapU* taps, int N, float* dtheta_layer, hipStream_t s);
+hipError_t launch_adjoint_finish(float* partial, int nblk, const float* theta_layer, int N, float* dtheta_layer,
+                                 hipStream_t s);
 // Input adjoint: Gprev = A^T G (exact transpose incl. CLAMP border folding).
 // pad: scratch of (H+2R)*(W+2R)*C floats for CLAMP (R = halo); may be null for ZERO.
-hipError_t launch_adjoint_input(int C, int boundary, const float* G, const TapU* taps, int N,
-                                int H, int W, int R, float* pad, float* Gprev, hipStream_t s);
-hipError_t launch_halo_of_taps(const TapU* taps, int T, int* out_halo, hipStream_t s);
+hipError_t launch_adjoint_input(int C, int boundary, const float* G, const TapU* taps, int N, int H, int W,
+                                float* Gprev, hipStream_t s);
 
 // ---- filter.hip: spatially varying filter ------------------------------------
 // Table row widths: 1-D 9 floats, 2-D 12 floats per (entry, tap).
