@@ -24,6 +24,15 @@ TAPS = [8, 8, 8, 8]
 G = 16
 # algorithmic HBM bytes of one pass per pixel: read C floats, read P, write C floats
 PASS_BYTES_PER_PX = 4 * C + 4 + 4 * C
+# algorithmic FP32 vector operations per pixel and tap (FMA counted once): 3 to
+# interpolate (ox, oy, w), 4 for floor and fraction of the two coordinates, 7
+# for the four corner weights, 12 accumulating FMAs (3 channels x 4 corners), 2
+# for the corner address
+OPS_PER_PX_TAP = 3 + 4 + 7 + 12 + 2
+# non-packed FP32 vector peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (one
+# operation per lane per cycle; the published 157.3 TFLOP/s counts an FMA as
+# two FLOPs and packed FP32 as two lanes)
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 
 
 def parse():
@@ -400,6 +409,8 @@ def main():
     pass_ms = e0.elapsed_time(e1) / (a.steps * len(TAPS))
     pass_bytes = PASS_BYTES_PER_PX * H * W
     achieved = pass_bytes / (pass_ms * 1e-3) / 1e9
+    ops_per_launch = OPS_PER_PX_TAP * TAPS[0] * H * W
+    ops_achieved = ops_per_launch / (pass_ms * 1e-3) / 1e12
 
     mpix = H * W / (ms * 1e-3) / 1e6
     frame_bytes = len(TAPS) * pass_bytes
@@ -412,9 +423,12 @@ def main():
                    "halo": basis.halo},
         "hbm_frac_frame": round(frame_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
         "event_ms_per_step": round(ev_ms, 5),
-        "roofline": {"bound": "hbm", "kernel": "sv_pass_pipe_kernel", "achieved": round(achieved, 1),
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": measured_traffic(), "pass_ms": round(pass_ms, 5), "bytes_per_launch": pass_bytes},
+        "roofline": {"bound": "alu", "kernel": "sv_pass_pipe_kernel", "achieved": round(ops_achieved, 3),
+                     "peak": round(VALU_PEAK_TOPS, 2), "unit": "Tops/s (FP32 vector, FMA = 1)",
+                     "frac": round(ops_achieved / VALU_PEAK_TOPS, 4), "traffic": measured_traffic(),
+                     "pass_ms": round(pass_ms, 5), "ops_per_launch": ops_per_launch,
+                     "hbm_achieved_gbs": round(achieved, 1), "hbm_peak_gbs": HBM_PEAK_GBS,
+                     "hbm_frac": round(achieved / HBM_PEAK_GBS, 4), "bytes_per_launch": pass_bytes},
     }
     if fit_info:
         res["config"]["basis_fit"] = fit_info
