@@ -18,10 +18,12 @@
 //   staging time removes all per-tap boundary logic).  Each wave owns PY
 //   consecutive 64-pixel rows; lanes are consecutive in x, so the gathers of a
 //   wave read consecutive LDS words (conflict-free) shifted by the tap offset.
-// * P varies slowly, so most 64-pixel rows share one basis interval k: the tap
-//   coefficients are then wave-uniform and come from the scalar cache, and the
-//   per-pixel interpolation is one FMA per component.  Rows straddling one node
-//   use a two-FMA kinked line; anything else reads per-lane coefficients.
+// * P varies slowly, so most 16 x 8 wave blocks share one basis interval k: the
+//   tap coefficients are then wave-uniform (broadcast LDS reads of the layer's
+//   table rows staged after the tile, or the scalar cache where the table does
+//   not fit), and the per-pixel interpolation is one FMA per component.  Blocks
+//   straddling up to three nodes use a kinked line; anything else reads
+//   per-lane coefficients.
 // * Blocks map to tiles XCD-contiguously so halo re-reads stay in one L2.
 #include "common.hpp"
 #include "internal.hpp"
@@ -188,10 +190,25 @@ __device__ __forceinline__ void gather_tap(float* acc, int base, int rowB, float
 // LDS byte address is formed with two exact FP32 FMAs (integers < 2^24) and one
 // conversion, cheaper than integer conversion plus 24-bit multiplies.
 typedef float v4f __attribute__((ext_vector_type(4)));
+typedef float v2f __attribute__((ext_vector_type(2)));
 typedef __attribute__((address_space(3))) v4f lds_v4f;
-template <int C>
+typedef __attribute__((address_space(3))) v2f lds_v2f;
+__device__ __forceinline__ v4f lds_ld4(int byte_off) {
+    return *reinterpret_cast<const lds_v4f*>(static_cast<uintptr_t>(static_cast<uint32_t>(byte_off)));
+}
+__device__ __forceinline__ v2f lds_ld2(int byte_off) {
+    return *reinterpret_cast<const lds_v2f*>(static_cast<uintptr_t>(static_cast<uint32_t>(byte_off)));
+}
+// ROWB > 0: the row stride is a compile-time constant, so the second row's
+// reads take it in their offset field (no address add, and no register reuse
+// that would make the second pair wait for the first).
+template <int C, int ROWB = 0>
 __device__ __forceinline__ void gather_tap4(float* acc, float basef, float rowBf, int rowB, float nx, float ny,
                                             float w) {
+    if (ROWB > 0) {
+        rowB = ROWB;
+        rowBf = static_cast<float>(ROWB);
+    }
     const float flx = floorf(nx), fly = floorf(ny);
     const float fx = nx - flx, fy = ny - fly;
     const float wy1 = w * fy, wy0 = w - wy1;
@@ -259,12 +276,24 @@ __device__ __forceinline__ void sv_decode(const float (&pv)[PY][DIMS], int G0, i
     }
 }
 
+// Layer table staged in LDS (1-D bases): one 48-byte row per (entry, tap),
+// entry-major: nAx nDx nAy nDy | Aw Dw 0 0 | nDDx nDDy DDw 0, plus one zero row
+// at the end (the pipelined loops read one row past the last tap).
+constexpr int kRowLB = 48;
+__host__ __device__ __forceinline__ int sv_ltab_bytes(int G, int N) { return (G * N + 1) * kRowLB; }
+
 // All N taps of one layer for this lane's PY pixels of a staged tile.
-template <int C, int DIMS, int PY>
+// ROWB > 0 fixes the staged row stride at compile time; TL reads the
+// coefficients of uniform and straddling waves from the LDS table at byte
+// offset tabL (wave-uniform broadcast reads, pipelined one tap ahead) instead
+// of the scalar cache.
+template <int C, int DIMS, int PY, int ROWB = 0, bool TL = false>
 __device__ __forceinline__ void sv_tile_taps(float (&acc)[PY][C], const float (&ta)[PY], const float (&tb)[PY],
                                              const int (&kk)[PY], int base0, int rowB,
-                                             const float* __restrict__ table, int tap0, int N, int T) {
+                                             const float* __restrict__ table, int tap0, int N, int T,
+                                             int tabL = 0) {
     constexpr int RW = DIMS == 1 ? kRow1D : kRow2D;
+    if (ROWB > 0) rowB = ROWB;
     const float rowBf = static_cast<float>(rowB);
     float basef[PY];
 #pragma unroll
@@ -276,7 +305,7 @@ __device__ __forceinline__ void sv_tile_taps(float (&acc)[PY][C], const float (&
 #define SV_TAP(j, nx, ny, w)                                                                       \
     do {                                                                                           \
         if (C >= 3)                                                                                \
-            gather_tap4<C>(acc[j], basef[j], rowBf, rowB, (nx), (ny), (w));                        \
+            gather_tap4<C, ROWB>(acc[j], basef[j], rowBf, rowB, (nx), (ny), (w));                  \
         else                                                                                       \
             gather_tap<C>(acc[j], base0 + (j) * 4 * rowB, rowB, (nx), (ny), (w));                  \
     } while (0)
@@ -293,7 +322,24 @@ __device__ __forceinline__ void sv_tile_taps(float (&acc)[PY][C], const float (&
     if (same) {
         // every pixel of the wave lies in one interval: wave-uniform coefficients
         const float* e = table + (static_cast<size_t>(k0u) * T + tap0) * RW;
-        if (DIMS == 1) {
+        if (TL && DIMS == 1) {
+            int r = uniform(tabL + k0u * N * kRowLB);
+            v4f a = lds_ld4(r);
+            v2f b = lds_ld2(r + 16);
+            for (int i = 0; i < N; ++i) {
+                r += kRowLB;
+                v4f na = lds_ld4(r);
+                v2f nb = lds_ld2(r + 16);
+#pragma unroll
+                for (int j = 0; j < PY; ++j)
+                    SV_TAP(j, fmaf(ta[j], a.y, a.x), fmaf(ta[j], a.w, a.z), fmaf(ta[j], b.y, b.x));
+                // the next tap's coefficients are needed only here: keeps their
+                // reads ahead of this tap's gathers
+                asm volatile("" : "+v"(na), "+v"(nb));
+                a = na;
+                b = nb;
+            }
+        } else if (DIMS == 1) {
             // software-pipelined: the next tap's scalar coefficients load while
             // this tap computes (the table carries one spare row at its end)
             float Ax = e[0], Dx = e[1], Ay = e[2], Dy = e[3], Aw = e[4], Dw = e[5];
@@ -336,6 +382,31 @@ __device__ __forceinline__ void sv_tile_taps(float (&acc)[PY][C], const float (&
                 t0[j] = tb[j] - static_cast<float>(bmin);
 #pragma unroll
                 for (int m = 0; m < SP; ++m) h[m][j] = fmaxf(t0[j] - static_cast<float>(m + 1), 0.0f);
+            }
+            if (TL) {
+                // entry bmin's line plus the slope changes stored with entries
+                // bmin .. bmin + SP - 1 (same tap), all from the LDS table
+                const int estep = N * kRowLB;
+                int r = uniform(tabL + bmin * estep);
+                for (int i = 0; i < N; ++i, r += kRowLB) {
+                    const v4f a = lds_ld4(r);
+                    const v2f b = lds_ld2(r + 16);
+                    v4f E[SP];
+#pragma unroll
+                    for (int m = 0; m < SP; ++m) E[m] = lds_ld4(r + m * estep + 32);
+#pragma unroll
+                    for (int j = 0; j < PY; ++j) {
+                        float nx = fmaf(t0[j], a.y, a.x), ny = fmaf(t0[j], a.w, a.z), w = fmaf(t0[j], b.y, b.x);
+#pragma unroll
+                        for (int m = 0; m < SP; ++m) {
+                            nx = fmaf(h[m][j], E[m].x, nx);
+                            ny = fmaf(h[m][j], E[m].y, ny);
+                            w = fmaf(h[m][j], E[m].z, w);
+                        }
+                        SV_TAP(j, nx, ny, w);
+                    }
+                }
+                return;
             }
             for (int i = 0; i < N; ++i) {
                 const float* r = e + i * RW;
@@ -516,12 +587,16 @@ struct PipeShape {
     static constexpr int NQ = (kTW + 2 * HMAX + 63) / 64;                  // 64-column chunks
 };
 
-template <int C, int DIMS, typename TIn, typename TOut, int NW, int HMAX>
-__global__ __launch_bounds__(64 * NW) void sv_pass_pipe_kernel(
+// ROWB > 0 (C >= 3): the staged row stride in bytes, fixed at compile time
+// (rowW is then ROWB / 4).  TL (1-D bases): the layer's coefficient rows are
+// staged in LDS after the tile, at byte offset SY * rowB.
+template <int C, int DIMS, typename TIn, typename TOut, int NW, int HMAX, int ROWB, bool TL>
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4, 4))) void sv_pass_pipe_kernel(
     const TIn* __restrict__ X, TOut* __restrict__ Y, const float* __restrict__ P,
     const float* __restrict__ table, int tap0, int N, int T, int G0, int G1, int H, int W, int halo,
     int tiles_x, int per, int ntiles, const int* __restrict__ flag, int rowW) {
     extern __shared__ float lds[];
+    if (ROWB > 0) rowW = ROWB / 4;
     constexpr int PY = kPipePY;
     constexpr int TH = PipeShape<NW, HMAX>::TH;
     constexpr int kPipeRPW = PipeShape<NW, HMAX>::RPW, kPipeNQ = PipeShape<NW, HMAX>::NQ;
@@ -548,6 +623,26 @@ __global__ __launch_bounds__(64 * NW) void sv_pass_pipe_kernel(
     const int base0 = lds_offset(lds) + (lyb + halo) * rowB + (lx + halo) * PXB;
     const int wv = uniform(wave);                // the wave index, in a scalar register
     const int nq = (SX + 63) >> 6;               // <= kPipeNQ
+    const int tabL = lds_offset(lds) + SY * rowB;
+    if (TL) {
+        // this layer's rows of the coefficient table -> LDS (visible after the
+        // first barrier below); the extra last row is zero
+        const int nrow = G0 * N;
+        for (int r = threadIdx.x; r <= nrow; r += 64 * NW) {
+            v4f q0 = {0.0f, 0.0f, 0.0f, 0.0f}, q1 = q0, q2 = q0;
+            if (r < nrow) {
+                const int k = r / N, i = r - k * N;
+                const float* g = table + (static_cast<size_t>(k) * T + tap0 + i) * kRow1D;
+                q0 = v4f{g[0], g[1], g[2], g[3]};
+                q1 = v4f{g[4], g[5], 0.0f, 0.0f};
+                q2 = v4f{g[6], g[7], g[8], 0.0f};
+            }
+            lds_v4f* d = reinterpret_cast<lds_v4f*>(static_cast<uintptr_t>(static_cast<uint32_t>(tabL + r * kRowLB)));
+            d[0] = q0;
+            d[1] = q1;
+            d[2] = q2;
+        }
+    }
     const int nr = (SY - wv + NW - 1) / NW;      // staged rows of this wave, <= kPipeRPW
     // one base pointer per plane and 32-bit element offsets inside a plane
     // (H W <= 2^30): the loads take a scalar base plus one vector offset
@@ -614,7 +709,7 @@ __global__ __launch_bounds__(64 * NW) void sv_pass_pipe_kernel(
         const int next = tile + nwg;
         if (next < tend) issue(next);
         float acc[PY][C];
-        sv_tile_taps<C, DIMS, PY>(acc, ta, tb, kk, base0, rowB, table, tap0, N, T);
+        sv_tile_taps<C, DIMS, PY, ROWB, TL>(acc, ta, tb, kk, base0, rowB, table, tap0, N, T, tabL);
         sv_store<C, TOut, PY>(Y, plane, W, H, x, y0, acc);
         if (next >= tend) break;
         tile = next;
@@ -751,16 +846,28 @@ static int cu_count() {
     return n;
 }
 
-template <int C, int DIMS, typename TIn, typename TOut, int NW, int HMAX>
+// Staged-tile row stride of the C >= 3 pipe kernels: 448 dwords (112 float4
+// pixels) holds 64 + 2 * 24 columns and is 64 mod 128 dwords (bank rule above)
+// for every halo up to 24.
+constexpr int kPipeRowB = 448 * 4;
+
+template <int C, int DIMS, typename TIn, typename TOut, int NW, int HMAX, int ROWB, bool TL>
+static size_t pipe_lds_bytes(int halo, int G0, int N) {
+    constexpr int TH = PipeShape<NW, HMAX>::TH;
+    const size_t rowB = ROWB > 0 ? ROWB : static_cast<size_t>(sv_row_dwords(halo, C)) * 4;
+    return rowB * (TH + 2 * halo) + (TL ? sv_ltab_bytes(G0, N) : 0);
+}
+
+template <int C, int DIMS, typename TIn, typename TOut, int NW, int HMAX, int ROWB, bool TL>
 static hipError_t launch_pipe(const void* src, void* dst, const float* pmap, const float* table, int tap0, int N,
                               int T, int G0, int G1, int H, int W, int halo, const int* flag, hipStream_t s) {
     constexpr int TH = PipeShape<NW, HMAX>::TH;
     const int tiles_x = (W + kTW - 1) / kTW, tiles_y = (H + TH - 1) / TH;
     const int ntiles = tiles_x * tiles_y;
     const int per = (ntiles + 7) / 8;
-    const size_t lds = sv_lds_bytes(halo, C, kPipePY * (NW / 4));
-    const int rowW = sv_row_dwords(halo, C);
-    auto fn = sv_pass_pipe_kernel<C, DIMS, TIn, TOut, NW, HMAX>;
+    const size_t lds = pipe_lds_bytes<C, DIMS, TIn, TOut, NW, HMAX, ROWB, TL>(halo, G0, N);
+    const int rowW = ROWB > 0 ? ROWB / 4 : sv_row_dwords(halo, C);
+    auto fn = sv_pass_pipe_kernel<C, DIMS, TIn, TOut, NW, HMAX, ROWB, TL>;
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
     if (e != hipSuccess) return e;
@@ -800,13 +907,27 @@ static hipError_t launch_typed(const void* src, void* dst, const float* pmap, co
                                int T, int G0, int G1, int H, int W, int halo, const int* flag, hipStream_t s) {
     static const int pipe = env_int("DISK_SV_PIPE", 1);
     // small halos: 8-wave work-groups of 64 x 16 tiles, two per CU, whose
-    // staging and gather phases drift apart and overlap
-    if (pipe && halo <= kPipeHalo8 && sv_lds_bytes(halo, C, kPipePY * 2) <= 80 * 1024)
-        return launch_pipe<C, DIMS, TIn, TOut, 8, kPipeHalo8>(src, dst, pmap, table, tap0, N, T, G0, G1, H, W, halo,
-                                                              flag, s);
-    if (pipe && halo <= kPipeHalo && sv_lds_bytes(halo, C, kPipePY * 4) <= 160 * 1024)
-        return launch_pipe<C, DIMS, TIn, TOut, 16, kPipeHalo>(src, dst, pmap, table, tap0, N, T, G0, G1, H, W, halo,
-                                                              flag, s);
+    // staging and gather phases drift apart and overlap; larger ones: 16-wave
+    // work-groups of 64 x 32 tiles, one per CU.  C >= 3 with a 1-D basis: fixed
+    // row stride and the layer table in LDS when it fits, else the scalar-cache
+    // table; C < 3 or 2-D: runtime stride, scalar-cache table.
+#define SV_TRY_PIPE(NW, HMAX, ROWB, TL, BUDGET)                                                              \
+    if (pipe && halo <= HMAX &&                                                                              \
+        pipe_lds_bytes<C, DIMS, TIn, TOut, NW, HMAX, ROWB, TL>(halo, G0, N) <= static_cast<size_t>(BUDGET)) \
+        return launch_pipe<C, DIMS, TIn, TOut, NW, HMAX, ROWB, TL>(src, dst, pmap, table, tap0, N, T, G0, G1, H, W, \
+                                                                  halo, flag, s);
+    if constexpr (C >= 3 && DIMS == 1) {
+        SV_TRY_PIPE(8, kPipeHalo8, kPipeRowB, true, 80 * 1024)
+        SV_TRY_PIPE(16, kPipeHalo, kPipeRowB, true, 160 * 1024)
+    }
+    if constexpr (C >= 3) {
+        SV_TRY_PIPE(8, kPipeHalo8, kPipeRowB, false, 80 * 1024)
+        SV_TRY_PIPE(16, kPipeHalo, kPipeRowB, false, 160 * 1024)
+    } else {
+        SV_TRY_PIPE(8, kPipeHalo8, 0, false, 80 * 1024)
+        SV_TRY_PIPE(16, kPipeHalo, 0, false, 160 * 1024)
+    }
+#undef SV_TRY_PIPE
     // A staged tile pays for its halo only when it is tall: 64 x 32 tiles while
     // they fit; below that the halo rows dominate (measured: an 8-row tile at
     // halo 33 is slower than reading the corners through L1), so larger halos
