@@ -260,7 +260,10 @@ disk_status disk_basis_set_halo(disk_basis* b, const float* basis_theta_host);
  *   basis_theta device float [G][T][3];   image device [C][H][W] of dtype io;
  *   pmap        device float [dims][H][W]; out  device [C][H][W] of dtype io.
  * If an offset in the basis exceeds its declared halo, the output is filled
- * with NaN (no out-of-tile reads happen).
+ * with NaN (no out-of-tile reads happen).  For 1-D bases with C >= 3 (and
+ * tables small enough for on-chip staging) the passes read the basis
+ * directly and no preparation launch runs; otherwise this call is
+ * disk_sv_prepare followed by disk_sv_apply.  The results are identical.
  */
 size_t disk_sv_filter_workspace_size(const disk_basis* b, int32_t C, int32_t H, int32_t W,
                                      disk_dtype io);

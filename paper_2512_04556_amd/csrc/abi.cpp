@@ -345,6 +345,25 @@ disk_status disk_sv_prepare(const disk_basis* b, const float* basis_theta, void*
     return ok();
 }
 
+// The L passes, ping-ponging through b0/b1: coefficients from a prepared table
+// and its flag, or (raw != nullptr) derived by each pass from the basis.
+static disk_status sv_passes(const disk_basis* b, const void* image, const float* pmap, void* out, int C, int H,
+                             int W, disk_dtype io, float* b0, float* b1, const float* tab, const int* flag,
+                             const float* raw, hipStream_t stream) {
+    const LayerSpec sp = make_spec(b->cx);
+    const int G0 = b->grid[0], G1 = b->dims == 2 ? b->grid[1] : 1;
+    for (int l = 0; l < sp.L; ++l) {
+        const void* src = l == 0 ? image : ((l - 1) % 2 ? b1 : b0);
+        void* dst = l == sp.L - 1 ? out : (l % 2 ? b1 : b0);
+        const int sb = (l == 0 && io == DISK_BF16) ? 1 : 0;
+        const int db = (l == sp.L - 1 && io == DISK_BF16) ? 1 : 0;
+        DISK_HIP(launch_sv_pass(C, b->dims, sb, src, db, dst, pmap, tab, sp.tap0[l], sp.taps[l], sp.T, G0, G1, H, W,
+                                b->halo[l], flag, raw, stream),
+                 "sv pass");
+    }
+    return ok();
+}
+
 disk_status disk_sv_apply(const disk_basis* b, const void* table, const void* image, const float* pmap, void* out,
                           int32_t C, int32_t H, int32_t W, disk_dtype io, void* ws, size_t ws_bytes,
                           hipStream_t stream) {
@@ -362,20 +381,9 @@ disk_status disk_sv_apply(const disk_basis* b, const void* table, const void* im
     sv_apply_ws(b, C, H, W, cv, &b0, &b1);
     if (cv.used > 0 && (!ws || cv.used > ws_bytes))
         return fail(DISK_WORKSPACE_TOO_SMALL, "workspace %zu < %zu bytes", ws_bytes, cv.used);
-    const LayerSpec sp = make_spec(b->cx);
-    const int G0 = b->grid[0], G1 = b->dims == 2 ? b->grid[1] : 1;
     const float* tab = static_cast<const float*>(table);
     const int* flag = reinterpret_cast<const int*>(static_cast<const char*>(table) + sv_table_bytes_of(b) - 256);
-    for (int l = 0; l < sp.L; ++l) {
-        const void* src = l == 0 ? image : ((l - 1) % 2 ? b1 : b0);
-        void* dst = l == sp.L - 1 ? out : (l % 2 ? b1 : b0);
-        const int sb = (l == 0 && io == DISK_BF16) ? 1 : 0;
-        const int db = (l == sp.L - 1 && io == DISK_BF16) ? 1 : 0;
-        DISK_HIP(launch_sv_pass(C, b->dims, sb, src, db, dst, pmap, tab, sp.tap0[l], sp.taps[l], sp.T, G0, G1, H, W,
-                                b->halo[l], flag, stream),
-                 "sv pass");
-    }
-    return ok();
+    return sv_passes(b, image, pmap, out, C, H, W, io, b0, b1, tab, flag, nullptr, stream);
 }
 
 disk_status disk_sv_filter(const disk_basis* b, const float* basis_theta, const void* image, const float* pmap,
@@ -388,6 +396,22 @@ disk_status disk_sv_filter(const disk_basis* b, const float* basis_theta, const 
     const size_t need = disk_sv_filter_workspace_size(b, C, H, W, io);
     if (!ws || ws_bytes < need) return fail(DISK_WORKSPACE_TOO_SMALL, "workspace %zu < %zu bytes", ws_bytes, need);
     if (image == out) return fail(DISK_INVALID_ARG, "image and out must not alias");
+    // One-shot call on a 1-D basis with C >= 3: every pass derives its layer's
+    // coefficients from the basis itself (no separate preparation launch).
+    const LayerSpec sp = make_spec(b->cx);
+    bool raw = true;
+    for (int l = 0; l < sp.L; ++l) raw = raw && sv_pass_raw_ok(C, b->dims, b->halo[l], b->grid[0], sp.taps[l]);
+    if (raw) {
+        DISK_TRY(check_ptr(basis_theta, "basis_theta"));
+        DISK_TRY(check_ptr(image, "image"));
+        DISK_TRY(check_ptr(pmap, "pmap"));
+        DISK_TRY(check_ptr(out, "out"));
+        if (io != DISK_F32 && io != DISK_BF16) return fail(DISK_INVALID_ARG, "bad dtype %d", int(io));
+        Carve cv(static_cast<char*>(ws) + tb, ws_bytes - tb);
+        float *b0, *b1;
+        sv_apply_ws(b, C, H, W, cv, &b0, &b1);
+        return sv_passes(b, image, pmap, out, C, H, W, io, b0, b1, nullptr, nullptr, basis_theta, stream);
+    }
     DISK_TRY(disk_sv_prepare(b, basis_theta, ws, tb, stream));
     return disk_sv_apply(b, ws, image, pmap, out, C, H, W, io, static_cast<char*>(ws) + tb, ws_bytes - tb, stream);
 }

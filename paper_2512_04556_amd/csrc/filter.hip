@@ -319,10 +319,11 @@ __device__ __forceinline__ void sv_tile_taps(float (&acc)[PY][C], const float (&
     const int k0u = uniform(kk[0]);
     const bool same = __all(lo == k0u && hi == k0u);
 
-    if (same) {
-        // every pixel of the wave lies in one interval: wave-uniform coefficients
-        const float* e = table + (static_cast<size_t>(k0u) * T + tap0) * RW;
-        if (TL && DIMS == 1) {
+    if constexpr (TL && DIMS == 1) {
+        // Every coefficient comes from this layer's LDS rows: row (k, i) at
+        // byte tabL + (k N + i) kRowLB.  `table` is not read on this path.
+        if (same) {
+            // one interval for the whole wave: wave-uniform (broadcast) reads
             int r = uniform(tabL + k0u * N * kRowLB);
             v4f a = lds_ld4(r);
             v2f b = lds_ld2(r + 16);
@@ -339,7 +340,69 @@ __device__ __forceinline__ void sv_tile_taps(float (&acc)[PY][C], const float (&
                 a = na;
                 b = nb;
             }
-        } else if (DIMS == 1) {
+            return;
+        }
+        const int bmin = uniform(wave_min_i(lo)), bmax = uniform(wave_max_i(hi));
+        const int span = bmax - bmin;
+        if (span <= 3) {
+            // entry bmin's line plus one hinge per interior node; the slope
+            // changes are stored with entries bmin .. bmax - 1 (same tap)
+            const int estep = N * kRowLB;
+            const int e0 = uniform(tabL + bmin * estep);
+            auto hinge_lds = [&](auto span_c) {
+                constexpr int SP = decltype(span_c)::value;
+                float t0[PY], h[SP][PY];
+#pragma unroll
+                for (int j = 0; j < PY; ++j) {
+                    t0[j] = tb[j] - static_cast<float>(bmin);
+#pragma unroll
+                    for (int m = 0; m < SP; ++m) h[m][j] = fmaxf(t0[j] - static_cast<float>(m + 1), 0.0f);
+                }
+                int r = e0;
+                for (int i = 0; i < N; ++i, r += kRowLB) {
+                    const v4f a = lds_ld4(r);
+                    const v2f b = lds_ld2(r + 16);
+                    v4f E[SP];
+#pragma unroll
+                    for (int m = 0; m < SP; ++m) E[m] = lds_ld4(r + m * estep + 32);
+#pragma unroll
+                    for (int j = 0; j < PY; ++j) {
+                        float nx = fmaf(t0[j], a.y, a.x), ny = fmaf(t0[j], a.w, a.z), w = fmaf(t0[j], b.y, b.x);
+#pragma unroll
+                        for (int m = 0; m < SP; ++m) {
+                            nx = fmaf(h[m][j], E[m].x, nx);
+                            ny = fmaf(h[m][j], E[m].y, ny);
+                            w = fmaf(h[m][j], E[m].z, w);
+                        }
+                        SV_TAP(j, nx, ny, w);
+                    }
+                }
+            };
+            if (span == 1)
+                hinge_lds(std::integral_constant<int, 1>{});
+            else if (span == 2)
+                hinge_lds(std::integral_constant<int, 2>{});
+            else
+                hinge_lds(std::integral_constant<int, 3>{});
+            return;
+        }
+        // any other wave: per-lane rows (kk[j] <= G - 1, so inside the table)
+        for (int i = 0; i < N; ++i) {
+#pragma unroll
+            for (int j = 0; j < PY; ++j) {
+                const int r = tabL + (kk[j] * N + i) * kRowLB;
+                const v4f a = lds_ld4(r);
+                const v2f b = lds_ld2(r + 16);
+                SV_TAP(j, fmaf(ta[j], a.y, a.x), fmaf(ta[j], a.w, a.z), fmaf(ta[j], b.y, b.x));
+            }
+        }
+        return;
+    }
+
+    if (same) {
+        // every pixel of the wave lies in one interval: wave-uniform coefficients
+        const float* e = table + (static_cast<size_t>(k0u) * T + tap0) * RW;
+        if (DIMS == 1) {
             // software-pipelined: the next tap's scalar coefficients load while
             // this tap computes (the table carries one spare row at its end)
             float Ax = e[0], Dx = e[1], Ay = e[2], Dy = e[3], Aw = e[4], Dw = e[5];
@@ -382,31 +445,6 @@ __device__ __forceinline__ void sv_tile_taps(float (&acc)[PY][C], const float (&
                 t0[j] = tb[j] - static_cast<float>(bmin);
 #pragma unroll
                 for (int m = 0; m < SP; ++m) h[m][j] = fmaxf(t0[j] - static_cast<float>(m + 1), 0.0f);
-            }
-            if (TL) {
-                // entry bmin's line plus the slope changes stored with entries
-                // bmin .. bmin + SP - 1 (same tap), all from the LDS table
-                const int estep = N * kRowLB;
-                int r = uniform(tabL + bmin * estep);
-                for (int i = 0; i < N; ++i, r += kRowLB) {
-                    const v4f a = lds_ld4(r);
-                    const v2f b = lds_ld2(r + 16);
-                    v4f E[SP];
-#pragma unroll
-                    for (int m = 0; m < SP; ++m) E[m] = lds_ld4(r + m * estep + 32);
-#pragma unroll
-                    for (int j = 0; j < PY; ++j) {
-                        float nx = fmaf(t0[j], a.y, a.x), ny = fmaf(t0[j], a.w, a.z), w = fmaf(t0[j], b.y, b.x);
-#pragma unroll
-                        for (int m = 0; m < SP; ++m) {
-                            nx = fmaf(h[m][j], E[m].x, nx);
-                            ny = fmaf(h[m][j], E[m].y, ny);
-                            w = fmaf(h[m][j], E[m].z, w);
-                        }
-                        SV_TAP(j, nx, ny, w);
-                    }
-                }
-                return;
             }
             for (int i = 0; i < N; ++i) {
                 const float* r = e + i * RW;
@@ -594,7 +632,7 @@ template <int C, int DIMS, typename TIn, typename TOut, int NW, int HMAX, int RO
 __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4, 4))) void sv_pass_pipe_kernel(
     const TIn* __restrict__ X, TOut* __restrict__ Y, const float* __restrict__ P,
     const float* __restrict__ table, int tap0, int N, int T, int G0, int G1, int H, int W, int halo,
-    int tiles_x, int per, int ntiles, const int* __restrict__ flag, int rowW) {
+    int tiles_x, int per, int ntiles, const int* __restrict__ flag, int rowW, const float* __restrict__ raw) {
     extern __shared__ float lds[];
     if (ROWB > 0) rowW = ROWB / 4;
     constexpr int PY = kPipePY;
@@ -608,15 +646,6 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4, 4)))
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int lx = ((wave & 3) << 4) + (lane & 15), lyb = (wave >> 2) * 4 * PY + (lane >> 4);
 
-    if (*flag) {  // an offset exceeds its declared halo: refuse to gather
-        float nan[PY][C];
-        for (int j = 0; j < PY; ++j)
-            for (int c = 0; c < C; ++c) nan[j][c] = __builtin_nanf("");
-        for (; tile < tend; tile += nwg)
-            sv_store<C, TOut, PY>(Y, plane, W, H, (tile % tiles_x) * kTW + lx, (tile / tiles_x) * TH + lyb, nan);
-        return;
-    }
-
     const int SX = kTW + 2 * halo, SY = TH + 2 * halo;
     const int rowB = rowW * 4;
     constexpr int PXB = C >= 3 ? 16 : 4 * C;
@@ -624,24 +653,57 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4, 4)))
     const int wv = uniform(wave);                // the wave index, in a scalar register
     const int nq = (SX + 63) >> 6;               // <= kPipeNQ
     const int tabL = lds_offset(lds) + SY * rowB;
+    // raw == nullptr: the prepared table and its flag (set when an offset
+    // exceeds its declared halo).  raw != nullptr (TL only): the basis itself;
+    // this layer's rows are derived here with the same arithmetic as the table
+    // preparation, and its offsets checked against this layer's halo.
+    int bad = raw ? 0 : *flag;
     if (TL) {
         // this layer's rows of the coefficient table -> LDS (visible after the
         // first barrier below); the extra last row is zero
         const int nrow = G0 * N;
+        const float lim = static_cast<float>(halo - 1);
+        int mine = 0;
         for (int r = threadIdx.x; r <= nrow; r += 64 * NW) {
             v4f q0 = {0.0f, 0.0f, 0.0f, 0.0f}, q1 = q0, q2 = q0;
             if (r < nrow) {
                 const int k = r / N, i = r - k * N;
-                const float* g = table + (static_cast<size_t>(k) * T + tap0 + i) * kRow1D;
-                q0 = v4f{g[0], g[1], g[2], g[3]};
-                q1 = v4f{g[4], g[5], 0.0f, 0.0f};
-                q2 = v4f{g[6], g[7], g[8], 0.0f};
+                if (raw) {
+                    const int tap = tap0 + i;
+                    const float* A = raw + (static_cast<size_t>(k) * T + tap) * 3;
+                    const float* B = raw + (static_cast<size_t>(min(k + 1, G0 - 1)) * T + tap) * 3;
+                    const float* Cn = raw + (static_cast<size_t>(min(k + 2, G0 - 1)) * T + tap) * 3;
+                    float D[3], D2[3];
+#pragma unroll
+                    for (int j = 0; j < 3; ++j) {
+                        D[j] = (k + 1 < G0) ? B[j] - A[j] : 0.0f;
+                        D2[j] = (k + 2 < G0) ? Cn[j] - B[j] : 0.0f;
+                    }
+                    q0 = v4f{-A[0], -D[0], -A[1], -D[1]};
+                    q1 = v4f{A[2], D[2], 0.0f, 0.0f};
+                    q2 = v4f{-(D2[0] - D[0]), -(D2[1] - D[1]), D2[2] - D[2], 0.0f};
+                    if (!(fabsf(A[0]) <= lim && fabsf(A[1]) <= lim) || !isfinite(A[2])) mine = 1;
+                } else {
+                    const float* g = table + (static_cast<size_t>(k) * T + tap0 + i) * kRow1D;
+                    q0 = v4f{g[0], g[1], g[2], g[3]};
+                    q1 = v4f{g[4], g[5], 0.0f, 0.0f};
+                    q2 = v4f{g[6], g[7], g[8], 0.0f};
+                }
             }
             lds_v4f* d = reinterpret_cast<lds_v4f*>(static_cast<uintptr_t>(static_cast<uint32_t>(tabL + r * kRowLB)));
             d[0] = q0;
             d[1] = q1;
             d[2] = q2;
         }
+        if (raw) bad = __syncthreads_or(mine);
+    }
+    if (bad) {  // an offset exceeds its declared halo: refuse to gather
+        float nan[PY][C];
+        for (int j = 0; j < PY; ++j)
+            for (int c = 0; c < C; ++c) nan[j][c] = __builtin_nanf("");
+        for (; tile < tend; tile += nwg)
+            sv_store<C, TOut, PY>(Y, plane, W, H, (tile % tiles_x) * kTW + lx, (tile / tiles_x) * TH + lyb, nan);
+        return;
     }
     const int nr = (SY - wv + NW - 1) / NW;      // staged rows of this wave, <= kPipeRPW
     // one base pointer per plane and 32-bit element offsets inside a plane
@@ -860,7 +922,8 @@ static size_t pipe_lds_bytes(int halo, int G0, int N) {
 
 template <int C, int DIMS, typename TIn, typename TOut, int NW, int HMAX, int ROWB, bool TL>
 static hipError_t launch_pipe(const void* src, void* dst, const float* pmap, const float* table, int tap0, int N,
-                              int T, int G0, int G1, int H, int W, int halo, const int* flag, hipStream_t s) {
+                              int T, int G0, int G1, int H, int W, int halo, const int* flag, const float* raw,
+                              hipStream_t s) {
     constexpr int TH = PipeShape<NW, HMAX>::TH;
     const int tiles_x = (W + kTW - 1) / kTW, tiles_y = (H + TH - 1) / TH;
     const int ntiles = tiles_x * tiles_y;
@@ -878,7 +941,7 @@ static hipError_t launch_pipe(const void* src, void* dst, const float* pmap, con
     per_xcd = std::max(1, std::min(per_xcd, per));
     hipLaunchKernelGGL(fn, dim3(8 * per_xcd), dim3(64 * NW), lds, s, static_cast<const TIn*>(src),
                        static_cast<TOut*>(dst), pmap, table, tap0, N, T, G0, G1, H, W, halo, tiles_x, per, ntiles,
-                       flag, rowW);
+                       flag, rowW, raw);
     return hipGetLastError();
 }
 
@@ -904,7 +967,8 @@ static hipError_t launch_tiles(const void* src, void* dst, const float* pmap, co
 
 template <int C, int DIMS, typename TIn, typename TOut>
 static hipError_t launch_typed(const void* src, void* dst, const float* pmap, const float* table, int tap0, int N,
-                               int T, int G0, int G1, int H, int W, int halo, const int* flag, hipStream_t s) {
+                               int T, int G0, int G1, int H, int W, int halo, const int* flag, const float* raw,
+                               hipStream_t s) {
     static const int pipe = env_int("DISK_SV_PIPE", 1);
     // small halos: 8-wave work-groups of 64 x 16 tiles, two per CU, whose
     // staging and gather phases drift apart and overlap; larger ones: 16-wave
@@ -915,11 +979,12 @@ static hipError_t launch_typed(const void* src, void* dst, const float* pmap, co
     if (pipe && halo <= HMAX &&                                                                              \
         pipe_lds_bytes<C, DIMS, TIn, TOut, NW, HMAX, ROWB, TL>(halo, G0, N) <= static_cast<size_t>(BUDGET)) \
         return launch_pipe<C, DIMS, TIn, TOut, NW, HMAX, ROWB, TL>(src, dst, pmap, table, tap0, N, T, G0, G1, H, W, \
-                                                                  halo, flag, s);
+                                                                  halo, flag, raw, s);
     if constexpr (C >= 3 && DIMS == 1) {
         SV_TRY_PIPE(8, kPipeHalo8, kPipeRowB, true, 80 * 1024)
         SV_TRY_PIPE(16, kPipeHalo, kPipeRowB, true, 160 * 1024)
     }
+    if (raw) return hipErrorInvalidValue;   // the raw-basis path exists only in the kernels above
     if constexpr (C >= 3) {
         SV_TRY_PIPE(8, kPipeHalo8, kPipeRowB, false, 80 * 1024)
         SV_TRY_PIPE(16, kPipeHalo, kPipeRowB, false, 160 * 1024)
@@ -944,32 +1009,43 @@ static hipError_t launch_typed(const void* src, void* dst, const float* pmap, co
 template <int C, int DIMS>
 static hipError_t launch_py(int src_bf16, const void* src, int dst_bf16, void* dst, const float* pmap,
                             const float* table, int tap0, int N, int T, int G0, int G1, int H, int W, int halo,
-                            const int* flag, hipStream_t s) {
+                            const int* flag, const float* raw, hipStream_t s) {
     if (!src_bf16 && !dst_bf16)
-        return launch_typed<C, DIMS, float, float>(src, dst, pmap, table, tap0, N, T, G0, G1, H, W, halo, flag, s);
+        return launch_typed<C, DIMS, float, float>(src, dst, pmap, table, tap0, N, T, G0, G1, H, W, halo, flag, raw, s);
     if (src_bf16 && !dst_bf16)
-        return launch_typed<C, DIMS, uint16_t, float>(src, dst, pmap, table, tap0, N, T, G0, G1, H, W, halo, flag, s);
+        return launch_typed<C, DIMS, uint16_t, float>(src, dst, pmap, table, tap0, N, T, G0, G1, H, W, halo, flag, raw, s);
     if (!src_bf16 && dst_bf16)
-        return launch_typed<C, DIMS, float, uint16_t>(src, dst, pmap, table, tap0, N, T, G0, G1, H, W, halo, flag, s);
-    return launch_typed<C, DIMS, uint16_t, uint16_t>(src, dst, pmap, table, tap0, N, T, G0, G1, H, W, halo, flag, s);
+        return launch_typed<C, DIMS, float, uint16_t>(src, dst, pmap, table, tap0, N, T, G0, G1, H, W, halo, flag, raw, s);
+    return launch_typed<C, DIMS, uint16_t, uint16_t>(src, dst, pmap, table, tap0, N, T, G0, G1, H, W, halo, flag, raw, s);
 }
 
 template <int C>
 static hipError_t launch_dims(int dims, int src_bf16, const void* src, int dst_bf16, void* dst, const float* pmap,
                               const float* table, int tap0, int N, int T, int G0, int G1, int H, int W, int halo,
-                              const int* flag, hipStream_t s) {
-    if (dims == 1) return launch_py<C, 1>(src_bf16, src, dst_bf16, dst, pmap, table, tap0, N, T, G0, G1, H, W, halo, flag, s);
-    return launch_py<C, 2>(src_bf16, src, dst_bf16, dst, pmap, table, tap0, N, T, G0, G1, H, W, halo, flag, s);
+                              const int* flag, const float* raw, hipStream_t s) {
+    if (dims == 1) return launch_py<C, 1>(src_bf16, src, dst_bf16, dst, pmap, table, tap0, N, T, G0, G1, H, W, halo, flag, raw, s);
+    return launch_py<C, 2>(src_bf16, src, dst_bf16, dst, pmap, table, tap0, N, T, G0, G1, H, W, halo, flag, raw, s);
+}
+
+bool sv_pass_raw_ok(int C, int dims, int halo, int G0, int N) {
+    static const int pipe = env_int("DISK_SV_PIPE", 1);
+    if (C < 3 || dims != 1 || !pipe) return false;
+    // the same conditions as the table-in-LDS branches of launch_typed
+    if (halo <= kPipeHalo8 &&
+        pipe_lds_bytes<3, 1, float, float, 8, kPipeHalo8, kPipeRowB, true>(halo, G0, N) <= 80 * 1024)
+        return true;
+    return halo <= kPipeHalo &&
+           pipe_lds_bytes<3, 1, float, float, 16, kPipeHalo, kPipeRowB, true>(halo, G0, N) <= 160 * 1024;
 }
 
 hipError_t launch_sv_pass(int C, int dims, int src_bf16, const void* src, int dst_bf16, void* dst,
                           const float* pmap, const float* table, int tap0, int N, int T, int G0, int G1,
-                          int H, int W, int halo, const int* flag, hipStream_t s) {
+                          int H, int W, int halo, const int* flag, const float* raw, hipStream_t s) {
     switch (C) {
-        case 1: return launch_dims<1>(dims, src_bf16, src, dst_bf16, dst, pmap, table, tap0, N, T, G0, G1, H, W, halo, flag, s);
-        case 2: return launch_dims<2>(dims, src_bf16, src, dst_bf16, dst, pmap, table, tap0, N, T, G0, G1, H, W, halo, flag, s);
-        case 3: return launch_dims<3>(dims, src_bf16, src, dst_bf16, dst, pmap, table, tap0, N, T, G0, G1, H, W, halo, flag, s);
-        default: return launch_dims<4>(dims, src_bf16, src, dst_bf16, dst, pmap, table, tap0, N, T, G0, G1, H, W, halo, flag, s);
+        case 1: return launch_dims<1>(dims, src_bf16, src, dst_bf16, dst, pmap, table, tap0, N, T, G0, G1, H, W, halo, flag, raw, s);
+        case 2: return launch_dims<2>(dims, src_bf16, src, dst_bf16, dst, pmap, table, tap0, N, T, G0, G1, H, W, halo, flag, raw, s);
+        case 3: return launch_dims<3>(dims, src_bf16, src, dst_bf16, dst, pmap, table, tap0, N, T, G0, G1, H, W, halo, flag, raw, s);
+        default: return launch_dims<4>(dims, src_bf16, src, dst_bf16, dst, pmap, table, tap0, N, T, G0, G1, H, W, halo, flag, raw, s);
     }
 }
 

@@ -68,9 +68,13 @@ hipError_t launch_sv_prep(int dims, int G0, int G1, const LayerSpec& spec, const
                           const float* basis, float* table, int* flag, hipStream_t s);
 int sv_rows_per_wave(int halo, int C);
 size_t sv_lds_bytes(int halo, int C, int py, bool pad = true);
+// table + flag from launch_sv_prep (raw == nullptr), or raw = the basis itself
+// (1-D, C >= 3 layers for which sv_pass_raw_ok holds): the pass derives its
+// layer's coefficient rows and checks its offsets against `halo` on its own.
 hipError_t launch_sv_pass(int C, int dims, int src_bf16, const void* src, int dst_bf16, void* dst,
                           const float* pmap, const float* table, int tap0, int N, int T, int G0,
-                          int G1, int H, int W, int halo, const int* flag, hipStream_t s);
+                          int G1, int H, int W, int halo, const int* flag, const float* raw, hipStream_t s);
+bool sv_pass_raw_ok(int C, int dims, int halo, int G0, int N);
 
 // ---- optimize.hip: batched optimiser and radial init --------------------------
 int opt_workgroups(int B);

@@ -93,6 +93,43 @@ def test_sv_halo_violation_gives_nan(dev):
     assert torch.isnan(out).all()
 
 
+@pytest.mark.parametrize("C,io,taps,G", [
+    (3, torch.float32, [8, 8, 8, 8], 16),
+    (4, torch.float32, [5, 9, 3], 7),
+    (3, torch.bfloat16, [12, 12, 12, 12], 16),
+])
+def test_sv_one_shot_equals_prepared_table(dev, C, io, taps, G):
+    """disk_sv_filter on a 1-D basis with C >= 3 derives every layer's
+    coefficients inside its pass; the result must be bitwise the one of the
+    prepared-table path (disk_sv_prepare + disk_sv_apply)."""
+    basis = _basis(G, taps, seed=5 * C + G, r0=1.5, dr=0.9)
+    H, W = 123, 301
+    img = noise_image(H, W, C, seed=C, n_rects=8)
+    P = param_map(H, W, seed=4, period=64.0)
+    b = disk.make_basis(to_dev(basis), taps, [G])
+    x, p = to_dev(img).to(io), to_dev(P)
+    say("sv one-shot vs prepared", C, io, taps, G)
+    one = disk.disk_sv_filter(b, x, p)
+    prep = disk.disk_sv_apply(b, disk.disk_sv_prepare(b), x, p)
+    torch.cuda.synchronize()
+    assert torch.equal(one, prep)
+
+
+@pytest.mark.parametrize("bad_layer", [0, 2])
+def test_sv_halo_violation_one_shot_gives_nan(dev, bad_layer):
+    """The one-shot path checks each layer's offsets in that layer's pass: a
+    violation in any layer still leaves the whole output NaN."""
+    taps = [6, 6, 6]
+    basis = _basis(5, taps, seed=9, r0=2.0)
+    b = disk.make_basis(to_dev(basis), taps, [5])
+    b.desc.halo[bad_layer] = 1
+    img = to_dev(noise_image(40, 90, 3, seed=3, n_rects=4))
+    P = to_dev(param_map(40, 90, seed=5, period=32.0))
+    say("sv halo violation one-shot", bad_layer)
+    out = disk.disk_sv_filter(b, img, P)
+    assert torch.isnan(out).all()
+
+
 def test_sv_full_1080p_parity(dev):
     """The benchmark's launch configuration: 1920x1080x3 FP32, 16-entry basis of
     4 x 8 taps (offsets up to ~17 px), smooth blur map; whole frame vs oracle."""
