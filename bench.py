@@ -46,6 +46,7 @@ def parse():
     ap.add_argument("--no-time-to-40db", action="store_true")
     ap.add_argument("--no-2d", action="store_true")
     ap.add_argument("--no-ablations", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip the gradient-chain and network measurements")
     ap.add_argument("--time-to-40db-only", action="store_true",
                     help="only run the batched-optimisation comparison (for profiling it)")
     ap.add_argument("--copy-reference", type=int, default=0, metavar="MIB",
@@ -308,6 +309,97 @@ def angle_effects(torch, disk, steps=20):
     return res
 
 
+# Learned initialiser (64 x 64 input, conv3x3/s2 widths 32..256, FC 256-512-144):
+# multiply-adds per sample, layer by layer (output pixels x out channels x 9 x in channels)
+NET_MACS = [32 * 32 * 32 * 9 * 1, 16 * 16 * 64 * 9 * 32, 8 * 8 * 128 * 9 * 64, 4 * 4 * 128 * 9 * 128,
+            2 * 2 * 256 * 9 * 128, 1 * 1 * 256 * 9 * 256, 256 * 512, 512 * 144]
+NET_FLOP_FWD = 2 * sum(NET_MACS)                                   # 28.1 MFLOP per sample
+NET_FLOP_TRAIN = 3 * NET_FLOP_FWD - 2 * NET_MACS[0]                # + weight and input gradients (no dX of layer 1)
+MFMA_BF16_PEAK_TFLOPS = 2500.0
+
+
+def gradient_chain(torch, disk, steps=20):
+    """The image chain and its adjoint (the gradient kernels behind
+    autograd): 1920 x 1080 x 3 FP32, uniform 4 x 8 taps (offsets up to ~12 px),
+    CLAMP; forward with saved intermediates, then the gradients of Theta and
+    of the input.  Algorithmic HBM bytes per pixel and layer: forward 12 in +
+    12 out; adjoint 12 (X_{l-1}) + 12 (G_l) for the tap sums and 12 + 12 for
+    G_{l-1}."""
+    from synth import random_theta, noise_image
+    taps = [8, 8, 8, 8]
+    th = torch.as_tensor(random_theta(taps, 6.0, seed=21).astype(np.float32)).cuda()
+    x = torch.as_tensor(noise_image(H, W, C, seed=5)).cuda()
+    g = torch.randn(C, H, W, device="cuda", dtype=torch.float32)
+    stream = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    out, saved = disk.disk_forward(th, taps, x, save=True)
+    disk.disk_backward(th, taps, x, saved, g)
+    torch.cuda.synchronize()
+    fw = bw = 0.0
+    for _ in range(steps):
+        ev[0].record(stream)
+        out, saved = disk.disk_forward(th, taps, x, save=True, out=out)
+        ev[1].record(stream)
+        disk.disk_backward(th, taps, x, saved, g)
+        ev[2].record(stream)
+        torch.cuda.synchronize()
+        fw += ev[0].elapsed_time(ev[1])
+        bw += ev[1].elapsed_time(ev[2])
+    fw, bw = fw / steps, bw / steps
+    px, L = H * W, len(taps)
+    fb, bb = L * 24 * px, L * 48 * px
+    return {"workload": "chain_1080p_f32_4x8_clamp", "forward_ms": round(fw, 4), "backward_ms": round(bw, 4),
+            "forward_gbs": round(fb / (fw * 1e-3) / 1e9, 1), "backward_gbs": round(bb / (bw * 1e-3) / 1e9, 1),
+            "backward_hbm_frac": round(bb / (bw * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "bytes": {"forward": fb, "backward": bb}}
+
+
+def network_mfma(torch, disk, steps=20):
+    """The learned initialiser's BF16 MFMA GEMMs: inference on 4096 prepared
+    targets and one Adam training step at batch 256 and 4096, as algorithmic
+    TFLOP/s against the dense BF16 MFMA peak."""
+    from synth import mixed_batch, pack_targets
+    from paper_2512_04556_amd import train_init
+    weights = train_init.load()
+    bt = disk.make_batch(*pack_targets(mixed_batch(4096, seed=11, fixed_L=4, fixed_N=12)))
+    x, hw = disk.disk_net_prepare_inputs(bt)
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    res = {"peak_tflops": MFMA_BF16_PEAK_TFLOPS, "flop_per_sample": {"inference": NET_FLOP_FWD,
+                                                                     "train_step": NET_FLOP_TRAIN}}
+    pws = torch.empty(int(disk.lib().disk_net_predict_workspace_size(4096)), dtype=torch.uint8, device="cuda")
+    ref = disk.disk_init_predict(weights, x, hw, ws=pws)
+    for _ in range(3):
+        disk.disk_init_predict(weights, x, hw, ws=pws)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(steps):
+        disk.disk_init_predict(weights, x, hw, ws=pws)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    tf = NET_FLOP_FWD * 4096 / (ms * 1e-3) / 1e12
+    res["inference_b4096"] = {"ms": round(ms, 4), "tflops": round(tf, 2), "frac": round(tf / MFMA_BF16_PEAK_TFLOPS, 4)}
+    for B in (256, 4096):
+        prm = weights.clone()
+        m, v = torch.zeros_like(prm), torch.zeros_like(prm)
+        xs, hs, rs = x[:B].contiguous(), hw[:B].contiguous(), ref[:B].contiguous()
+        ws = disk.net_workspace(B)
+        for k in range(3):
+            disk.disk_net_train_step(prm, m, v, k + 1, 1e-4, xs, hs, rs, ws=ws)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for k in range(steps):
+            disk.disk_net_train_step(prm, m, v, k + 4, 1e-4, xs, hs, rs, ws=ws)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        tf = NET_FLOP_TRAIN * B / (ms * 1e-3) / 1e12
+        res[f"train_step_b{B}"] = {"ms": round(ms, 4), "tflops": round(tf, 2),
+                                   "frac": round(tf / MFMA_BF16_PEAK_TFLOPS, 4)}
+    return res
+
+
 def time_to_40db(torch, disk, n=4096):
     """Batched optimisation of n fresh targets (odd sides 15..127, the shape
     families of the batching workload, 4 layers x 12 taps, seed 7) to 40 dB or
@@ -455,6 +547,12 @@ def main():
         res["ablations"] = ablations(torch, disk)
     if not a.no_2d:
         res["sv2d_4k_bf16"] = sv2d_4k(torch, disk)
+    if not a.no_extras:
+        res["gradient_chain_1080p"] = gradient_chain(torch, disk)
+        try:
+            res["network_mfma"] = network_mfma(torch, disk)
+        except (OSError, ValueError) as e:
+            res["network_mfma"] = {"missing_weights": str(e)}
     if not a.no_time_to_40db:
         res["time_to_40db"] = time_to_40db(torch, disk)
     if not a.no_cpu_baseline:

@@ -105,6 +105,27 @@ def test_impulse_backward_parity(dev, M, taps):
     assert e <= 1e-4
 
 
+def test_image_chain_1080p_bench_configuration(dev):
+    """The gradient workload the benchmark times: 1920 x 1080 x 3 FP32, uniform
+    4 x 8 taps (offsets up to ~6 px), CLAMP; forward with saved intermediates,
+    then dTheta and the input gradient, the whole frame against the oracle."""
+    taps = [8, 8, 8, 8]
+    th = random_theta(taps, 6.0, seed=21).astype(np.float32)
+    H, W = 1080, 1920
+    img = noise_image(H, W, 3, seed=5)
+    G = np.random.default_rng(6).standard_normal((3, H, W)).astype(np.float32)
+    say("image chain 1080p forward + backward")
+    out, saved = disk.disk_forward(to_dev(th), taps, to_dev(img), boundary=S.CLAMP, save=True)
+    gt, gi = disk.disk_backward(to_dev(th), taps, to_dev(img), saved, to_dev(G), boundary=S.CLAMP)
+    got_out, got_t, got_i = to_np(out), to_np(gt), to_np(gi)
+    want_out = S.chain(img.astype(np.float64), th.astype(np.float64), taps, S.CLAMP)
+    assert rel_err(got_out, want_out) <= TOL_F32
+    wt, wi = A.chain_vjp(img.astype(np.float64), th.astype(np.float64), taps, S.CLAMP, G.astype(np.float64))
+    et, ei = rel_err(got_t, wt), rel_err(got_i, wi)
+    print(f"1080p backward: dtheta {et:.2e} dinput {ei:.2e}")
+    assert et <= 1e-4 and ei <= TOL_F32
+
+
 def test_backward_deterministic(dev):
     taps = [8, 8]
     th = to_dev(random_theta(taps, 5.0, seed=3))
