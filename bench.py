@@ -47,6 +47,8 @@ def parse():
     ap.add_argument("--no-2d", action="store_true")
     ap.add_argument("--no-ablations", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the gradient-chain and network measurements")
+    ap.add_argument("--extras-only", action="store_true",
+                    help="only the gradient-chain and network measurements (for profiling them)")
     ap.add_argument("--time-to-40db-only", action="store_true",
                     help="only run the batched-optimisation comparison (for profiling it)")
     ap.add_argument("--copy-reference", type=int, default=0, metavar="MIB",
@@ -473,6 +475,10 @@ def main():
     from synth import noise_image, param_map
     if a.time_to_40db_only:
         print(json.dumps(time_to_40db(torch, disk)), flush=True)
+        return
+    if a.extras_only:
+        print(json.dumps({"gradient_chain_1080p": gradient_chain(torch, disk),
+                          "network_mfma": network_mfma(torch, disk)}), flush=True)
         return
 
     img = noise_image(H, W, C, seed=2)

@@ -294,16 +294,19 @@ __global__ __launch_bounds__(256) void pack_kernel(PackArgs a, const float* __re
 }
 
 // Loss (before the update) and dL/dy_hat = 2 (y_hat - y) / (B 144), y the
-// reference in network units.  One work-group, fixed summation order.
-__global__ __launch_bounds__(1024) void loss_kernel(int B, const float* __restrict__ yhat,
-                                                    const float* __restrict__ ref, const float* __restrict__ hw,
-                                                    float* __restrict__ g32, uint16_t* __restrict__ gq,
-                                                    float* __restrict__ loss_out) {
-    __shared__ float red[16];
+// reference in network units.  Grid-stride over the B x 144 outputs; each
+// block writes its partial sum of squares (fixed order inside the block), and
+// loss_final_kernel adds the partials in block order.
+constexpr int kLossBlocks = 256;
+__global__ __launch_bounds__(256) void loss_grad_kernel(int B, const float* __restrict__ yhat,
+                                                        const float* __restrict__ ref, const float* __restrict__ hw,
+                                                        float* __restrict__ g32, uint16_t* __restrict__ gq,
+                                                        float* __restrict__ part) {
+    __shared__ float red[4];
     const long n = static_cast<long>(B) * kOut;
     const float fn = static_cast<float>(n);
     float s = 0.0f;
-    for (long i = threadIdx.x; i < n; i += 1024) {
+    for (long i = blockIdx.x * 256L + threadIdx.x; i < n; i += static_cast<long>(gridDim.x) * 256) {
         const int b = static_cast<int>(i / kOut), c = static_cast<int>(i - static_cast<long>(b) * kOut);
         const float y = (c % 3) < 2 ? ref[i] / hw[b] : ref[i];
         const float d = yhat[i] - y;
@@ -315,11 +318,20 @@ __global__ __launch_bounds__(1024) void loss_kernel(int B, const float* __restri
     s = wave_sum(s);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
     __syncthreads();
-    if (threadIdx.x == 0) {
-        float t = 0.0f;
-        for (int i = 0; i < 16; ++i) t += red[i];
-        loss_out[0] = t / fn;
+    if (threadIdx.x == 0) part[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+__global__ __launch_bounds__(256) void loss_final_kernel(const float* __restrict__ part, int nb, long n,
+                                                         float* __restrict__ loss_out) {
+    __shared__ float buf[256];
+    float v = 0.0f;
+    for (int b = threadIdx.x; b < nb; b += 256) v += part[b];
+    buf[threadIdx.x] = v;
+    __syncthreads();
+    for (int m = 128; m >= 1; m >>= 1) {
+        if (threadIdx.x < m) buf[threadIdx.x] += buf[threadIdx.x + m];
+        __syncthreads();
     }
+    if (threadIdx.x == 0) loss_out[0] = buf[0] / static_cast<float>(n);
 }
 
 // Column sums of g [M][N] (FP32): stage 1 writes part[blk][N] for 256-row
@@ -334,13 +346,20 @@ __global__ __launch_bounds__(256) void colsum_part_kernel(const float* __restric
         part[static_cast<size_t>(blockIdx.x) * N + n] = s;
     }
 }
+// One work-group per column: strided partial sums, then a fixed tree.
 __global__ __launch_bounds__(256) void colsum_final_kernel(const float* __restrict__ part, int nblk, int N,
                                                            float* __restrict__ out) {
-    const int n = blockIdx.x * 256 + threadIdx.x;
-    if (n >= N) return;
+    __shared__ float buf[256];
+    const int n = blockIdx.x;
     float s = 0.0f;
-    for (int b = 0; b < nblk; ++b) s += part[static_cast<size_t>(b) * N + n];
-    out[n] = s;
+    for (int b = threadIdx.x; b < nblk; b += 256) s += part[static_cast<size_t>(b) * N + n];
+    buf[threadIdx.x] = s;
+    __syncthreads();
+    for (int m = 128; m >= 1; m >>= 1) {
+        if (threadIdx.x < m) buf[threadIdx.x] += buf[threadIdx.x + m];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[n] = buf[0];
 }
 
 // Sum the split-K slabs of a weight gradient [S][cout][Kp] into the blob's
@@ -591,7 +610,13 @@ hipError_t net_backward(const float* params, const uint16_t* x0, const float* re
     float* dcol = reinterpret_cast<float*>(ws + w.dcol);
     float* part = reinterpret_cast<float*>(ws + w.part);
     float* cpart = reinterpret_cast<float*>(ws + w.cpart);
-    hipLaunchKernelGGL(loss_kernel, dim3(1), dim3(1024), 0, s, B, yhat, ref, hw, g32[0], gq[0], loss_out);
+    {
+        // the loss partials use the column-sum scratch (>= 128 B floats: layer 1's slab count x 32)
+        const long n = static_cast<long>(B) * kOut;
+        const int nb = static_cast<int>(std::min<long>(kLossBlocks, (n + 1023) / 1024));
+        hipLaunchKernelGGL(loss_grad_kernel, dim3(nb), dim3(256), 0, s, B, yhat, ref, hw, g32[0], gq[0], cpart);
+        hipLaunchKernelGGL(loss_final_kernel, dim3(1), dim3(256), 0, s, cpart, nb, n, loss_out);
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     int cur = 0;
@@ -602,7 +627,7 @@ hipError_t net_backward(const float* params, const uint16_t* x0, const float* re
         // bias gradient: column sums of g (FP32)
         const int nblk = (M + kColRows - 1) / kColRows;
         hipLaunchKernelGGL(colsum_part_kernel, dim3(nblk), dim3(256), 0, s, g32[cur], M, L.cout, cpart);
-        hipLaunchKernelGGL(colsum_final_kernel, dim3((L.cout + 255) / 256), dim3(256), 0, s, cpart, nblk, L.cout,
+        hipLaunchKernelGGL(colsum_final_kernel, dim3(L.cout), dim3(256), 0, s, cpart, nblk, L.cout,
                            grad + L.b_off);
         // weight gradient: dW(co, j) = sum_m g(m, co) x_col(m, j), split over m
         int S, kc;
