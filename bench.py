@@ -333,21 +333,23 @@ def gradient_chain(torch, disk, steps=20):
     x = torch.as_tensor(noise_image(H, W, C, seed=5)).cuda()
     g = torch.randn(C, H, W, device="cuda", dtype=torch.float32)
     stream = torch.cuda.current_stream()
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     out, saved = disk.disk_forward(th, taps, x, save=True)
     disk.disk_backward(th, taps, x, saved, g)
     torch.cuda.synchronize()
-    fw = bw = 0.0
+    # back-to-back calls (as a training loop issues them): device time per call
+    e0.record(stream)
     for _ in range(steps):
-        ev[0].record(stream)
         out, saved = disk.disk_forward(th, taps, x, save=True, out=out)
-        ev[1].record(stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    fw = e0.elapsed_time(e1) / steps
+    e0.record(stream)
+    for _ in range(steps):
         disk.disk_backward(th, taps, x, saved, g)
-        ev[2].record(stream)
-        torch.cuda.synchronize()
-        fw += ev[0].elapsed_time(ev[1])
-        bw += ev[1].elapsed_time(ev[2])
-    fw, bw = fw / steps, bw / steps
+    e1.record(stream)
+    torch.cuda.synchronize()
+    bw = e0.elapsed_time(e1) / steps
     px, L = H * W, len(taps)
     fb, bb = L * 24 * px, L * 48 * px
     return {"workload": "chain_1080p_f32_4x8_clamp", "forward_ms": round(fw, 4), "backward_ms": round(bw, 4),

@@ -160,8 +160,20 @@ disk_status disk_forward(const disk_complex* cx, const float* theta, const void*
         return fail(DISK_WORKSPACE_TOO_SMALL, "workspace %zu < %zu bytes", ws_bytes, cv.used);
     const LayerSpec sp = make_spec(*cx);
     const size_t n = image_floats(C, H, W);
-    DISK_HIP(launch_prep_uniform(theta, sp.T, tapu, stream), "prep");
     const int io_kind = io == DISK_BF16 ? 1 : 0;
+    if (!impulse && chain_pass_ok(C, boundary)) {
+        // images with C = 3, 4 and CLAMP: the LDS-staged pass kernel, taps from Theta
+        for (int l = 0; l < sp.L; ++l) {
+            const void* src = l == 0 ? in : (saved ? saved + (l - 1) * n : ((l - 1) % 2 ? b1 : b0));
+            void* dst = l == sp.L - 1 ? out : (saved ? saved + l * n : (l % 2 ? b1 : b0));
+            const int sb = (l == 0 && io_kind) ? 1 : 0;
+            const int db = (l == sp.L - 1 && io_kind) ? 1 : 0;
+            DISK_HIP(launch_chain_pass(C, sb, src, db, dst, theta, sp.tap0[l], sp.taps[l], sp.T, H, W, stream),
+                     "chain layer");
+        }
+        return ok();
+    }
+    DISK_HIP(launch_prep_uniform(theta, sp.T, tapu, stream), "prep");
     for (int l = 0; l < sp.L; ++l) {
         const void* src;
         int src_kind;
@@ -254,8 +266,17 @@ disk_status disk_backward(const disk_complex* cx, const float* theta, const floa
         }
         if (l > 0 || grad_in) {
             float* Gn = l == 0 ? grad_in : (G == g0 ? g1 : g0);
-            DISK_HIP(launch_adjoint_input(C, boundary, G, tapu + sp.tap0[l], sp.taps[l], H, W, Gn, stream),
-                     "adjoint input");
+            if (!impulse && chain_pass_ok(C, DISK_CLAMP)) {
+                // staged transposed gather; CLAMP border pixels recomputed exactly
+                DISK_HIP(launch_chain_transpose(C, G, Gn, theta, sp.tap0[l], sp.taps[l], sp.T, H, W, stream),
+                         "adjoint input");
+                if (boundary == DISK_CLAMP)
+                    DISK_HIP(launch_adjoint_input_border(C, G, tapu + sp.tap0[l], sp.taps[l], H, W, Gn, stream),
+                             "adjoint input border");
+            } else {
+                DISK_HIP(launch_adjoint_input(C, boundary, G, tapu + sp.tap0[l], sp.taps[l], H, W, Gn, stream),
+                         "adjoint input");
+            }
             G = Gn;
         }
     }

@@ -206,15 +206,12 @@ __device__ __forceinline__ void preimage(int q, int d, int n, int& lo, int& hi) 
     hi = min(hi, n - 1);
 }
 
+// Gprev at pixel (x, y): the exact transpose (border pixels of CLAMP sum the
+// run or block of output pixels whose clamped corner lands on them).
 template <int C, int BOUND>
-__global__ __launch_bounds__(256) void adjoint_input_kernel(const float* __restrict__ G,
-                                                            const TapU* __restrict__ taps, int N, int H,
-                                                            int W, float* __restrict__ Gprev) {
-    const int x = blockIdx.x * 64 + (threadIdx.x & 63);
-    const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
-    if (x >= W || y >= H) return;
+__device__ __forceinline__ void input_adjoint_pixel(const float* __restrict__ G, const TapU* __restrict__ taps, int N,
+                                                    int H, int W, int x, int y, float (&acc)[C]) {
     const size_t plane = static_cast<size_t>(H) * W;
-    float acc[C];
 #pragma unroll
     for (int c = 0; c < C; ++c) acc[c] = 0.0f;
     const bool border = (BOUND == DISK_CLAMP) && (x == 0 || y == 0 || x == W - 1 || y == H - 1);
@@ -244,8 +241,61 @@ __global__ __launch_bounds__(256) void adjoint_input_kernel(const float* __restr
             }
         }
     }
+}
+
+template <int C, int BOUND>
+__global__ __launch_bounds__(256) void adjoint_input_kernel(const float* __restrict__ G,
+                                                            const TapU* __restrict__ taps, int N, int H,
+                                                            int W, float* __restrict__ Gprev) {
+    const int x = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
+    if (x >= W || y >= H) return;
+    const size_t plane = static_cast<size_t>(H) * W;
+    float acc[C];
+    input_adjoint_pixel<C, BOUND>(G, taps, N, H, W, x, y, acc);
 #pragma unroll
     for (int c = 0; c < C; ++c) Gprev[c * plane + static_cast<size_t>(y) * W + x] = acc[c];
+}
+
+// The CLAMP border pixels only (rows 0 and H-1, columns 0 and W-1): run after
+// the interior was produced by the zero-padded transposed gather.
+template <int C>
+__global__ __launch_bounds__(256) void adjoint_input_border_kernel(const float* __restrict__ G,
+                                                                   const TapU* __restrict__ taps, int N, int H,
+                                                                   int W, float* __restrict__ Gprev) {
+    const long nb = (H <= 2 || W <= 2) ? static_cast<long>(H) * W : 2L * W + 2L * (H - 2);
+    const long i = static_cast<long>(blockIdx.x) * 256 + threadIdx.x;
+    if (i >= nb) return;
+    int x, y;
+    if (H <= 2 || W <= 2) {
+        y = static_cast<int>(i / W);
+        x = static_cast<int>(i - static_cast<long>(y) * W);
+    } else if (i < 2L * W) {
+        y = i < W ? 0 : H - 1;
+        x = static_cast<int>(i < W ? i : i - W);
+    } else {
+        const int j = static_cast<int>(i - 2L * W);
+        x = j < H - 2 ? 0 : W - 1;
+        y = 1 + (j < H - 2 ? j : j - (H - 2));
+    }
+    const size_t plane = static_cast<size_t>(H) * W;
+    float acc[C];
+    input_adjoint_pixel<C, DISK_CLAMP>(G, taps, N, H, W, x, y, acc);
+#pragma unroll
+    for (int c = 0; c < C; ++c) Gprev[c * plane + static_cast<size_t>(y) * W + x] = acc[c];
+}
+
+hipError_t launch_adjoint_input_border(int C, const float* G, const TapU* taps, int N, int H, int W, float* Gprev,
+                                       hipStream_t s) {
+    const long nb = (H <= 2 || W <= 2) ? static_cast<long>(H) * W : 2L * W + 2L * (H - 2);
+    const dim3 grid(static_cast<unsigned>((nb + 255) / 256)), block(256);
+    if (C == 3)
+        hipLaunchKernelGGL((adjoint_input_border_kernel<3>), grid, block, 0, s, G, taps, N, H, W, Gprev);
+    else if (C == 4)
+        hipLaunchKernelGGL((adjoint_input_border_kernel<4>), grid, block, 0, s, G, taps, N, H, W, Gprev);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
 }
 
 template <int C>

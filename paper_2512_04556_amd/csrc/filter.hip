@@ -31,6 +31,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdlib>
+#include <mutex>
 #include <type_traits>
 
 namespace disk {
@@ -625,6 +626,59 @@ struct PipeShape {
     static constexpr int NQ = (kTW + 2 * HMAX + 63) / 64;                  // 64-column chunks
 };
 
+// Uniform chain layer whose offsets exceed the staged halo (or are not
+// finite): the work-group's tiles with corners read straight from the clamped
+// source planes, in the staged path's arithmetic and order.
+// tr: the transposed layer (offsets negated, reads outside the image are 0).
+template <int C, typename TIn, typename TOut, int PY, int TH>
+__device__ void chain_tiles_global(const TIn* __restrict__ X, TOut* __restrict__ Y, const float* __restrict__ raw,
+                                   int tap0, int N, int H, int W, int tile, int tend, int nwg, int tiles_x, int lx,
+                                   int lyb, bool tr) {
+    const size_t plane = static_cast<size_t>(H) * W;
+    for (; tile < tend; tile += nwg) {
+        const int x = (tile % tiles_x) * kTW + lx, y0 = (tile / tiles_x) * TH + lyb;
+        float acc[PY][C];
+#pragma unroll
+        for (int j = 0; j < PY; ++j)
+#pragma unroll
+            for (int c = 0; c < C; ++c) acc[j][c] = 0.0f;
+        for (int i = 0; i < N; ++i) {
+            const float* r = raw + static_cast<size_t>(tap0 + i) * 3;
+            const float nx = tr ? r[0] : -r[0], ny = tr ? r[1] : -r[1], w = r[2];
+            const float flx = floorf(nx), fly = floorf(ny);
+            const float fx = nx - flx, fy = ny - fly;
+            const float wy1 = w * fy, wy0 = w - wy1;
+            const float c01 = wy0 * fx, c00 = wy0 - c01;
+            const float c11 = wy1 * fx, c10 = wy1 - c11;
+            // integer parts bounded before conversion (a non-finite offset
+            // still reads in bounds; its NaN weights carry to the output)
+            const int dx = static_cast<int>(fminf(fmaxf(flx, -1048576.0f), 1048576.0f));
+            const int dy = static_cast<int>(fminf(fmaxf(fly, -1048576.0f), 1048576.0f));
+            const int xa = min(max(x + dx, 0), W - 1), xb = min(max(x + dx + 1, 0), W - 1);
+            // ZERO reads (tr): a corner outside the image contributes 0
+            const bool ia = !tr || (x + dx >= 0 && x + dx < W), ib = !tr || (x + dx + 1 >= 0 && x + dx + 1 < W);
+#pragma unroll
+            for (int j = 0; j < PY; ++j) {
+                const int y = y0 + 4 * j;
+                const size_t ra = static_cast<size_t>(min(max(y + dy, 0), H - 1)) * W;
+                const size_t rb = static_cast<size_t>(min(max(y + dy + 1, 0), H - 1)) * W;
+                const bool ja = !tr || (y + dy >= 0 && y + dy < H), jb = !tr || (y + dy + 1 >= 0 && y + dy + 1 < H);
+#pragma unroll
+                for (int c = 0; c < C; ++c) {
+                    const size_t o = c * plane;
+                    float a = acc[j][c];
+                    a = fmaf(c00, (ja && ia) ? IO<TIn>::load(X, o + ra + xa) : 0.0f, a);
+                    a = fmaf(c01, (ja && ib) ? IO<TIn>::load(X, o + ra + xb) : 0.0f, a);
+                    a = fmaf(c10, (jb && ia) ? IO<TIn>::load(X, o + rb + xa) : 0.0f, a);
+                    a = fmaf(c11, (jb && ib) ? IO<TIn>::load(X, o + rb + xb) : 0.0f, a);
+                    acc[j][c] = a;
+                }
+            }
+        }
+        sv_store<C, TOut, PY>(Y, plane, W, H, x, y0, acc);
+    }
+}
+
 // ROWB > 0 (C >= 3): the staged row stride in bytes, fixed at compile time
 // (rowW is then ROWB / 4).  TL (1-D bases): the layer's coefficient rows are
 // staged in LDS after the tile, at byte offset SY * rowB.
@@ -645,6 +699,27 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4, 4)))
     const size_t plane = static_cast<size_t>(H) * W;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int lx = ((wave & 3) << 4) + (lane & 15), lyb = (wave >> 2) * 4 * PY + (lane >> 4);
+
+    // halo < 0 (TL, raw = Theta, G0 = 1, P == nullptr): a uniform chain layer;
+    // halo == -2: its transpose (offsets negated, the tile staged with zeros
+    // outside the image: the input adjoint away from CLAMP-border pixels).
+    // The halo comes from the layer's own taps (every wave reads the N <= 32
+    // taps): ceil(max |offset|) + 1; beyond HMAX the tiles take the global path.
+    const bool chain = halo < 0, trans = halo == -2;
+    if (TL && chain) {
+        float m = 0.0f;
+        if (lane < N) {
+            const float* r = raw + static_cast<size_t>(tap0 + lane) * 3;
+            m = fmaxf(fabsf(r[0]), fabsf(r[1]));
+            if (!(m <= 1.0e6f)) m = 1.0e6f;    // non-finite or huge
+        }
+        halo = uniform(static_cast<int>(ceilf(wave_max(m))) + 1);
+        if (halo > HMAX) {
+            chain_tiles_global<C, TIn, TOut, PY, TH>(X, Y, raw, tap0, N, H, W, tile, tend, nwg, tiles_x, lx, lyb,
+                                                     trans);
+            return;
+        }
+    }
 
     const int SX = kTW + 2 * halo, SY = TH + 2 * halo;
     const int rowB = rowW * 4;
@@ -679,10 +754,10 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4, 4)))
                         D[j] = (k + 1 < G0) ? B[j] - A[j] : 0.0f;
                         D2[j] = (k + 2 < G0) ? Cn[j] - B[j] : 0.0f;
                     }
-                    q0 = v4f{-A[0], -D[0], -A[1], -D[1]};
+                    q0 = trans ? v4f{A[0], D[0], A[1], D[1]} : v4f{-A[0], -D[0], -A[1], -D[1]};
                     q1 = v4f{A[2], D[2], 0.0f, 0.0f};
                     q2 = v4f{-(D2[0] - D[0]), -(D2[1] - D[1]), D2[2] - D[2], 0.0f};
-                    if (!(fabsf(A[0]) <= lim && fabsf(A[1]) <= lim) || !isfinite(A[2])) mine = 1;
+                    if (!chain && (!(fabsf(A[0]) <= lim && fabsf(A[1]) <= lim) || !isfinite(A[2]))) mine = 1;
                 } else {
                     const float* g = table + (static_cast<size_t>(k) * T + tap0 + i) * kRow1D;
                     q0 = v4f{g[0], g[1], g[2], g[3]};
@@ -713,26 +788,35 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4, 4)))
     for (int c = 0; c < C; ++c) Xc[c] = X + c * plane;
     const float* Pd[DIMS];
 #pragma unroll
-    for (int d = 0; d < DIMS; ++d) Pd[d] = P + d * plane;
+    for (int d = 0; d < DIMS; ++d) Pd[d] = P ? P + d * plane : nullptr;
 
     float stg[kPipeRPW][kPipeNQ][C];
     float pv[PY][DIMS];
     auto issue = [&](int t) {
         const int tx0 = (t % tiles_x) * kTW, ty0 = (t / tiles_x) * TH;
         uint32_t gx[kPipeNQ];
+        bool vx[kPipeNQ];
 #pragma unroll
-        for (int q = 0; q < kPipeNQ; ++q) gx[q] = static_cast<uint32_t>(min(max(tx0 - halo + lane + 64 * q, 0), W - 1));
+        for (int q = 0; q < kPipeNQ; ++q) {
+            const int cx = tx0 - halo + lane + 64 * q;
+            gx[q] = static_cast<uint32_t>(min(max(cx, 0), W - 1));
+            vx[q] = !trans || static_cast<unsigned>(cx) < static_cast<unsigned>(W);
+        }
 #pragma unroll
         for (int rr = 0; rr < kPipeRPW; ++rr) {
             if (rr < nr) {
-                const uint32_t grow = static_cast<uint32_t>(min(max(ty0 - halo + wv + NW * rr, 0), H - 1)) *
-                                      static_cast<uint32_t>(W);
+                const int ry = ty0 - halo + wv + NW * rr;
+                const uint32_t grow = static_cast<uint32_t>(min(max(ry, 0), H - 1)) * static_cast<uint32_t>(W);
+                const bool vy = !trans || static_cast<unsigned>(ry) < static_cast<unsigned>(H);
 #pragma unroll
                 for (int q = 0; q < kPipeNQ; ++q) {
                     if (q < nq) {
                         const uint32_t off = (grow + gx[q]) * static_cast<uint32_t>(sizeof(TIn));   // bytes
 #pragma unroll
-                        for (int c = 0; c < C; ++c) stg[rr][q][c] = IO<TIn>::load(byte_at(Xc[c], off), 0);
+                        for (int c = 0; c < C; ++c) {
+                            const float v = IO<TIn>::load(byte_at(Xc[c], off), 0);
+                            stg[rr][q][c] = (vy && vx[q]) ? v : 0.0f;
+                        }
                     }
                 }
             }
@@ -742,7 +826,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4, 4)))
         for (int j = 0; j < PY; ++j) {
             const uint32_t pi = (static_cast<uint32_t>(min(ty0 + 4 * j + lyb, H - 1)) * static_cast<uint32_t>(W) + xc) * 4u;
 #pragma unroll
-            for (int d = 0; d < DIMS; ++d) pv[j][d] = *byte_at(Pd[d], pi);
+            for (int d = 0; d < DIMS; ++d) pv[j][d] = P ? *byte_at(Pd[d], pi) : 0.0f;
         }
     };
 
@@ -928,15 +1012,34 @@ static hipError_t launch_pipe(const void* src, void* dst, const float* pmap, con
     const int tiles_x = (W + kTW - 1) / kTW, tiles_y = (H + TH - 1) / TH;
     const int ntiles = tiles_x * tiles_y;
     const int per = (ntiles + 7) / 8;
-    const size_t lds = pipe_lds_bytes<C, DIMS, TIn, TOut, NW, HMAX, ROWB, TL>(halo, G0, N);
-    const int rowW = ROWB > 0 ? ROWB / 4 : sv_row_dwords(halo, C);
+    const int hs = halo < 0 ? HMAX : halo;   // chain layers (halo < 0) size the tile for HMAX
+    const size_t lds = pipe_lds_bytes<C, DIMS, TIn, TOut, NW, HMAX, ROWB, TL>(hs, G0, N);
+    const int rowW = ROWB > 0 ? ROWB / 4 : sv_row_dwords(hs, C);
     auto fn = sv_pass_pipe_kernel<C, DIMS, TIn, TOut, NW, HMAX, ROWB, TL>;
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
-    if (e != hipSuccess) return e;
-    int occ = 0;
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, reinterpret_cast<const void*>(fn), 64 * NW, lds);
-    if (e != hipSuccess || occ < 1) occ = 1;
+    // Host queries once per kernel and LDS size (launches of a frame repeat them)
+    static std::mutex mu;
+    static size_t attr_lds = 0, occ_lds = 0;
+    static int occ_cached = 1;
+    int occ = 1;
+    {
+        std::lock_guard<std::mutex> lock(mu);
+        if (lds > attr_lds) {
+            hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
+            if (e != hipSuccess) return e;
+            attr_lds = lds;
+        }
+        if (lds != occ_lds) {
+            int o = 0;
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, reinterpret_cast<const void*>(fn), 64 * NW, lds) !=
+                    hipSuccess ||
+                o < 1)
+                o = 1;
+            occ_cached = o;
+            occ_lds = lds;
+        }
+        occ = occ_cached;
+    }
     int per_xcd = (cu_count() * occ) / 8;                 // work-groups per XCD
     per_xcd = std::max(1, std::min(per_xcd, per));
     hipLaunchKernelGGL(fn, dim3(8 * per_xcd), dim3(64 * NW), lds, s, static_cast<const TIn*>(src),
@@ -1025,6 +1128,46 @@ static hipError_t launch_dims(int dims, int src_bf16, const void* src, int dst_b
                               const int* flag, const float* raw, hipStream_t s) {
     if (dims == 1) return launch_py<C, 1>(src_bf16, src, dst_bf16, dst, pmap, table, tap0, N, T, G0, G1, H, W, halo, flag, raw, s);
     return launch_py<C, 2>(src_bf16, src, dst_bf16, dst, pmap, table, tap0, N, T, G0, G1, H, W, halo, flag, raw, s);
+}
+
+// One layer of a uniform chain on an image (CLAMP), as a pass of the staged
+// kernel with a single-entry basis (Theta itself) and no parameter map: every
+// pixel sits in the one interval at t = 0, so its coefficients are Theta's.
+template <int C, typename TIn, typename TOut>
+static hipError_t chain_typed(const void* src, void* dst, const float* theta, int tap0, int N, int T, int H, int W,
+                              hipStream_t s) {
+    return launch_pipe<C, 1, TIn, TOut, 16, kPipeHalo, kPipeRowB, true>(src, dst, nullptr, nullptr, tap0, N, T, 1, 1,
+                                                                        H, W, -1, nullptr, theta, s);
+}
+template <int C>
+static hipError_t chain_io(int src_bf16, const void* src, int dst_bf16, void* dst, const float* theta, int tap0,
+                           int N, int T, int H, int W, hipStream_t s) {
+    if (!src_bf16 && !dst_bf16) return chain_typed<C, float, float>(src, dst, theta, tap0, N, T, H, W, s);
+    if (src_bf16 && !dst_bf16) return chain_typed<C, uint16_t, float>(src, dst, theta, tap0, N, T, H, W, s);
+    if (!src_bf16 && dst_bf16) return chain_typed<C, float, uint16_t>(src, dst, theta, tap0, N, T, H, W, s);
+    return chain_typed<C, uint16_t, uint16_t>(src, dst, theta, tap0, N, T, H, W, s);
+}
+template <int C>
+static hipError_t chain_trans_c(const float* G, float* Gprev, const float* theta, int tap0, int N, int T, int H, int W,
+                                hipStream_t s) {
+    return launch_pipe<C, 1, float, float, 16, kPipeHalo, kPipeRowB, true>(G, Gprev, nullptr, nullptr, tap0, N, T, 1, 1,
+                                                                          H, W, -2, nullptr, theta, s);
+}
+hipError_t launch_chain_transpose(int C, const float* G, float* Gprev, const float* theta, int tap0, int N, int T,
+                                  int H, int W, hipStream_t s) {
+    if (C == 3) return chain_trans_c<3>(G, Gprev, theta, tap0, N, T, H, W, s);
+    if (C == 4) return chain_trans_c<4>(G, Gprev, theta, tap0, N, T, H, W, s);
+    return hipErrorInvalidValue;
+}
+bool chain_pass_ok(int C, int boundary) {
+    static const int pipe = env_int("DISK_SV_PIPE", 1);
+    return pipe && C >= 3 && C <= 4 && boundary == DISK_CLAMP;
+}
+hipError_t launch_chain_pass(int C, int src_bf16, const void* src, int dst_bf16, void* dst, const float* theta,
+                             int tap0, int N, int T, int H, int W, hipStream_t s) {
+    if (C == 3) return chain_io<3>(src_bf16, src, dst_bf16, dst, theta, tap0, N, T, H, W, s);
+    if (C == 4) return chain_io<4>(src_bf16, src, dst_bf16, dst, theta, tap0, N, T, H, W, s);
+    return hipErrorInvalidValue;
 }
 
 bool sv_pass_raw_ok(int C, int dims, int halo, int G0, int N) {

@@ -75,6 +75,18 @@ hipError_t launch_sv_pass(int C, int dims, int src_bf16, const void* src, int ds
                           const float* pmap, const float* table, int tap0, int N, int T, int G0,
                           int G1, int H, int W, int halo, const int* flag, const float* raw, hipStream_t s);
 bool sv_pass_raw_ok(int C, int dims, int halo, int G0, int N);
+// One uniform-chain layer on a C = 3 or 4 image with the CLAMP boundary through
+// the staged pass kernel (halo derived on the device from the layer's taps).
+bool chain_pass_ok(int C, int boundary);
+// Input adjoint of one uniform layer (C = 3, 4) through the staged kernel:
+// the zero-padded gather at negated offsets, exact except on CLAMP border
+// pixels, which launch_adjoint_input_border then recomputes.
+hipError_t launch_chain_transpose(int C, const float* G, float* Gprev, const float* theta, int tap0, int N, int T,
+                                  int H, int W, hipStream_t s);
+hipError_t launch_adjoint_input_border(int C, const float* G, const TapU* taps, int N, int H, int W, float* Gprev,
+                                       hipStream_t s);
+hipError_t launch_chain_pass(int C, int src_bf16, const void* src, int dst_bf16, void* dst, const float* theta,
+                             int tap0, int N, int T, int H, int W, hipStream_t s);
 
 // ---- optimize.hip: batched optimiser and radial init --------------------------
 int opt_workgroups(int B);

@@ -92,6 +92,31 @@ def test_image_backward_parity(dev, boundary, C, H, W):
     assert et <= 1e-4 and ei <= TOL_F32
 
 
+@pytest.mark.parametrize("boundary,C,H,W,radius", [
+    (S.ZERO, 3, 41, 77, 4.0),       # staged transposed gather, exact everywhere
+    (S.CLAMP, 4, 37, 130, 5.0),     # staged, then the border pixels recomputed
+    (S.CLAMP, 3, 1, 70, 3.0),       # every pixel on the border
+    (S.CLAMP, 3, 2, 33, 3.0),
+    (S.CLAMP, 3, 60, 90, 30.0),     # offsets past the staged halo: direct reads
+    (S.ZERO, 3, 50, 64, 30.0),
+])
+def test_image_backward_staged_input_adjoint(dev, boundary, C, H, W, radius):
+    """C >= 3 images take the input adjoint through the staged kernel (the
+    gather at negated offsets on a zero-padded tile) plus, for CLAMP, an exact
+    recomputation of the border pixels; against the oracle's adjoint."""
+    taps = [6, 4, 5]
+    th = random_theta(taps, radius, seed=H + W)
+    img = uniform_image(H, W, C, seed=W)
+    G = np.random.default_rng(H * W + C).standard_normal((C, H, W)).astype(np.float32)
+    say("image backward staged", boundary, C, H, W, radius)
+    out, saved = disk.disk_forward(to_dev(th), taps, to_dev(img), boundary=boundary, save=True)
+    gt, gi = disk.disk_backward(to_dev(th), taps, to_dev(img), saved, to_dev(G), boundary=boundary)
+    wt, wi = A.chain_vjp(img.astype(np.float64), th.astype(np.float64), taps, boundary, G.astype(np.float64))
+    et, ei = rel_err(to_np(gt), wt), rel_err(to_np(gi), wi)
+    print(f"staged backward b={boundary} C={C} {H}x{W} r={radius}: dtheta {et:.2e} dinput {ei:.2e}")
+    assert et <= 1e-4 and ei <= TOL_F32
+
+
 @pytest.mark.parametrize("M,taps", [(31, [8, 8, 8]), (63, [12, 12, 12, 12]), (101, [7, 9, 5, 11, 6])])
 def test_impulse_backward_parity(dev, M, taps):
     th = random_theta(taps, M / 6.0, seed=M)
@@ -103,6 +128,29 @@ def test_impulse_backward_parity(dev, M, taps):
     e = rel_err(to_np(gt), wt)
     print(f"impulse backward M={M}: {e:.2e}")
     assert e <= 1e-4
+
+
+@pytest.mark.parametrize("C,io", [(3, torch.float32), (4, torch.float32), (3, torch.bfloat16)])
+def test_image_forward_large_offsets(dev, C, io):
+    """C >= 3 CLAMP images run through the staged pass kernel, which derives
+    each layer's halo from its taps on the device: a layer whose offsets go
+    past the staged tile (here 27.5 px) takes the direct-read path, its
+    neighbours the staged one; both against the oracle."""
+    taps = [6, 5, 7]
+    th = random_theta(taps, 4.0, seed=31).astype(np.float32)
+    th[6] = [27.5, -3.25, 0.2]          # layer 2, first tap
+    th[13] = [-11.75, 24.0, 0.1]        # layer 3: halo 25
+    H, W = 90, 150
+    img = noise_image(H, W, C, seed=3, n_rects=6)
+    say("image forward large offsets", C, io)
+    x = to_dev(img).to(io)
+    out, saved = disk.disk_forward(to_dev(th), taps, x, boundary=S.CLAMP, save=True)
+    src = bf16_round(img) if io == torch.bfloat16 else img.astype(np.float64)
+    Xs = S.chain(src, th.astype(np.float64), taps, S.CLAMP, keep=True)
+    tol = TOL_BF16 if io == torch.bfloat16 else TOL_F32
+    assert rel_err(to_np(out), Xs[-1]) <= tol
+    for l in range(len(taps) - 1):
+        assert rel_err(to_np(saved[l]), Xs[l + 1]) <= TOL_F32
 
 
 def test_image_chain_1080p_bench_configuration(dev):
