@@ -258,14 +258,19 @@ __global__ __launch_bounds__(256) void adjoint_input_kernel(const float* __restr
 }
 
 // The CLAMP border pixels only (rows 0 and H-1, columns 0 and W-1): run after
-// the interior was produced by the zero-padded transposed gather.
+// the interior was produced by the zero-padded transposed gather.  One wave per
+// border pixel: lane l takes the (tap, corner) pairs l, l + 64, ... and sums
+// their preimage runs; a fixed butterfly adds the lanes.
+__device__ __forceinline__ long border_count(int H, int W) {
+    return (H <= 2 || W <= 2) ? static_cast<long>(H) * W : 2L * W + 2L * (H - 2);
+}
 template <int C>
 __global__ __launch_bounds__(256) void adjoint_input_border_kernel(const float* __restrict__ G,
                                                                    const TapU* __restrict__ taps, int N, int H,
                                                                    int W, float* __restrict__ Gprev) {
-    const long nb = (H <= 2 || W <= 2) ? static_cast<long>(H) * W : 2L * W + 2L * (H - 2);
-    const long i = static_cast<long>(blockIdx.x) * 256 + threadIdx.x;
-    if (i >= nb) return;
+    const long i = (static_cast<long>(blockIdx.x) * 256 + threadIdx.x) >> 6;   // wave-uniform
+    const int lane = threadIdx.x & 63;
+    if (i >= border_count(H, W)) return;
     int x, y;
     if (H <= 2 || W <= 2) {
         y = static_cast<int>(i / W);
@@ -280,15 +285,33 @@ __global__ __launch_bounds__(256) void adjoint_input_border_kernel(const float* 
     }
     const size_t plane = static_cast<size_t>(H) * W;
     float acc[C];
-    input_adjoint_pixel<C, DISK_CLAMP>(G, taps, N, H, W, x, y, acc);
 #pragma unroll
-    for (int c = 0; c < C; ++c) Gprev[c * plane + static_cast<size_t>(y) * W + x] = acc[c];
+    for (int c = 0; c < C; ++c) acc[c] = 0.0f;
+    for (int pr = lane; pr < 4 * N; pr += 64) {
+        const TapU t = taps[pr >> 2];
+        const int a = pr & 3;
+        const float cw = a == 0 ? t.c00 : a == 1 ? t.c01 : a == 2 ? t.c10 : t.c11;
+        int xl, xh, yl, yh;
+        preimage<DISK_CLAMP>(x, t.ix + (a & 1), W, xl, xh);
+        preimage<DISK_CLAMP>(y, t.iy + (a >> 1), H, yl, yh);
+        for (int py = yl; py <= yh; ++py)
+            for (int px = xl; px <= xh; ++px) {
+                const size_t pi = static_cast<size_t>(py) * W + px;
+#pragma unroll
+                for (int c = 0; c < C; ++c) acc[c] = fmaf(cw, G[c * plane + pi], acc[c]);
+            }
+    }
+#pragma unroll
+    for (int c = 0; c < C; ++c) acc[c] = wave_sum(acc[c]);
+    if (lane == 0)
+#pragma unroll
+        for (int c = 0; c < C; ++c) Gprev[c * plane + static_cast<size_t>(y) * W + x] = acc[c];
 }
 
 hipError_t launch_adjoint_input_border(int C, const float* G, const TapU* taps, int N, int H, int W, float* Gprev,
                                        hipStream_t s) {
     const long nb = (H <= 2 || W <= 2) ? static_cast<long>(H) * W : 2L * W + 2L * (H - 2);
-    const dim3 grid(static_cast<unsigned>((nb + 255) / 256)), block(256);
+    const dim3 grid(static_cast<unsigned>((nb + 3) / 4)), block(256);   // one wave per border pixel
     if (C == 3)
         hipLaunchKernelGGL((adjoint_input_border_kernel<3>), grid, block, 0, s, G, taps, N, H, W, Gprev);
     else if (C == 4)

@@ -682,7 +682,9 @@ __device__ void chain_tiles_global(const TIn* __restrict__ X, TOut* __restrict__
 // ROWB > 0 (C >= 3): the staged row stride in bytes, fixed at compile time
 // (rowW is then ROWB / 4).  TL (1-D bases): the layer's coefficient rows are
 // staged in LDS after the tile, at byte offset SY * rowB.
-template <int C, int DIMS, typename TIn, typename TOut, int NW, int HMAX, int ROWB, bool TL>
+// MODE 0: a spatially varying pass.  MODE 1 (TL, raw = Theta, G0 = 1, P ==
+// nullptr): one layer of a uniform chain.  MODE 2: that layer's transpose.
+template <int C, int DIMS, typename TIn, typename TOut, int NW, int HMAX, int ROWB, bool TL, int MODE = 0>
 __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4, 4))) void sv_pass_pipe_kernel(
     const TIn* __restrict__ X, TOut* __restrict__ Y, const float* __restrict__ P,
     const float* __restrict__ table, int tap0, int N, int T, int G0, int G1, int H, int W, int halo,
@@ -700,13 +702,13 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4, 4)))
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int lx = ((wave & 3) << 4) + (lane & 15), lyb = (wave >> 2) * 4 * PY + (lane >> 4);
 
-    // halo < 0 (TL, raw = Theta, G0 = 1, P == nullptr): a uniform chain layer;
-    // halo == -2: its transpose (offsets negated, the tile staged with zeros
-    // outside the image: the input adjoint away from CLAMP-border pixels).
-    // The halo comes from the layer's own taps (every wave reads the N <= 32
-    // taps): ceil(max |offset|) + 1; beyond HMAX the tiles take the global path.
-    const bool chain = halo < 0, trans = halo == -2;
-    if (TL && chain) {
+    // Chain layers (MODE 1, 2): no parameter map (every pixel at k = 0, t = 0);
+    // the transpose (MODE 2) negates the offsets and stages the tile with zeros
+    // outside the image (the input adjoint away from CLAMP-border pixels).  The
+    // halo comes from the layer's own taps (every wave reads the N <= 32 taps):
+    // ceil(max |offset|) + 1; beyond HMAX the tiles take the global path.
+    constexpr bool chain = MODE != 0, trans = MODE == 2;
+    if constexpr (TL && chain) {
         float m = 0.0f;
         if (lane < N) {
             const float* r = raw + static_cast<size_t>(tap0 + lane) * 3;
@@ -754,7 +756,10 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4, 4)))
                         D[j] = (k + 1 < G0) ? B[j] - A[j] : 0.0f;
                         D2[j] = (k + 2 < G0) ? Cn[j] - B[j] : 0.0f;
                     }
-                    q0 = trans ? v4f{A[0], D[0], A[1], D[1]} : v4f{-A[0], -D[0], -A[1], -D[1]};
+                    if constexpr (trans)
+                        q0 = v4f{A[0], D[0], A[1], D[1]};
+                    else
+                        q0 = v4f{-A[0], -D[0], -A[1], -D[1]};
                     q1 = v4f{A[2], D[2], 0.0f, 0.0f};
                     q2 = v4f{-(D2[0] - D[0]), -(D2[1] - D[1]), D2[2] - D[2], 0.0f};
                     if (!chain && (!(fabsf(A[0]) <= lim && fabsf(A[1]) <= lim) || !isfinite(A[2]))) mine = 1;
@@ -788,7 +793,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4, 4)))
     for (int c = 0; c < C; ++c) Xc[c] = X + c * plane;
     const float* Pd[DIMS];
 #pragma unroll
-    for (int d = 0; d < DIMS; ++d) Pd[d] = P ? P + d * plane : nullptr;
+    for (int d = 0; d < DIMS; ++d) Pd[d] = chain ? nullptr : P + d * plane;
 
     float stg[kPipeRPW][kPipeNQ][C];
     float pv[PY][DIMS];
@@ -800,14 +805,14 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4, 4)))
         for (int q = 0; q < kPipeNQ; ++q) {
             const int cx = tx0 - halo + lane + 64 * q;
             gx[q] = static_cast<uint32_t>(min(max(cx, 0), W - 1));
-            vx[q] = !trans || static_cast<unsigned>(cx) < static_cast<unsigned>(W);
+            vx[q] = trans ? static_cast<unsigned>(cx) < static_cast<unsigned>(W) : true;
         }
 #pragma unroll
         for (int rr = 0; rr < kPipeRPW; ++rr) {
             if (rr < nr) {
                 const int ry = ty0 - halo + wv + NW * rr;
                 const uint32_t grow = static_cast<uint32_t>(min(max(ry, 0), H - 1)) * static_cast<uint32_t>(W);
-                const bool vy = !trans || static_cast<unsigned>(ry) < static_cast<unsigned>(H);
+                const bool vy = trans ? static_cast<unsigned>(ry) < static_cast<unsigned>(H) : true;
 #pragma unroll
                 for (int q = 0; q < kPipeNQ; ++q) {
                     if (q < nq) {
@@ -815,7 +820,10 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4, 4)))
 #pragma unroll
                         for (int c = 0; c < C; ++c) {
                             const float v = IO<TIn>::load(byte_at(Xc[c], off), 0);
-                            stg[rr][q][c] = (vy && vx[q]) ? v : 0.0f;
+                            if constexpr (trans)
+                                stg[rr][q][c] = (vy && vx[q]) ? v : 0.0f;
+                            else
+                                stg[rr][q][c] = v;
                         }
                     }
                 }
@@ -826,7 +834,12 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4, 4)))
         for (int j = 0; j < PY; ++j) {
             const uint32_t pi = (static_cast<uint32_t>(min(ty0 + 4 * j + lyb, H - 1)) * static_cast<uint32_t>(W) + xc) * 4u;
 #pragma unroll
-            for (int d = 0; d < DIMS; ++d) pv[j][d] = P ? *byte_at(Pd[d], pi) : 0.0f;
+            for (int d = 0; d < DIMS; ++d) {
+                if constexpr (chain)
+                    pv[j][d] = 0.0f;
+                else
+                    pv[j][d] = *byte_at(Pd[d], pi);
+            }
         }
     };
 
@@ -1004,7 +1017,7 @@ static size_t pipe_lds_bytes(int halo, int G0, int N) {
     return rowB * (TH + 2 * halo) + (TL ? sv_ltab_bytes(G0, N) : 0);
 }
 
-template <int C, int DIMS, typename TIn, typename TOut, int NW, int HMAX, int ROWB, bool TL>
+template <int C, int DIMS, typename TIn, typename TOut, int NW, int HMAX, int ROWB, bool TL, int MODE = 0>
 static hipError_t launch_pipe(const void* src, void* dst, const float* pmap, const float* table, int tap0, int N,
                               int T, int G0, int G1, int H, int W, int halo, const int* flag, const float* raw,
                               hipStream_t s) {
@@ -1012,10 +1025,10 @@ static hipError_t launch_pipe(const void* src, void* dst, const float* pmap, con
     const int tiles_x = (W + kTW - 1) / kTW, tiles_y = (H + TH - 1) / TH;
     const int ntiles = tiles_x * tiles_y;
     const int per = (ntiles + 7) / 8;
-    const int hs = halo < 0 ? HMAX : halo;   // chain layers (halo < 0) size the tile for HMAX
+    const int hs = MODE != 0 ? HMAX : halo;   // chain layers size the tile for HMAX
     const size_t lds = pipe_lds_bytes<C, DIMS, TIn, TOut, NW, HMAX, ROWB, TL>(hs, G0, N);
     const int rowW = ROWB > 0 ? ROWB / 4 : sv_row_dwords(hs, C);
-    auto fn = sv_pass_pipe_kernel<C, DIMS, TIn, TOut, NW, HMAX, ROWB, TL>;
+    auto fn = sv_pass_pipe_kernel<C, DIMS, TIn, TOut, NW, HMAX, ROWB, TL, MODE>;
     // Host queries once per kernel and LDS size (launches of a frame repeat them)
     static std::mutex mu;
     static size_t attr_lds = 0, occ_lds = 0;
@@ -1136,8 +1149,8 @@ static hipError_t launch_dims(int dims, int src_bf16, const void* src, int dst_b
 template <int C, typename TIn, typename TOut>
 static hipError_t chain_typed(const void* src, void* dst, const float* theta, int tap0, int N, int T, int H, int W,
                               hipStream_t s) {
-    return launch_pipe<C, 1, TIn, TOut, 16, kPipeHalo, kPipeRowB, true>(src, dst, nullptr, nullptr, tap0, N, T, 1, 1,
-                                                                        H, W, -1, nullptr, theta, s);
+    return launch_pipe<C, 1, TIn, TOut, 16, kPipeHalo, kPipeRowB, true, 1>(src, dst, nullptr, nullptr, tap0, N, T, 1,
+                                                                           1, H, W, 0, nullptr, theta, s);
 }
 template <int C>
 static hipError_t chain_io(int src_bf16, const void* src, int dst_bf16, void* dst, const float* theta, int tap0,
@@ -1150,8 +1163,8 @@ static hipError_t chain_io(int src_bf16, const void* src, int dst_bf16, void* ds
 template <int C>
 static hipError_t chain_trans_c(const float* G, float* Gprev, const float* theta, int tap0, int N, int T, int H, int W,
                                 hipStream_t s) {
-    return launch_pipe<C, 1, float, float, 16, kPipeHalo, kPipeRowB, true>(G, Gprev, nullptr, nullptr, tap0, N, T, 1, 1,
-                                                                          H, W, -2, nullptr, theta, s);
+    return launch_pipe<C, 1, float, float, 16, kPipeHalo, kPipeRowB, true, 2>(G, Gprev, nullptr, nullptr, tap0, N, T, 1,
+                                                                             1, H, W, 0, nullptr, theta, s);
 }
 hipError_t launch_chain_transpose(int C, const float* G, float* Gprev, const float* theta, int tap0, int N, int T,
                                   int H, int W, hipStream_t s) {
