@@ -257,10 +257,17 @@ disk_status disk_backward(const disk_complex* cx, const float* theta, const floa
         const void* X = l == 0 ? static_cast<const void*>(in) : static_cast<const void*>(saved + (l - 1) * n);
         const int src_kind = (l == 0 && impulse) ? 2 : 0;
         if (grad_theta) {
-            DISK_HIP(launch_adjoint_taps(C, boundary, src_kind, X, G, tapu + sp.tap0[l], sp.taps[l], H, W, partial,
-                                         stream),
-                     "adjoint taps");
-            DISK_HIP(launch_adjoint_finish(partial, nblk, theta + 3 * sp.tap0[l], sp.taps[l],
+            int nb = nblk;
+            if (!impulse && chain_pass_ok(C, DISK_CLAMP)) {
+                DISK_HIP(launch_adjoint_corr(C, boundary, static_cast<const float*>(X), G, theta, sp.tap0[l], sp.taps[l],
+                                             sp.T, H, W, partial, &nb, stream),
+                         "adjoint taps");
+            } else {
+                DISK_HIP(launch_adjoint_taps(C, boundary, src_kind, X, G, tapu + sp.tap0[l], sp.taps[l], H, W, partial,
+                                             stream),
+                         "adjoint taps");
+            }
+            DISK_HIP(launch_adjoint_finish(partial, nb, theta + 3 * sp.tap0[l], sp.taps[l],
                                            grad_theta + 3 * sp.tap0[l], stream),
                      "adjoint finish");
         }

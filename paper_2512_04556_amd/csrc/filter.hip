@@ -631,7 +631,7 @@ struct PipeShape {
 // source planes, in the staged path's arithmetic and order.
 // tr: the transposed layer (offsets negated, reads outside the image are 0).
 template <int C, typename TIn, typename TOut, int PY, int TH>
-__device__ void chain_tiles_global(const TIn* __restrict__ X, TOut* __restrict__ Y, const float* __restrict__ raw,
+__device__ __forceinline__ void chain_tiles_global(const TIn* __restrict__ X, TOut* __restrict__ Y, const float* __restrict__ raw,
                                    int tap0, int N, int H, int W, int tile, int tend, int nwg, int tiles_x, int lx,
                                    int lyb, bool tr) {
     const size_t plane = static_cast<size_t>(H) * W;
@@ -679,6 +679,104 @@ __device__ void chain_tiles_global(const TIn* __restrict__ X, TOut* __restrict__
     }
 }
 
+// Tap correlations S_ab = sum_p sum_c G[c][p] X[c][map(p + d_ab)] of a chunk
+// of <= kCorrTaps uniform taps (the tap gradients of a chain layer), for the
+// PY pixels of a lane, added to s.  ZR: reads outside the image are 0, else
+// clamped.  Direct global reads: the path for offsets beyond the staged halo.
+constexpr int kCorrTaps = 8;
+template <int C, typename TIn, int PY, int TH, bool ZR>
+__device__ __forceinline__ void corr_tiles_global(const TIn* __restrict__ X, const float* __restrict__ G,
+                                  const float* __restrict__ raw, int tap0, int N, int H, int W, int tile, int tend,
+                                  int nwg, int tiles_x, int lx, int lyb, float (&s)[kCorrTaps][4]) {
+    const size_t plane = static_cast<size_t>(H) * W;
+    for (; tile < tend; tile += nwg) {
+        const int x = (tile % tiles_x) * kTW + lx, y0 = (tile / tiles_x) * TH + lyb;
+        float g[PY][C];
+#pragma unroll
+        for (int j = 0; j < PY; ++j) {
+            const int y = y0 + 4 * j;
+            const bool in = x < W && y < H;
+#pragma unroll
+            for (int c = 0; c < C; ++c) g[j][c] = in ? G[c * plane + static_cast<size_t>(y) * W + x] : 0.0f;
+        }
+#pragma unroll
+        for (int i = 0; i < kCorrTaps; ++i) {
+            if (i < N) {
+                const float* r = raw + static_cast<size_t>(tap0 + i) * 3;
+                const float flx = floorf(-r[0]), fly = floorf(-r[1]);
+                const int dx = static_cast<int>(fminf(fmaxf(flx, -1048576.0f), 1048576.0f));
+                const int dy = static_cast<int>(fminf(fmaxf(fly, -1048576.0f), 1048576.0f));
+#pragma unroll
+                for (int j = 0; j < PY; ++j) {
+                    const int y = y0 + 4 * j;
+#pragma unroll
+                    for (int ab = 0; ab < 4; ++ab) {
+                        const int cx = x + dx + (ab & 1), cy = y + dy + (ab >> 1);
+                        const bool ok = !ZR || (cx >= 0 && cx < W && cy >= 0 && cy < H);
+                        const size_t o = static_cast<size_t>(min(max(cy, 0), H - 1)) * W + min(max(cx, 0), W - 1);
+                        float v = s[i][ab];
+#pragma unroll
+                        for (int c = 0; c < C; ++c) v = fmaf(g[j][c], ok ? IO<TIn>::load(X, c * plane + o) : 0.0f, v);
+                        s[i][ab] = v;
+                    }
+                }
+            }
+        }
+    }
+}
+
+// Work-group sum of s (wave butterflies, then waves in order) into
+// part[(blockIdx.x * pN + pofs + i) * 4 + ab]; red: >= NW * kCorrTaps * 4 floats of LDS.
+template <int NW>
+__device__ __forceinline__ void corr_block_reduce(float (&s)[kCorrTaps][4], int N, float* red, float* __restrict__ part, int pN,
+                                  int pofs) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+    for (int i = 0; i < kCorrTaps; ++i)
+#pragma unroll
+        for (int ab = 0; ab < 4; ++ab) {
+            const float v = wave_sum(s[i][ab]);
+            if (lane == 0) red[(wave * kCorrTaps + i) * 4 + ab] = v;
+        }
+    __syncthreads();
+    if (threadIdx.x < 4 * N) {
+        const int i = threadIdx.x >> 2, ab = threadIdx.x & 3;
+        float v = 0.0f;
+        for (int w = 0; w < NW; ++w) v += red[(w * kCorrTaps + i) * 4 + ab];
+        part[(static_cast<size_t>(blockIdx.x) * pN + pofs + i) * 4 + ab] = v;
+    }
+}
+
+// Staged tap correlations of one tile: the chunk's taps (LDS rows, t = 0:
+// -o = (nAx, nAy)) read their four corners from the tile for the lane's PY
+// pixels, weighted by the pixel's gradient over the channels.
+template <int C, int PY, int ROWB>
+__device__ __forceinline__ void corr_tile_taps(float (&s)[kCorrTaps][4], const float (&g)[PY][C], int base0, int tabL,
+                                               int N) {
+    float basef[PY];
+#pragma unroll
+    for (int j = 0; j < PY; ++j) basef[j] = static_cast<float>(base0 + j * 4 * ROWB);
+#pragma unroll
+    for (int i = 0; i < kCorrTaps; ++i) {
+        if (i < N) {
+            const v4f a = lds_ld4(tabL + i * kRowLB);
+            const float flx = floorf(a.x), fly = floorf(a.z);
+#pragma unroll
+            for (int j = 0; j < PY; ++j) {
+                const int a0 = static_cast<int>(fmaf(flx, 16.0f, fmaf(fly, static_cast<float>(ROWB), basef[j])));
+                const v4f v[4] = {lds_ld4(a0), lds_ld4(a0 + 16), lds_ld4(a0 + ROWB), lds_ld4(a0 + ROWB + 16)};
+#pragma unroll
+                for (int ab = 0; ab < 4; ++ab) {
+                    float t = s[i][ab];
+#pragma unroll
+                    for (int c = 0; c < C; ++c) t = fmaf(g[j][c], v[ab][c], t);
+                    s[i][ab] = t;
+                }
+            }
+        }
+    }
+}
+
 // ROWB > 0 (C >= 3): the staged row stride in bytes, fixed at compile time
 // (rowW is then ROWB / 4).  TL (1-D bases): the layer's coefficient rows are
 // staged in LDS after the tile, at byte offset SY * rowB.
@@ -688,7 +786,8 @@ template <int C, int DIMS, typename TIn, typename TOut, int NW, int HMAX, int RO
 __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4, 4))) void sv_pass_pipe_kernel(
     const TIn* __restrict__ X, TOut* __restrict__ Y, const float* __restrict__ P,
     const float* __restrict__ table, int tap0, int N, int T, int G0, int G1, int H, int W, int halo,
-    int tiles_x, int per, int ntiles, const int* __restrict__ flag, int rowW, const float* __restrict__ raw) {
+    int tiles_x, int per, int ntiles, const int* __restrict__ flag, int rowW, const float* __restrict__ raw,
+    int pN, int pofs) {
     extern __shared__ float lds[];
     if (ROWB > 0) rowW = ROWB / 4;
     constexpr int PY = kPipePY;
@@ -697,7 +796,28 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4, 4)))
     const int xcd = blockIdx.x & 7, nwg = gridDim.x >> 3;
     const int tend = min((xcd + 1) * per, ntiles);
     int tile = xcd * per + (blockIdx.x >> 3);
-    if (tile >= tend) return;
+    // MODE 3, 4: tap correlations of a chain layer (CLAMP / ZERO): X = the
+    // layer input, P = G (its output gradient), Y = the partial sums
+    // [grid][pN][4]; taps tap0 .. tap0 + N - 1 (N <= kCorrTaps) are entries
+    // pofs .. pofs + N - 1 of the layer.
+    constexpr bool corr = MODE >= 3;
+    float s[kCorrTaps][4];
+    if constexpr (corr) {
+#pragma unroll
+        for (int i = 0; i < kCorrTaps; ++i)
+#pragma unroll
+            for (int ab = 0; ab < 4; ++ab) s[i][ab] = 0.0f;
+    }
+    auto corr_finish = [&]() {
+        if constexpr (corr) {
+            __syncthreads();   // the LDS is free again
+            corr_block_reduce<NW>(s, N, lds, reinterpret_cast<float*>(Y), pN, pofs);
+        }
+    };
+    if (tile >= tend) {
+        corr_finish();
+        return;
+    }
     const size_t plane = static_cast<size_t>(H) * W;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int lx = ((wave & 3) << 4) + (lane & 15), lyb = (wave >> 2) * 4 * PY + (lane >> 4);
@@ -707,7 +827,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4, 4)))
     // outside the image (the input adjoint away from CLAMP-border pixels).  The
     // halo comes from the layer's own taps (every wave reads the N <= 32 taps):
     // ceil(max |offset|) + 1; beyond HMAX the tiles take the global path.
-    constexpr bool chain = MODE != 0, trans = MODE == 2;
+    constexpr bool chain = MODE != 0, trans = MODE == 2, zstage = MODE == 2 || MODE == 4;
     if constexpr (TL && chain) {
         float m = 0.0f;
         if (lane < N) {
@@ -717,8 +837,14 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4, 4)))
         }
         halo = uniform(static_cast<int>(ceilf(wave_max(m))) + 1);
         if (halo > HMAX) {
-            chain_tiles_global<C, TIn, TOut, PY, TH>(X, Y, raw, tap0, N, H, W, tile, tend, nwg, tiles_x, lx, lyb,
-                                                     trans);
+            if constexpr (corr) {
+                corr_tiles_global<C, TIn, PY, TH, zstage>(X, P, raw, tap0, N, H, W, tile, tend, nwg, tiles_x, lx, lyb,
+                                                          s);
+                corr_finish();
+            } else {
+                chain_tiles_global<C, TIn, TOut, PY, TH>(X, Y, raw, tap0, N, H, W, tile, tend, nwg, tiles_x, lx,
+                                                         lyb, trans);
+            }
             return;
         }
     }
@@ -797,6 +923,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4, 4)))
 
     float stg[kPipeRPW][kPipeNQ][C];
     float pv[PY][DIMS];
+    float gv[PY][C];   // corr: the tile's output gradient at the lane's pixels
     auto issue = [&](int t) {
         const int tx0 = (t % tiles_x) * kTW, ty0 = (t / tiles_x) * TH;
         uint32_t gx[kPipeNQ];
@@ -805,14 +932,14 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4, 4)))
         for (int q = 0; q < kPipeNQ; ++q) {
             const int cx = tx0 - halo + lane + 64 * q;
             gx[q] = static_cast<uint32_t>(min(max(cx, 0), W - 1));
-            vx[q] = trans ? static_cast<unsigned>(cx) < static_cast<unsigned>(W) : true;
+            vx[q] = zstage ? static_cast<unsigned>(cx) < static_cast<unsigned>(W) : true;
         }
 #pragma unroll
         for (int rr = 0; rr < kPipeRPW; ++rr) {
             if (rr < nr) {
                 const int ry = ty0 - halo + wv + NW * rr;
                 const uint32_t grow = static_cast<uint32_t>(min(max(ry, 0), H - 1)) * static_cast<uint32_t>(W);
-                const bool vy = trans ? static_cast<unsigned>(ry) < static_cast<unsigned>(H) : true;
+                const bool vy = zstage ? static_cast<unsigned>(ry) < static_cast<unsigned>(H) : true;
 #pragma unroll
                 for (int q = 0; q < kPipeNQ; ++q) {
                     if (q < nq) {
@@ -820,7 +947,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4, 4)))
 #pragma unroll
                         for (int c = 0; c < C; ++c) {
                             const float v = IO<TIn>::load(byte_at(Xc[c], off), 0);
-                            if constexpr (trans)
+                            if constexpr (zstage)
                                 stg[rr][q][c] = (vy && vx[q]) ? v : 0.0f;
                             else
                                 stg[rr][q][c] = v;
@@ -830,6 +957,19 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4, 4)))
             }
         }
         const uint32_t xc = static_cast<uint32_t>(min(tx0 + lx, W - 1));
+        if constexpr (corr) {
+#pragma unroll
+            for (int j = 0; j < PY; ++j) {
+                const int y = ty0 + 4 * j + lyb;
+                const bool in = tx0 + lx < W && y < H;
+                const uint32_t pi = (static_cast<uint32_t>(min(y, H - 1)) * static_cast<uint32_t>(W) + xc) * 4u;
+#pragma unroll
+                for (int c = 0; c < C; ++c) {
+                    const float v = *byte_at(P + c * plane, pi);
+                    gv[j][c] = in ? v : 0.0f;
+                }
+            }
+        }
 #pragma unroll
         for (int j = 0; j < PY; ++j) {
             const uint32_t pi = (static_cast<uint32_t>(min(ty0 + 4 * j + lyb, H - 1)) * static_cast<uint32_t>(W) + xc) * 4u;
@@ -866,14 +1006,28 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4, 4)))
         __syncthreads();
         const int x = (tile % tiles_x) * kTW + lx, y0 = (tile / tiles_x) * TH + lyb;
         const int next = tile + nwg;
-        if (next < tend) issue(next);
-        float acc[PY][C];
-        sv_tile_taps<C, DIMS, PY, ROWB, TL>(acc, ta, tb, kk, base0, rowB, table, tap0, N, T, tabL);
-        sv_store<C, TOut, PY>(Y, plane, W, H, x, y0, acc);
+        if constexpr (corr) {
+            float gc[PY][C];
+#pragma unroll
+            for (int j = 0; j < PY; ++j)
+#pragma unroll
+                for (int c = 0; c < C; ++c) {
+                    gc[j][c] = gv[j][c];
+                    asm volatile("" ::"v"(gc[j][c]));   // this tile's G ahead of the prefetch
+                }
+            if (next < tend) issue(next);
+            corr_tile_taps<C, PY, ROWB>(s, gc, base0, tabL, N);
+        } else {
+            if (next < tend) issue(next);
+            float acc[PY][C];
+            sv_tile_taps<C, DIMS, PY, ROWB, TL>(acc, ta, tb, kk, base0, rowB, table, tap0, N, T, tabL);
+            sv_store<C, TOut, PY>(Y, plane, W, H, x, y0, acc);
+        }
         if (next >= tend) break;
         tile = next;
         __syncthreads();  // every wave is done reading this tile before the next is written
     }
+    corr_finish();
 }
 
 // Fallback for halos whose staged tile does not fit in LDS: one pixel per
@@ -1020,7 +1174,7 @@ static size_t pipe_lds_bytes(int halo, int G0, int N) {
 template <int C, int DIMS, typename TIn, typename TOut, int NW, int HMAX, int ROWB, bool TL, int MODE = 0>
 static hipError_t launch_pipe(const void* src, void* dst, const float* pmap, const float* table, int tap0, int N,
                               int T, int G0, int G1, int H, int W, int halo, const int* flag, const float* raw,
-                              hipStream_t s) {
+                              hipStream_t s, int pN = 0, int pofs = 0, int* grid_out = nullptr) {
     constexpr int TH = PipeShape<NW, HMAX>::TH;
     const int tiles_x = (W + kTW - 1) / kTW, tiles_y = (H + TH - 1) / TH;
     const int ntiles = tiles_x * tiles_y;
@@ -1057,7 +1211,8 @@ static hipError_t launch_pipe(const void* src, void* dst, const float* pmap, con
     per_xcd = std::max(1, std::min(per_xcd, per));
     hipLaunchKernelGGL(fn, dim3(8 * per_xcd), dim3(64 * NW), lds, s, static_cast<const TIn*>(src),
                        static_cast<TOut*>(dst), pmap, table, tap0, N, T, G0, G1, H, W, halo, tiles_x, per, ntiles,
-                       flag, rowW, raw);
+                       flag, rowW, raw, pN, pofs);
+    if (grid_out) *grid_out = 8 * per_xcd;
     return hipGetLastError();
 }
 
@@ -1172,6 +1327,33 @@ hipError_t launch_chain_transpose(int C, const float* G, float* Gprev, const flo
     if (C == 4) return chain_trans_c<4>(G, Gprev, theta, tap0, N, T, H, W, s);
     return hipErrorInvalidValue;
 }
+// Tap correlations of one chain layer (C = 3, 4) into partial[grid][N][4]
+// (N taps, chunks of kCorrTaps per launch); *nblk = the grid (rows of partial).
+template <int C, typename TIn, int MODE>
+static hipError_t corr_typed(const void* X, const float* G, const float* theta, int tap0, int N, int T, int H, int W,
+                             float* partial, int* nblk, hipStream_t s) {
+    for (int c0 = 0; c0 < N; c0 += kCorrTaps) {
+        const hipError_t e = launch_pipe<C, 1, TIn, float, 16, kPipeHalo, kPipeRowB, true, MODE>(
+            X, partial, G, nullptr, tap0 + c0, std::min(kCorrTaps, N - c0), T, 1, 1, H, W, 0, nullptr, theta, s, N,
+            c0, nblk);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+template <int C>
+static hipError_t corr_c(int zero, const float* X, const float* G, const float* theta, int tap0, int N, int T, int H,
+                         int W, float* partial, int* nblk, hipStream_t s) {
+    if (zero) return corr_typed<C, float, 4>(X, G, theta, tap0, N, T, H, W, partial, nblk, s);
+    return corr_typed<C, float, 3>(X, G, theta, tap0, N, T, H, W, partial, nblk, s);
+}
+hipError_t launch_adjoint_corr(int C, int boundary, const float* X, const float* G, const float* theta, int tap0,
+                               int N, int T, int H, int W, float* partial, int* nblk, hipStream_t s) {
+    const int zero = boundary == DISK_ZERO;
+    if (C == 3) return corr_c<3>(zero, X, G, theta, tap0, N, T, H, W, partial, nblk, s);
+    if (C == 4) return corr_c<4>(zero, X, G, theta, tap0, N, T, H, W, partial, nblk, s);
+    return hipErrorInvalidValue;
+}
+
 bool chain_pass_ok(int C, int boundary) {
     static const int pipe = env_int("DISK_SV_PIPE", 1);
     return pipe && C >= 3 && C <= 4 && boundary == DISK_CLAMP;

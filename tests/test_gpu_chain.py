@@ -117,6 +117,21 @@ def test_image_backward_staged_input_adjoint(dev, boundary, C, H, W, radius):
     assert et <= 1e-4 and ei <= TOL_F32
 
 
+@pytest.mark.parametrize("boundary,taps", [(S.CLAMP, [12, 9, 17]), (S.ZERO, [16, 3])])
+def test_image_backward_many_taps(dev, boundary, taps):
+    """Layers of more than 8 taps: the staged tap correlations run in chunks of
+    8 taps, each chunk's partial sums landing at its taps' rows."""
+    th = random_theta(taps, 5.0, seed=sum(taps))
+    H, W = 57, 140
+    img = uniform_image(H, W, 3, seed=7)
+    G = np.random.default_rng(8).standard_normal((3, H, W)).astype(np.float32)
+    say("image backward many taps", boundary, taps)
+    out, saved = disk.disk_forward(to_dev(th), taps, to_dev(img), boundary=boundary, save=True)
+    gt, gi = disk.disk_backward(to_dev(th), taps, to_dev(img), saved, to_dev(G), boundary=boundary)
+    wt, wi = A.chain_vjp(img.astype(np.float64), th.astype(np.float64), taps, boundary, G.astype(np.float64))
+    assert rel_err(to_np(gt), wt) <= 1e-4 and rel_err(to_np(gi), wi) <= TOL_F32
+
+
 @pytest.mark.parametrize("M,taps", [(31, [8, 8, 8]), (63, [12, 12, 12, 12]), (101, [7, 9, 5, 11, 6])])
 def test_impulse_backward_parity(dev, M, taps):
     th = random_theta(taps, M / 6.0, seed=M)
