@@ -56,7 +56,16 @@ struct TapO {
     int ix, iy;                 // floor(-o)
     float c00, c01, c10, c11;   // w * bilinear corner weights
     float fx, fy;               // fractions of -o
+    int off;                    // iy * S + ix: the corner's canvas offset
+    int inside;                 // tap_inside(P): all four corners within the zero frame
 };
+
+// Canvas element at a 32-bit element index: a scalar base plus one 32-bit
+// vector byte offset per load (no 64-bit address arithmetic per tap).
+__device__ __forceinline__ const float* at(const float* base, int idx) {
+    return reinterpret_cast<const float*>(reinterpret_cast<const char*>(base) +
+                                          static_cast<uint32_t>(idx) * 4u);
+}
 
 __device__ __forceinline__ int opt_pad(int M) { return (M + 1) / 2 + 1; }
 
@@ -121,12 +130,12 @@ template <int SGN>
 __device__ __forceinline__ float gather_tap(float acc, const TapO& t, const float* __restrict__ src, int base, int x,
                                             int y, const Walk& wk) {
     const int M = wk.M, S = wk.S, P = wk.P;
-    if (tap_inside(t, P)) {
-        const float* q = src + base + SGN * (t.iy * S + t.ix);
-        acc = fmaf(t.c00, q[0], acc);
-        acc = fmaf(t.c01, q[SGN], acc);
-        acc = fmaf(t.c10, q[SGN * S], acc);
-        acc = fmaf(t.c11, q[SGN * (S + 1)], acc);
+    if (t.inside) {
+        const int q = base + SGN * t.off;
+        acc = fmaf(t.c00, *at(src, q), acc);
+        acc = fmaf(t.c01, *at(src, q + SGN), acc);
+        acc = fmaf(t.c10, *at(src, q + SGN * S), acc);
+        acc = fmaf(t.c11, *at(src, q + SGN * (S + 1)), acc);
     } else {
         const int xc = min(x, M - 1), yc = min(y, M - 1);
         acc = fmaf(t.c00, masked(src, xc, yc, SGN * t.ix, SGN * t.iy, M, S, P), acc);
@@ -145,7 +154,7 @@ template <int SGN>
 __device__ void gather_layer(const float* __restrict__ src, float* __restrict__ dst, const TapO* tp, int N,
                              const Walk& wk) {
     const int wave = threadIdx.x >> 6;
-    const int S = wk.S, P = wk.P;
+    const int S = wk.S;
     for (int blk = wave; blk < wk.nblk; blk += kOptWaves) {
         int x, y;
         bool act;
@@ -156,15 +165,15 @@ __device__ void gather_layer(const float* __restrict__ src, float* __restrict__ 
             TapO t[4];
 #pragma unroll
             for (int k = 0; k < 4; ++k) t[k] = tp[i + k];
-            if (tap_inside(t[0], P) && tap_inside(t[1], P) && tap_inside(t[2], P) && tap_inside(t[3], P)) {
+            if (t[0].inside & t[1].inside & t[2].inside & t[3].inside) {
                 float v[4][4];
 #pragma unroll
                 for (int k = 0; k < 4; ++k) {
-                    const float* q = src + base + SGN * (t[k].iy * S + t[k].ix);
-                    v[k][0] = q[0];
-                    v[k][1] = q[SGN];
-                    v[k][2] = q[SGN * S];
-                    v[k][3] = q[SGN * (S + 1)];
+                    const int q = base + SGN * uniform(t[k].off);
+                    v[k][0] = *at(src, q);
+                    v[k][1] = *at(src, q + SGN);
+                    v[k][2] = *at(src, q + SGN * S);
+                    v[k][3] = *at(src, q + SGN * (S + 1));
                 }
 #pragma unroll
                 for (int k = 0; k < 4; ++k) {
@@ -263,6 +272,8 @@ __global__ __launch_bounds__(kOptThreads, 4) void opt_kernel(OptArgs a) {
                 t.c00 = wy0 - t.c01;
                 t.c11 = wy1 * t.fx;
                 t.c10 = wy1 - t.c11;
+                t.off = t.iy * S + t.ix;
+                t.inside = tap_inside(t, P) ? 1 : 0;
                 tap[i] = t;
             }
             __syncthreads();
@@ -361,8 +372,8 @@ __global__ __launch_bounds__(kOptThreads, 4) void opt_kernel(OptArgs a) {
                             off[k] = 0;
                             if (k < nc) {
                                 const TapO t = tp[i0 + k];
-                                off[k] = uniform(t.iy * S + t.ix);
-                                all_in = all_in && tap_inside(t, P);
+                                off[k] = uniform(t.off);
+                                all_in = all_in && t.inside;
                             }
                         }
                         if (all_in) {
@@ -376,11 +387,11 @@ __global__ __launch_bounds__(kOptThreads, 4) void opt_kernel(OptArgs a) {
                                     float v[4][4];
 #pragma unroll
                                     for (int k = 0; k < 4; ++k) {
-                                        const float* q = X + base + off[k0 + k];
-                                        v[k][0] = q[0];
-                                        v[k][1] = q[1];
-                                        v[k][2] = q[S];
-                                        v[k][3] = q[S + 1];
+                                        const int q = base + off[k0 + k];
+                                        v[k][0] = *at(X, q);
+                                        v[k][1] = *at(X, q + 1);
+                                        v[k][2] = *at(X, q + S);
+                                        v[k][3] = *at(X, q + S + 1);
                                     }
 #pragma unroll
                                     for (int k = 0; k < 4; ++k)
@@ -400,12 +411,12 @@ __global__ __launch_bounds__(kOptThreads, 4) void opt_kernel(OptArgs a) {
                                 if (k < nc) {
                                     const TapO t = tp[i0 + k];
                                     float v00, v01, v10, v11;
-                                    if (tap_inside(t, P)) {
-                                        const float* q = X + base + t.iy * S + t.ix;
-                                        v00 = q[0];
-                                        v01 = q[1];
-                                        v10 = q[S];
-                                        v11 = q[S + 1];
+                                    if (t.inside) {
+                                        const int q = base + t.off;
+                                        v00 = *at(X, q);
+                                        v01 = *at(X, q + 1);
+                                        v10 = *at(X, q + S);
+                                        v11 = *at(X, q + S + 1);
                                     } else {
                                         const int xc = min(x, M - 1), yc = min(y, M - 1);
                                         v00 = masked(X, xc, yc, t.ix, t.iy, M, S, P);
