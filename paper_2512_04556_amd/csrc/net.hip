@@ -18,6 +18,10 @@ namespace {
 
 constexpr int kConvWidth[6] = {32, 64, 128, 128, 256, 256};
 constexpr int kFc0 = 512, kOut = 144, kSide = 64;
+constexpr bool pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+static_assert(pow2(kSide) && pow2(kConvWidth[0]) && pow2(kConvWidth[1]) && pow2(kConvWidth[2]) &&
+                  pow2(kConvWidth[3]) && pow2(kConvWidth[4]) && pow2(kConvWidth[5]),
+              "the im2col index splits are shifts");
 constexpr int kBM = 64, kBN = 64, kBK = 32;
 constexpr int kLds = 40;   // LDS row stride in BF16 elements (80 B: 16-B aligned, spreads banks)
 
@@ -48,16 +52,19 @@ struct LdCol {   // Op(r, k) = p[k * ld + r]
 
 // im2col of a 3x3 / stride 2 / zero-padding 1 convolution over NHWC x:
 // Op(m, k) with m = (b, oy, ox) and k = (ky * 3 + kx) * Cin + ci.
+// Every extent of this network is a power of two (64 x 64 input, stride 2,
+// widths 32..256): the index splits are shifts (lg*), and tap / 3 for a tap
+// below 9 is (tap * 11) >> 5.
 struct Im2col {
     const uint16_t* x;
     int H, W, Cin, Ho, Wo, M, K;   // K = 9 Cin
+    int lgHW, lgWo, lgCin;         // log2(Ho Wo), log2 Wo, log2 Cin
     __device__ uint4 fetch8(int m, int k) const {
         if (m >= M || k >= K) return zero4();
-        const int hw = Ho * Wo;
-        const int b = m / hw, r = m - b * hw, oy = r / Wo, ox = r - oy * Wo;
+        const int b = m >> lgHW, r = m - (b << lgHW), oy = r >> lgWo, ox = r - (oy << lgWo);
         if (Cin >= 8) {   // 8 channels of one tap
-            const int tap = k / Cin, ci = k - tap * Cin;
-            const int ky = tap / 3, kx = tap - 3 * ky;
+            const int tap = k >> lgCin, ci = k - (tap << lgCin);
+            const int ky = (tap * 11) >> 5, kx = tap - 3 * ky;
             const int iy = 2 * oy + ky - 1, ix = 2 * ox + kx - 1;
             if (iy < 0 || iy >= H || ix < 0 || ix >= W) return zero4();
             return *reinterpret_cast<const uint4*>(x + ((static_cast<size_t>(b) * H + iy) * W + ix) * Cin + ci);
@@ -66,8 +73,8 @@ struct Im2col {
         uint16_t e[8];
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
-            const int tap = k + j;
-            const int ky = tap / 3, kx = tap - 3 * ky;
+            const int tap = k + j;   // used only below 9
+            const int ky = (tap * 11) >> 5, kx = tap - 3 * ky;
             const int iy = 2 * oy + ky - 1, ix = 2 * ox + kx - 1;
             e[j] = (tap < 9 && iy >= 0 && iy < H && ix >= 0 && ix < W)
                        ? x[(static_cast<size_t>(b) * H + iy) * W + ix]
@@ -263,6 +270,17 @@ Table make_table() {
 const Table& table() {
     static const Table T = make_table();
     return T;
+}
+
+static int lg2(int v) {   // v a power of two
+    int l = 0;
+    while ((1 << l) < v) ++l;
+    return l;
+}
+static void set_shifts(Im2col& a, const Layer& L) {
+    a.lgHW = lg2(L.hout * L.hout);
+    a.lgWo = lg2(L.hout);
+    a.lgCin = lg2(L.cin);
 }
 
 // ---- small kernels ----------------------------------------------------------
@@ -585,6 +603,7 @@ hipError_t net_forward(const float* params, const uint16_t* x0, int B, char* ws,
             if (L.conv) {
                 LdIm2col a;
                 a.x = xin; a.H = L.hin; a.W = L.hin; a.Cin = L.cin; a.Ho = L.hout; a.Wo = L.hout; a.M = M; a.K = L.K;
+                set_shifts(a, L);
                 e = gemm(a, wb, ep, M, L.cout, L.Kp, 1, L.Kp, s);
             } else {
                 LdRow a{xin, L.K, M, L.K};
@@ -637,6 +656,7 @@ hipError_t net_backward(const float* params, const uint16_t* x0, const float* re
         if (L.conv) {
             LdIm2colT xb;
             xb.x = xin; xb.H = L.hin; xb.W = L.hin; xb.Cin = L.cin; xb.Ho = L.hout; xb.Wo = L.hout; xb.M = M; xb.K = L.K;
+            set_shifts(xb, L);
             e = gemm(ga, xb, ps, L.cout, L.Kp, M, S, kc, s);
         } else {
             LdCol xb{xin, L.K, L.K, M};
