@@ -116,12 +116,16 @@ __device__ __forceinline__ void tile_store(uint16_t* S, int t, uint4 v) {
 }
 
 // ---- epilogues ------------------------------------------------------------
+// Staged epilogues (kStaged) produce BF16 values that the GEMM gathers in LDS
+// and stores eight at a time (put8: columns n..n+7, N a multiple of 8).
 struct EpAct {   // hidden layer: out = bf16(ReLU(acc + bias))
     uint16_t* out;
     const float* bias;
     int ld;
-    __device__ void put(int m, int n, float acc, int) const {
-        out[static_cast<size_t>(m) * ld + n] = f32_to_bf16(fmaxf(acc + bias[n], 0.0f));
+    static constexpr bool kStaged = true;
+    __device__ uint16_t value(int n, float acc) const { return f32_to_bf16(fmaxf(acc + bias[n], 0.0f)); }
+    __device__ void put8(int m, int n, uint4 v) const {
+        *reinterpret_cast<uint4*>(out + static_cast<size_t>(m) * ld + n) = v;
     }
 };
 struct EpOut {   // last layer: out = acc + bias, offsets times hw[m] when hw is given
@@ -129,6 +133,7 @@ struct EpOut {   // last layer: out = acc + bias, offsets times hw[m] when hw is
     const float* bias;
     const float* hw;
     int ld;
+    static constexpr bool kStaged = false;
     __device__ void put(int m, int n, float acc, int) const {
         float v = acc + bias[n];
         if (hw && (n % 3) < 2) v *= hw[m];
@@ -139,6 +144,7 @@ struct EpStore {  // plain FP32 store; split z writes its own M x N slab
     float* out;
     int ld;
     size_t slab;
+    static constexpr bool kStaged = false;
     __device__ void put(int m, int n, float acc, int z) const {
         out[z * slab + static_cast<size_t>(m) * ld + n] = acc;
     }
@@ -148,6 +154,7 @@ struct EpMaskGrad {  // FC input gradient: g = acc * [x > 0], kept in FP32 and B
     uint16_t* gq;
     const uint16_t* x;
     int ld;
+    static constexpr bool kStaged = false;
     __device__ void put(int m, int n, float acc, int) const {
         const size_t i = static_cast<size_t>(m) * ld + n;
         const float g = (x[i] & 0x7fffu) != 0 && !(x[i] & 0x8000u) ? acc : 0.0f;
@@ -161,8 +168,9 @@ struct EpMaskGrad {  // FC input gradient: g = acc * [x > 0], kept in FP32 and B
 // Grid: x = M tiles, y = N tiles, z = splits of the k range (kchunk each).
 template <class LA, class LB, class EP>
 __global__ __launch_bounds__(256) void gemm_kernel(LA la, LB lb, EP ep, int M, int N, int K, int kchunk) {
-    __shared__ __attribute__((aligned(16))) uint16_t As[kBM * kLds];
-    __shared__ __attribute__((aligned(16))) uint16_t Bs[kBN * kLds];
+    __shared__ __attribute__((aligned(16))) uint16_t smem[(kBM + kBN) * kLds];
+    uint16_t* const As = smem;
+    uint16_t* const Bs = smem + kBM * kLds;
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     const int wm = w >> 1, wn = w & 1;
     const int row0 = blockIdx.x * kBM, col0 = blockIdx.y * kBN;
@@ -200,21 +208,46 @@ __global__ __launch_bounds__(256) void gemm_kernel(LA la, LB lb, EP ep, int M, i
                 acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bf[j], acc[i][j], 0, 0, 0);
     }
     // C block (i, j): lane holds rows 4 (lane >> 4) + r, column lane & 15
+    if constexpr (EP::kStaged) {
+        // BF16 tile through LDS (over the operand buffers): each store
+        // instruction then writes eight whole 128-byte tile rows
+        constexpr int kCs = kBN + 8;   // C tile row stride, BF16 elements (144 B)
+        static_assert(kBM * kCs <= (kBM + kBN) * kLds, "C tile fits the operand buffers");
+        __syncthreads();
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+        for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+            for (int j = 0; j < 2; ++j)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int m = row0 + wm * 32 + i * 16 + 4 * (lane >> 4) + r;
-                const int n = col0 + wn * 32 + j * 16 + (lane & 15);
-                if (m < M && n < N) ep.put(m, n, acc[i][j][r], blockIdx.z);
-            }
+                for (int r = 0; r < 4; ++r) {
+                    const int rr = wm * 32 + i * 16 + 4 * (lane >> 4) + r, cc = wn * 32 + j * 16 + (lane & 15);
+                    smem[rr * kCs + cc] = ep.value(col0 + cc, acc[i][j][r]);
+                }
+        __syncthreads();
+#pragma unroll
+        for (int c = t; c < kBM * kBN / 8; c += 256) {
+            const int rr = c / (kBN / 8), c8 = (c % (kBN / 8)) * 8;
+            if (row0 + rr < M && col0 + c8 < N)
+                ep.put8(row0 + rr, col0 + c8, *reinterpret_cast<const uint4*>(smem + rr * kCs + c8));
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int m = row0 + wm * 32 + i * 16 + 4 * (lane >> 4) + r;
+                    const int n = col0 + wn * 32 + j * 16 + (lane & 15);
+                    if (m < M && n < N) ep.put(m, n, acc[i][j][r], blockIdx.z);
+                }
+    }
 }
 
 template <class LA, class LB, class EP>
 hipError_t gemm(const LA& la, const LB& lb, const EP& ep, int M, int N, int K, int splits, int kchunk,
                 hipStream_t s) {
+    if (EP::kStaged && N % 8 != 0) return hipErrorInvalidValue;
     const dim3 grid((M + kBM - 1) / kBM, (N + kBN - 1) / kBN, splits);
     hipLaunchKernelGGL((gemm_kernel<LA, LB, EP>), grid, dim3(256), 0, s, la, lb, ep, M, N, K, kchunk);
     return hipGetLastError();
@@ -281,6 +314,60 @@ static void set_shifts(Im2col& a, const Layer& L) {
     a.lgHW = lg2(L.hout * L.hout);
     a.lgWo = lg2(L.hout);
     a.lgCin = lg2(L.cin);
+}
+
+// First convolution (one input channel, kSide x kSide in, kConvWidth[0] out):
+// as a GEMM its reduction is only 9 long (padded to 32) and its 64-wide column
+// tile half used, so it runs as a direct 3 x 3 / stride 2 stencil instead, one
+// output pixel per thread and all output channels, eight at a time with those
+// eight channels' weights in scalar registers.  The work-group's 256 pixels x
+// kC0 channels are one contiguous stretch of the NHWC output: they go through
+// LDS so that each store instruction writes 1 KB contiguous.  Same arithmetic
+// as the GEMM path: BF16 operands, exact products summed in FP32 in tap
+// order, then bias, ReLU and BF16 rounding.
+constexpr int kHo0 = kSide / 2, kC0 = kConvWidth[0];
+static_assert(kSide % 2 == 0 && kC0 % 8 == 0 && (kHo0 * kHo0) % 256 == 0, "conv_first_kernel tiling");
+__global__ __launch_bounds__(256) void conv_first_kernel(const uint16_t* __restrict__ x,
+                                                         const uint16_t* __restrict__ wp, int Kp,
+                                                         const float* __restrict__ bias, uint16_t* __restrict__ y) {
+    constexpr int Q = kC0 / 8;   // uint4 pieces per pixel
+    __shared__ uint4 stage[256 * Q];
+    const int tid = threadIdx.x;
+    const long m = blockIdx.x * 256L + tid;   // grid: B * kHo0 * kHo0 / 256 blocks exactly
+    const int b = static_cast<int>(m / (kHo0 * kHo0)), r = static_cast<int>(m % (kHo0 * kHo0));
+    const int oy = r / kHo0, ox = r % kHo0;
+    const uint16_t* xb = x + static_cast<size_t>(b) * kSide * kSide;
+    float xv[9];
+#pragma unroll
+    for (int tap = 0; tap < 9; ++tap) {
+        const int iy = 2 * oy + tap / 3 - 1, ix = 2 * ox + tap % 3 - 1;
+        xv[tap] = (iy >= 0 && iy < kSide && ix >= 0 && ix < kSide) ? bf16_to_f32(xb[iy * kSide + ix]) : 0.0f;
+    }
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        float acc[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            // row co of the packed weights: taps 0..8, then zeros up to Kp
+            const uint32_t* wr = reinterpret_cast<const uint32_t*>(wp + (8 * q + j) * Kp);
+            acc[j] = 0.0f;
+#pragma unroll
+            for (int tap = 0; tap < 9; ++tap) {
+                const uint32_t u = wr[tap >> 1];
+                acc[j] = fmaf(xv[tap], __uint_as_float((tap & 1) ? (u & 0xffff0000u) : (u << 16)), acc[j]);
+            }
+        }
+        uint32_t pk[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            pk[j] = static_cast<uint32_t>(f32_to_bf16(fmaxf(acc[2 * j] + bias[8 * q + 2 * j], 0.0f))) |
+                    static_cast<uint32_t>(f32_to_bf16(fmaxf(acc[2 * j + 1] + bias[8 * q + 2 * j + 1], 0.0f))) << 16;
+        stage[tid * Q + q] = make_uint4(pk[0], pk[1], pk[2], pk[3]);
+    }
+    __syncthreads();
+    uint4* dst = reinterpret_cast<uint4*>(y + blockIdx.x * 256L * kC0);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) dst[tid + 256 * i] = stage[tid + 256 * i];
 }
 
 // ---- small kernels ----------------------------------------------------------
@@ -600,7 +687,12 @@ hipError_t net_forward(const float* params, const uint16_t* x0, int B, char* ws,
         LdRow wb{wp + L.wp_off, L.Kp, L.cout, L.Kp};
         if (i < 7) {
             EpAct ep{act_ptr(ws, w, B, T.l[i + 1], x0), bias, L.cout};
-            if (L.conv) {
+            if (i == 0) {
+                const long nblk = static_cast<long>(B) * kHo0 * kHo0 / 256;
+                hipLaunchKernelGGL(conv_first_kernel, dim3(static_cast<unsigned>(nblk)), dim3(256), 0, s, xin, wb.p,
+                                   L.Kp, bias, ep.out);
+                e = hipGetLastError();
+            } else if (L.conv) {
                 LdIm2col a;
                 a.x = xin; a.H = L.hin; a.W = L.hin; a.Cin = L.cin; a.Ho = L.hout; a.Wo = L.hout; a.M = M; a.K = L.K;
                 set_shifts(a, L);
