@@ -24,8 +24,26 @@ static_assert(pow2(kSide) && pow2(kConvWidth[0]) && pow2(kConvWidth[1]) && pow2(
               "the im2col index splits are shifts");
 constexpr int kBM = 64, kBN = 64, kBK = 32;
 constexpr int kLds = 40;   // LDS row stride in BF16 elements (80 B: 16-B aligned, spreads banks)
+constexpr int kPre = 3;    // GEMM k-steps of operand loads in flight
 
 __device__ __forceinline__ uint4 zero4() { return make_uint4(0u, 0u, 0u, 0u); }
+
+// 16 zero bytes in device memory (never written): the source of the operand
+// pieces that fall outside a matrix or into the convolution's zero padding.
+__device__ uint4 g_zero16;
+
+// 8 BF16 at p[off] when in, else zeros, as one unconditional load: the chosen
+// address passes through an empty asm statement, so the compiler can neither
+// make the load conditional nor select afterwards (conditional loads make it
+// wait for every load in flight).
+// (The pointer stays in the global address space: a generic one would make
+// these flat loads, which the LDS waits count as well.)
+typedef const __attribute__((address_space(1))) uint4 GlobalU4;
+__device__ __forceinline__ uint4 load8_or_zero(const uint16_t* p, size_t off, bool in) {
+    GlobalU4* q = in ? (GlobalU4*)(p + off) : (GlobalU4*)&g_zero16;
+    asm volatile("" : "+v"(q));
+    return *(const uint4*)q;
+}
 
 // ---- operand loaders ------------------------------------------------------
 // A loader describes a matrix Op(row, k).  kContig loaders return the 8
@@ -34,9 +52,9 @@ struct LdRow {   // Op(r, k) = p[r * ld + k]
     const uint16_t* p;
     int ld, rows, K;
     static constexpr bool kContig = true;
+    __device__ void limit(int ke) { K = min(K, ke); }   // zeros from reduction index ke on
     __device__ uint4 fetch(int r, int k) const {
-        if (r >= rows || k >= K) return zero4();
-        return *reinterpret_cast<const uint4*>(p + static_cast<size_t>(r) * ld + k);
+        return load8_or_zero(p, static_cast<size_t>(r) * ld + k, r < rows && k < K);
     }
 };
 
@@ -44,9 +62,9 @@ struct LdCol {   // Op(r, k) = p[k * ld + r]
     const uint16_t* p;
     int ld, rows, K;
     static constexpr bool kContig = false;
+    __device__ void limit(int ke) { K = min(K, ke); }
     __device__ uint4 fetch(int r, int k) const {
-        if (r >= rows || k >= K) return zero4();
-        return *reinterpret_cast<const uint4*>(p + static_cast<size_t>(k) * ld + r);
+        return load8_or_zero(p, static_cast<size_t>(k) * ld + r, r < rows && k < K);
     }
 };
 
@@ -59,16 +77,20 @@ struct Im2col {
     const uint16_t* x;
     int H, W, Cin, Ho, Wo, M, K;   // K = 9 Cin
     int lgHW, lgWo, lgCin;         // log2(Ho Wo), log2 Wo, log2 Cin
+    // Cin >= 8: 8 channels of one tap (branch-free, so that loads of several
+    // k-steps can be in flight at once).
+    __device__ uint4 fetch_wide(int m, int k) const {
+        const int b = m >> lgHW, r = m - (b << lgHW), oy = r >> lgWo, ox = r - (oy << lgWo);
+        const int tap = k >> lgCin, ci = k - (tap << lgCin);
+        const int ky = (tap * 11) >> 5, kx = tap - 3 * ky;
+        const int iy = 2 * oy + ky - 1, ix = 2 * ox + kx - 1;
+        return load8_or_zero(x, ((static_cast<size_t>(b) * H + iy) * W + ix) * Cin + ci,
+                             m < M && k < K && iy >= 0 && iy < H && ix >= 0 && ix < W);
+    }
     __device__ uint4 fetch8(int m, int k) const {
+        if (Cin >= 8) return fetch_wide(m, k);
         if (m >= M || k >= K) return zero4();
         const int b = m >> lgHW, r = m - (b << lgHW), oy = r >> lgWo, ox = r - (oy << lgWo);
-        if (Cin >= 8) {   // 8 channels of one tap
-            const int tap = k >> lgCin, ci = k - (tap << lgCin);
-            const int ky = (tap * 11) >> 5, kx = tap - 3 * ky;
-            const int iy = 2 * oy + ky - 1, ix = 2 * ox + kx - 1;
-            if (iy < 0 || iy >= H || ix < 0 || ix >= W) return zero4();
-            return *reinterpret_cast<const uint4*>(x + ((static_cast<size_t>(b) * H + iy) * W + ix) * Cin + ci);
-        }
         // Cin == 1: 8 consecutive taps
         uint16_t e[8];
 #pragma unroll
@@ -85,12 +107,14 @@ struct Im2col {
         return v;
     }
 };
-struct LdIm2col : Im2col {   // Op(m, k)
+struct LdIm2col : Im2col {   // Op(m, k); Cin >= 8 (the first convolution has its own kernel)
     static constexpr bool kContig = true;
-    __device__ uint4 fetch(int r, int k) const { return fetch8(r, k); }
+    __device__ void limit(int ke) { K = min(K, ke); }
+    __device__ uint4 fetch(int r, int k) const { return fetch_wide(r, k); }
 };
 struct LdIm2colT : Im2col {  // Op(j, m) = im2col(m, j): rows j..j+7 at reduction index m
     static constexpr bool kContig = false;
+    __device__ void limit(int ke) { M = min(M, ke); }
     __device__ uint4 fetch(int r, int k) const { return fetch8(k, r); }
 };
 
@@ -165,47 +189,75 @@ struct EpMaskGrad {  // FC input gradient: g = acc * [x > 0], kept in FP32 and B
 
 // C[M][N] = sum_k A(m, k) B(k, n), B given as Op(n, k).  Block: 64 x 64 tile,
 // four waves of 32 x 32 (2 x 2 MFMA blocks of 16 x 16), k-steps of 32.
-// Grid: x = M tiles, y = N tiles, z = splits of the k range (kchunk each).
+// Grid: x = M tiles (rounded up to eight when xcd is set) x N tiles, z =
+// splits of the k range (kchunk each).
 template <class LA, class LB, class EP>
-__global__ __launch_bounds__(256) void gemm_kernel(LA la, LB lb, EP ep, int M, int N, int K, int kchunk) {
+__global__ __launch_bounds__(256) void gemm_kernel(LA la, LB lb, EP ep, int M, int N, int K, int kchunk,
+                                                   int xcd) {
     __shared__ __attribute__((aligned(16))) uint16_t smem[(kBM + kBN) * kLds];
     uint16_t* const As = smem;
     uint16_t* const Bs = smem + kBM * kLds;
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     const int wm = w >> 1, wn = w & 1;
-    const int row0 = blockIdx.x * kBM, col0 = blockIdx.y * kBN;
+    // Tile order.  Work-groups are dealt to the eight XCDs in turn; with xcd set
+    // the N tiles of one M tile take ids eight apart: same XCD (same L2) and
+    // dispatched together, so the A rows they share are read from HBM once.
+    // Otherwise M tiles run fastest.
+    const int nM = (M + kBM - 1) / kBM, nN = (N + kBN - 1) / kBN;
+    int mt, nt;
+    if (xcd) {
+        const int slot = blockIdx.x >> 3;
+        mt = (slot / nN) * 8 + (blockIdx.x & 7);
+        nt = slot - (slot / nN) * nN;
+        if (mt >= nM) return;   // padding tiles of the last group of eight
+    } else {
+        nt = blockIdx.x / nM;
+        mt = blockIdx.x - nt * nM;
+    }
+    const int row0 = mt * kBM, col0 = nt * kBN;
     const int kb = blockIdx.z * kchunk, ke = min(K, kb + kchunk);
     f32x4 acc[2][2];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-    uint4 va = zero4(), vb = zero4();
-    if (kb < ke) {
-        va = tile_fetch(la, row0, kb, t);
-        vb = tile_fetch(lb, col0, kb, t);
+    // kPre k-steps of operand loads in flight (registers, rotating): a step's
+    // LDS store waits only for the loads issued kPre steps earlier.  The step
+    // count is rounded up to a multiple of kPre and the loaders return zeros
+    // from ke on, so the loop body is straight-line code.
+    la.limit(ke);
+    lb.limit(ke);
+    uint4 va[kPre], vb[kPre];
+#pragma unroll
+    for (int p = 0; p < kPre; ++p) {
+        va[p] = tile_fetch(la, row0, kb + p * kBK, t);
+        vb[p] = tile_fetch(lb, col0, kb + p * kBK, t);
     }
-    for (int k0 = kb; k0 < ke; k0 += kBK) {
-        __syncthreads();
-        tile_store<LA>(As, t, va);
-        tile_store<LB>(Bs, t, vb);
-        __syncthreads();
-        if (k0 + kBK < ke) {   // next tile's loads in flight during the MFMAs
-            va = tile_fetch(la, row0, k0 + kBK, t);
-            vb = tile_fetch(lb, col0, k0 + kBK, t);
-        }
-        bf16x8 af[2], bf[2];
+    const int groups = (ke - kb + kPre * kBK - 1) / (kPre * kBK);
+    for (int g = 0, k0 = kb; g < groups; ++g, k0 += kPre * kBK) {
 #pragma unroll
-        for (int i = 0; i < 2; ++i)
-            af[i] = *reinterpret_cast<const bf16x8*>(As + (wm * 32 + i * 16 + (lane & 15)) * kLds + 8 * (lane >> 4));
+        for (int p = 0; p < kPre; ++p) {
+            __syncthreads();
+            tile_store<LA>(As, t, va[p]);
+            tile_store<LB>(Bs, t, vb[p]);
+            __syncthreads();
+            va[p] = tile_fetch(la, row0, k0 + (p + kPre) * kBK, t);
+            vb[p] = tile_fetch(lb, col0, k0 + (p + kPre) * kBK, t);
+            bf16x8 af[2], bf[2];
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
-            bf[j] = *reinterpret_cast<const bf16x8*>(Bs + (wn * 32 + j * 16 + (lane & 15)) * kLds + 8 * (lane >> 4));
-#pragma unroll
-        for (int i = 0; i < 2; ++i)
+            for (int i = 0; i < 2; ++i)
+                af[i] = *reinterpret_cast<const bf16x8*>(As + (wm * 32 + i * 16 + (lane & 15)) * kLds +
+                                                         8 * (lane >> 4));
 #pragma unroll
             for (int j = 0; j < 2; ++j)
-                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bf[j], acc[i][j], 0, 0, 0);
+                bf[j] = *reinterpret_cast<const bf16x8*>(Bs + (wn * 32 + j * 16 + (lane & 15)) * kLds +
+                                                         8 * (lane >> 4));
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bf[j], acc[i][j], 0, 0, 0);
+        }
     }
     // C block (i, j): lane holds rows 4 (lane >> 4) + r, column lane & 15
     if constexpr (EP::kStaged) {
@@ -248,8 +300,12 @@ template <class LA, class LB, class EP>
 hipError_t gemm(const LA& la, const LB& lb, const EP& ep, int M, int N, int K, int splits, int kchunk,
                 hipStream_t s) {
     if (EP::kStaged && N % 8 != 0) return hipErrorInvalidValue;
-    const dim3 grid((M + kBM - 1) / kBM, (N + kBN - 1) / kBN, splits);
-    hipLaunchKernelGGL((gemm_kernel<LA, LB, EP>), grid, dim3(256), 0, s, la, lb, ep, M, N, K, kchunk);
+    const long nM = (M + kBM - 1) / kBM, nN = (N + kBN - 1) / kBN;
+    const int xcd = nM >= 8 && nN > 1;
+    const long nx = (xcd ? (nM + 7) / 8 * 8 : nM) * nN;
+    if (nx > 0x7fffffffL) return hipErrorInvalidValue;
+    const dim3 grid(static_cast<unsigned>(nx), 1, splits);
+    hipLaunchKernelGGL((gemm_kernel<LA, LB, EP>), grid, dim3(256), 0, s, la, lb, ep, M, N, K, kchunk, xcd);
     return hipGetLastError();
 }
 
