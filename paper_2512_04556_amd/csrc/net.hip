@@ -23,7 +23,11 @@ static_assert(pow2(kSide) && pow2(kConvWidth[0]) && pow2(kConvWidth[1]) && pow2(
                   pow2(kConvWidth[3]) && pow2(kConvWidth[4]) && pow2(kConvWidth[5]),
               "the im2col index splits are shifts");
 constexpr int kBM = 64, kBN = 64, kBK = 32;
-constexpr int kLds = 40;   // LDS row stride in BF16 elements (80 B: 16-B aligned, spreads banks)
+// Operand tiles in LDS: rows of kBK BF16 (64 B: four 16-B chunks) with chunk c
+// of row r stored at chunk c ^ ((r >> 2) & 3), so that the 16-B stores of four
+// consecutive rows and the MFMA fragment reads (one chunk of 16 rows) fall on
+// distinct banks.
+__host__ __device__ constexpr int tile_off(int r, int c) { return r * kBK + ((c ^ ((r >> 2) & 3)) << 3); }
 constexpr int kPre = 3;    // GEMM k-steps of operand loads in flight
 
 __device__ __forceinline__ uint4 zero4() { return make_uint4(0u, 0u, 0u, 0u); }
@@ -129,13 +133,13 @@ __device__ __forceinline__ uint4 tile_fetch(const LD& ld, int row0, int k0, int 
 template <class LD>
 __device__ __forceinline__ void tile_store(uint16_t* S, int t, uint4 v) {
     if constexpr (LD::kContig) {
-        *reinterpret_cast<uint4*>(S + (t >> 2) * kLds + (t & 3) * 8) = v;
+        *reinterpret_cast<uint4*>(S + tile_off(t >> 2, t & 3)) = v;
     } else {
         uint16_t e[8];
         __builtin_memcpy(e, &v, 16);
         const int r = (t & 7) * 8, k = t >> 3;
 #pragma unroll
-        for (int j = 0; j < 8; ++j) S[(r + j) * kLds + k] = e[j];
+        for (int j = 0; j < 8; ++j) S[tile_off(r + j, k >> 3) + (k & 7)] = e[j];
     }
 }
 
@@ -194,9 +198,11 @@ struct EpMaskGrad {  // FC input gradient: g = acc * [x > 0], kept in FP32 and B
 template <class LA, class LB, class EP>
 __global__ __launch_bounds__(256) void gemm_kernel(LA la, LB lb, EP ep, int M, int N, int K, int kchunk,
                                                    int xcd) {
-    __shared__ __attribute__((aligned(16))) uint16_t smem[(kBM + kBN) * kLds];
+    constexpr int kCs = kBN + 8;   // staged C tile row stride, BF16 elements (144 B)
+    constexpr int kSmem = (kBM + kBN) * kBK > kBM * kCs ? (kBM + kBN) * kBK : kBM * kCs;
+    __shared__ __attribute__((aligned(16))) uint16_t smem[kSmem];
     uint16_t* const As = smem;
-    uint16_t* const Bs = smem + kBM * kLds;
+    uint16_t* const Bs = smem + kBM * kBK;
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     const int wm = w >> 1, wn = w & 1;
     // Tile order.  Work-groups are dealt to the eight XCDs in turn; with xcd set
@@ -246,12 +252,10 @@ __global__ __launch_bounds__(256) void gemm_kernel(LA la, LB lb, EP ep, int M, i
             bf16x8 af[2], bf[2];
 #pragma unroll
             for (int i = 0; i < 2; ++i)
-                af[i] = *reinterpret_cast<const bf16x8*>(As + (wm * 32 + i * 16 + (lane & 15)) * kLds +
-                                                         8 * (lane >> 4));
+                af[i] = *reinterpret_cast<const bf16x8*>(As + tile_off(wm * 32 + i * 16 + (lane & 15), lane >> 4));
 #pragma unroll
             for (int j = 0; j < 2; ++j)
-                bf[j] = *reinterpret_cast<const bf16x8*>(Bs + (wn * 32 + j * 16 + (lane & 15)) * kLds +
-                                                         8 * (lane >> 4));
+                bf[j] = *reinterpret_cast<const bf16x8*>(Bs + tile_off(wn * 32 + j * 16 + (lane & 15), lane >> 4));
 #pragma unroll
             for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -261,10 +265,8 @@ __global__ __launch_bounds__(256) void gemm_kernel(LA la, LB lb, EP ep, int M, i
     }
     // C block (i, j): lane holds rows 4 (lane >> 4) + r, column lane & 15
     if constexpr (EP::kStaged) {
-        // BF16 tile through LDS (over the operand buffers): each store
+        // BF16 tile through LDS (over the operand tiles): each store
         // instruction then writes eight whole 128-byte tile rows
-        constexpr int kCs = kBN + 8;   // C tile row stride, BF16 elements (144 B)
-        static_assert(kBM * kCs <= (kBM + kBN) * kLds, "C tile fits the operand buffers");
         __syncthreads();
 #pragma unroll
         for (int i = 0; i < 2; ++i)
@@ -387,6 +389,11 @@ __global__ __launch_bounds__(256) void conv_first_kernel(const uint16_t* __restr
                                                          const uint16_t* __restrict__ wp, int Kp,
                                                          const float* __restrict__ bias, uint16_t* __restrict__ y) {
     constexpr int Q = kC0 / 8;   // uint4 pieces per pixel
+    static_assert(Q == 4, "stage_slot swizzles four pieces per pixel");
+    // piece q of pixel p at slot 4 p + (q ^ ((p >> 2) & 3)): sixteen lanes
+    // writing one piece of sixteen pixels, or reading four pieces of four
+    // pixels, use sixteen distinct bank groups
+    auto stage_slot = [](int p, int q) { return 4 * p + (q ^ ((p >> 2) & 3)); };
     __shared__ uint4 stage[256 * Q];
     const int tid = threadIdx.x;
     const long m = blockIdx.x * 256L + tid;   // grid: B * kHo0 * kHo0 / 256 blocks exactly
@@ -418,12 +425,15 @@ __global__ __launch_bounds__(256) void conv_first_kernel(const uint16_t* __restr
         for (int j = 0; j < 4; ++j)
             pk[j] = static_cast<uint32_t>(f32_to_bf16(fmaxf(acc[2 * j] + bias[8 * q + 2 * j], 0.0f))) |
                     static_cast<uint32_t>(f32_to_bf16(fmaxf(acc[2 * j + 1] + bias[8 * q + 2 * j + 1], 0.0f))) << 16;
-        stage[tid * Q + q] = make_uint4(pk[0], pk[1], pk[2], pk[3]);
+        stage[stage_slot(tid, q)] = make_uint4(pk[0], pk[1], pk[2], pk[3]);
     }
     __syncthreads();
     uint4* dst = reinterpret_cast<uint4*>(y + blockIdx.x * 256L * kC0);
 #pragma unroll
-    for (int i = 0; i < Q; ++i) dst[tid + 256 * i] = stage[tid + 256 * i];
+    for (int i = 0; i < Q; ++i) {
+        const int c = tid + 256 * i;   // 16-B piece c of the stretch: pixel c / Q, piece c % Q
+        dst[c] = stage[stage_slot(c / Q, c % Q)];
+    }
 }
 
 // ---- small kernels ----------------------------------------------------------
