@@ -192,11 +192,128 @@ __device__ void gather_layer(const float* __restrict__ src, float* __restrict__ 
     }
 }
 
+// Backward of a layer past the first, in one pass over the canvas.  The tap
+// correlations S_ab(i) = sum_p G(p) X(p + d_i + ab) equal, with q = p + d_i +
+// ab, sum_q X(q) G(q - d_i - ab): the same G values the transposed gather
+// G'(q) = sum_i sum_ab c_ab G(q - d_i - ab) reads.  So each lane reads X(q)
+// once and the 4 N values of G once, and accumulates both: G' of all N <= NT
+// taps (in the order of gather_layer<-1>) and the sums of the first NS taps
+// (registers; the later taps' sums are taken beforehand by the plain
+// correlation pass, since G'(q) then overwrites X(q), which only this lane
+// reads).  The sums go through the fixed-order wave + LDS reduction into sS.
+constexpr int kFuseS = 8;      // taps whose sums the fused pass accumulates
+constexpr int kFuseMax = 12;   // taps per layer up to which the fused pass runs
+template <int NS, int NT>
+__device__ __forceinline__ void fused_backward(const float* __restrict__ G, float* X, const TapO* tp, int N,
+                                               const Walk& wk, float (*sS)[4], float* red) {
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int S = wk.S;
+    float s[NS][4];
+    int off[NT];
+    bool all_in = true;
+#pragma unroll
+    for (int k = 0; k < NS; ++k)
+#pragma unroll
+        for (int ab = 0; ab < 4; ++ab) s[k][ab] = 0.0f;
+#pragma unroll
+    for (int k = 0; k < NT; ++k) {
+        off[k] = 0;
+        if (k < N) {
+            off[k] = uniform(tp[k].off);
+            all_in = all_in && tp[k].inside;
+        }
+    }
+    for (int blk = wave; blk < wk.nblk; blk += kOptWaves) {
+        int x, y;
+        bool act;
+        const int base = wk.pixel(blk, x, y, act);
+        const float xv = act ? *at(X, base) : 0.0f;
+        float gl = 0.0f;
+        if (all_in) {
+#pragma unroll
+            for (int k0 = 0; k0 < NT; k0 += 4) {
+                if (k0 < N) {
+                    float v[4][4];
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        const int q = base - off[k0 + k];
+                        v[k][0] = *at(G, q);
+                        v[k][1] = *at(G, q - 1);
+                        v[k][2] = *at(G, q - S);
+                        v[k][3] = *at(G, q - (S + 1));
+                    }
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        if (k0 + k < N) {
+                            const TapO& t = tp[k0 + k];
+                            gl = fmaf(t.c00, v[k][0], gl);
+                            gl = fmaf(t.c01, v[k][1], gl);
+                            gl = fmaf(t.c10, v[k][2], gl);
+                            gl = fmaf(t.c11, v[k][3], gl);
+                            if (k0 + k < NS)
+#pragma unroll
+                                for (int ab = 0; ab < 4; ++ab)
+                                    s[k0 + k][ab] = fmaf(xv, v[k][ab], s[k0 + k][ab]);
+                        }
+                    }
+                }
+            }
+        } else {
+            const int M = wk.M, P = wk.P;
+            const int xc = min(x, M - 1), yc = min(y, M - 1);
+#pragma unroll
+            for (int k = 0; k < NT; ++k) {
+                if (k < N) {
+                    const TapO t = tp[k];
+                    float v[4];
+                    if (t.inside) {
+                        const int q = base - t.off;
+                        v[0] = *at(G, q);
+                        v[1] = *at(G, q - 1);
+                        v[2] = *at(G, q - S);
+                        v[3] = *at(G, q - (S + 1));
+                    } else {
+                        v[0] = masked(G, xc, yc, -t.ix, -t.iy, M, S, P);
+                        v[1] = masked(G, xc, yc, -(t.ix + 1), -t.iy, M, S, P);
+                        v[2] = masked(G, xc, yc, -t.ix, -(t.iy + 1), M, S, P);
+                        v[3] = masked(G, xc, yc, -(t.ix + 1), -(t.iy + 1), M, S, P);
+                    }
+                    gl = fmaf(t.c00, v[0], gl);
+                    gl = fmaf(t.c01, v[1], gl);
+                    gl = fmaf(t.c10, v[2], gl);
+                    gl = fmaf(t.c11, v[3], gl);
+                    if (k < NS)
+#pragma unroll
+                        for (int ab = 0; ab < 4; ++ab) s[k][ab] = fmaf(xv, v[ab], s[k][ab]);
+                }
+            }
+        }
+        if (act) X[base] = gl;
+    }
+    // fixed-order reduction of the first min(N, NS) taps' sums
+    const int ns = min(N, NS);
+#pragma unroll
+    for (int k = 0; k < NS; ++k)
+        if (k < ns)
+#pragma unroll
+            for (int ab = 0; ab < 4; ++ab) {
+                const float v = wave_sum(s[k][ab]);
+                if (lane == 0) red[(wave * NS + k) * 4 + ab] = v;
+            }
+    __syncthreads();
+    if (tid < 4 * ns) {
+        const int k = tid >> 2, ab = tid & 3;
+        float v = 0.0f;
+        for (int w = 0; w < kOptWaves; ++w) v += red[(w * NS + k) * 4 + ab];
+        sS[k][ab] = v;
+    }
+}
+
 __global__ __launch_bounds__(kOptThreads, 4) void opt_kernel(OptArgs a) {
     __shared__ float th[kMaxT * 3], am[kMaxT * 3], av[kMaxT * 3], gr[kMaxT * 3];
     __shared__ TapO tap[kMaxT];
     __shared__ float sS[kMaxT][4];
-    __shared__ float red[kOptWaves * kChunk * 4];
+    __shared__ float red[kOptWaves * (kChunk > kFuseS ? kChunk : kFuseS) * 4];
     __shared__ int s_q;
     __shared__ int t0[DISK_MAX_LAYERS + 1];
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
@@ -356,7 +473,11 @@ __global__ __launch_bounds__(kOptThreads, 4) void opt_kernel(OptArgs a) {
                     }
                 } else {
                     const float* X = slot + l * SS;   // X_l (1-based), input of this layer
-                    for (int i0 = 0; i0 < N; i0 += kChunk) {
+                    // up to kFuseMax taps the fused pass below takes the first kFuseS
+                    // taps' sums; the rest (all of them for wider layers) come from
+                    // the correlation pass here, which must precede it
+                    const bool fuse = N <= kFuseMax;
+                    for (int i0 = fuse ? kFuseS : 0; i0 < N; i0 += kChunk) {
                         const int nc = min(kChunk, N - i0);
                         float s[kChunk][4];
 #pragma unroll
@@ -449,6 +570,8 @@ __global__ __launch_bounds__(kOptThreads, 4) void opt_kernel(OptArgs a) {
                         }
                         __syncthreads();
                     }
+                    // correlations of the first taps and G_l (1-based) in one pass; G_l replaces X_l
+                    if (fuse) fused_backward<kFuseS, kFuseMax>(G, slot + l * SS, tp, N, wk, sS, red);
                 }
                 __syncthreads();
                 // dTheta of this layer's taps
@@ -462,7 +585,7 @@ __global__ __launch_bounds__(kOptThreads, 4) void opt_kernel(OptArgs a) {
                     gr[3 * (t0[l] + i) + 2] =
                         (1.0f - fy) * ((1.0f - fx) * S00 + fx * S01) + fy * ((1.0f - fx) * S10 + fx * S11);
                 }
-                if (l > 0) {
+                if (l > 0 && N > kFuseMax) {
                     // G_l (1-based) = transpose of layer l+1 applied to G_{l+1}, into X_l's canvas
                     gather_layer<-1>(G, slot + l * SS, tp, N, wk);
                 }
