@@ -146,13 +146,45 @@ __device__ __forceinline__ float gather_tap(float acc, const TapO& t, const floa
     return acc;
 }
 
-// dst[p] = sum_taps sum_ab c_ab src[p + sgn * d_ab] over the interior (sgn = +1:
+// Where a gathered pixel goes: a plain store, or, for the last forward layer,
+// the loss terms of the chain output (NMSE, Eq. 11, or Charbonnier) and
+// dL/dK_syn written in place of K_syn.
+struct StoreOut {
+    float* dst;
+    __device__ __forceinline__ void operator()(int base, int, int, bool act, float acc) {
+        if (act) dst[base] = acc;
+    }
+};
+struct LossOut {
+    float* dst;
+    const float* tgt;
+    int M, charb;
+    float pk, inv_pk2, n, ce;
+    float se, ch;   // this lane's sums, in block order
+    __device__ __forceinline__ void operator()(int base, int x, int y, bool act, float acc) {
+        if (act) {
+            const float dv = acc - tgt[y * M + x];
+            se = fmaf(dv, dv, se);
+            float g;
+            if (charb) {
+                const float dn = dv / pk;
+                const float r = sqrtf(fmaf(dn, dn, ce * ce));
+                ch += r;
+                g = dn / (r * n * pk);
+            } else {
+                g = 2.0f * dv * inv_pk2 / n;
+            }
+            dst[base] = g;
+        }
+    }
+};
+
+// out(p, sum_taps sum_ab c_ab src[p + sgn * d_ab]) over the interior (sgn = +1:
 // forward gather; sgn = -1: the transpose, used for G_{l-1}).  Taps go four at
 // a time: when all four stay inside the zero frame their 16 reads are issued
 // together before the FMAs (same accumulation order as one tap at a time).
-template <int SGN>
-__device__ void gather_layer(const float* __restrict__ src, float* __restrict__ dst, const TapO* tp, int N,
-                             const Walk& wk) {
+template <int SGN, class Out>
+__device__ void gather_layer(const float* __restrict__ src, const TapO* tp, int N, const Walk& wk, Out& out) {
     const int wave = threadIdx.x >> 6;
     const int S = wk.S;
     for (int blk = wave; blk < wk.nblk; blk += kOptWaves) {
@@ -188,7 +220,7 @@ __device__ void gather_layer(const float* __restrict__ src, float* __restrict__ 
             }
         }
         for (; i < N; ++i) acc = gather_tap<SGN>(acc, tp[i], src, base, x, y, wk);
-        if (act) dst[base] = acc;
+        out(base, x, y, act, acc);
     }
 }
 
@@ -412,34 +444,33 @@ __global__ __launch_bounds__(kOptThreads, 4) void opt_kernel(OptArgs a) {
                 if (act) X1[base] = acc;
             }
             __syncthreads();
-            for (int l = 1; l < L; ++l) {
-                const float* src = slot + l * SS;
-                float* dst = slot + (l == L - 1 ? 0 : (l + 1) * SS);
-                gather_layer<1>(src, dst, tap + t0[l], ntap[l], wk);
-                __syncthreads();
-            }
-
-            // ---- loss, PSNR, G_L (in place of K_syn) ------------------------
+            // ---- loss, PSNR, G_L (in place of K_syn): in the last layer's pass,
+            // or over X_1 for a one-layer chain -----------------------------
             float se = 0.0f, ch = 0.0f;
             const float ce = a.p.charb_eps;
-            for (int blk = wave; blk < wk.nblk; blk += kOptWaves) {
-                int x, y;
-                bool act;
-                const int base = wk.pixel(blk, x, y, act);
-                if (act) {
-                    const float dv = slot[base] - tgt[y * M + x];
-                    se = fmaf(dv, dv, se);
-                    float g;
-                    if (a.p.loss == DISK_LOSS_CHARBONNIER) {
-                        const float dn = dv / pk;
-                        const float r = sqrtf(fmaf(dn, dn, ce * ce));
-                        ch += r;
-                        g = dn / (r * n * pk);
-                    } else {
-                        g = 2.0f * dv * inv_pk2 / n;
-                    }
-                    slot[base] = g;
+            for (int l = 1; l < L; ++l) {
+                const float* src = slot + l * SS;
+                if (l < L - 1) {
+                    StoreOut o{slot + (l + 1) * SS};
+                    gather_layer<1>(src, tap + t0[l], ntap[l], wk, o);
+                } else {
+                    LossOut o{slot, tgt, M, a.p.loss == DISK_LOSS_CHARBONNIER, pk, inv_pk2, n, ce, 0.0f, 0.0f};
+                    gather_layer<1>(src, tap + t0[l], ntap[l], wk, o);
+                    se = o.se;
+                    ch = o.ch;
                 }
+                __syncthreads();
+            }
+            if (L == 1) {
+                LossOut o{slot, tgt, M, a.p.loss == DISK_LOSS_CHARBONNIER, pk, inv_pk2, n, ce, 0.0f, 0.0f};
+                for (int blk = wave; blk < wk.nblk; blk += kOptWaves) {
+                    int x, y;
+                    bool act;
+                    const int base = wk.pixel(blk, x, y, act);
+                    o(base, x, y, act, slot[base]);
+                }
+                se = o.se;
+                ch = o.ch;
             }
             se = wg_sum(se, red);
             if (a.p.loss == DISK_LOSS_CHARBONNIER) ch = wg_sum(ch, red);
@@ -587,7 +618,8 @@ __global__ __launch_bounds__(kOptThreads, 4) void opt_kernel(OptArgs a) {
                 }
                 if (l > 0 && N > kFuseMax) {
                     // G_l (1-based) = transpose of layer l+1 applied to G_{l+1}, into X_l's canvas
-                    gather_layer<-1>(G, slot + l * SS, tp, N, wk);
+                    StoreOut o{slot + l * SS};
+                    gather_layer<-1>(G, tp, N, wk, o);
                 }
                 __syncthreads();
             }
