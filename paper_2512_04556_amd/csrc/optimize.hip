@@ -429,12 +429,24 @@ __global__ __launch_bounds__(kOptThreads, 4) void opt_kernel(OptArgs a) {
 
             // ---- forward: X_1 = splats of layer 1 on the impulse ------------
             float* X1 = slot + (L == 1 ? 0 : SS);
+            // pixel x receives from tap i only at x = c - ix_i - {0, 1} (likewise
+            // y): blocks outside the box of all splats hold zeros and skip the taps
+            int sx0 = M, sx1 = -1, sy0 = M, sy1 = -1;
+            for (int i = 0; i < ntap[0]; ++i) {
+                const int ix = uniform(tap[i].ix), iy = uniform(tap[i].iy);
+                sx0 = min(sx0, c - ix - 1);
+                sx1 = max(sx1, c - ix);
+                sy0 = min(sy0, c - iy - 1);
+                sy1 = max(sy1, c - iy);
+            }
             for (int blk = wave; blk < wk.nblk; blk += kOptWaves) {
                 int x, y;
                 bool act;
                 const int base = wk.pixel(blk, x, y, act);
                 float acc = 0.0f;
-                for (int i = 0; i < ntap[0]; ++i) {
+                const int bx = uniform(x - (lane & 7)), by = uniform(y - (lane >> 3));   // block corner
+                const bool hit = bx <= sx1 && bx + 7 >= sx0 && by <= sy1 && by + 7 >= sy0;
+                for (int i = 0; hit && i < ntap[0]; ++i) {
                     const TapO t = tap[i];
                     // corner (a, b) of pixel p reads p + (ix+a, iy+b); the impulse is at c
                     const int ax = c - x - t.ix, ay = c - y - t.iy;
