@@ -114,6 +114,23 @@ struct Walk {
     }
 };
 
+// Support boxes.  X_1 (the first layer's splats on the impulse) is nonzero
+// only in a box around the centre, and X_{l+1}(p) reads X_l(p + d_i + ab), so
+// the box of X_{l+1} is that of X_l moved by -d_i - ab over the layer's taps
+// (clipped to the M x M interior).  Passes skip the 8 x 8 blocks that miss the
+// box they need; an empty box has x0 > x1.
+struct Box {
+    int x0, x1, y0, y1;
+};
+__device__ __forceinline__ bool block_meets(const Walk& wk, int blk, const Box& b) {
+    const int by = (blk * wk.inv) >> 16, bx = blk - by * wk.nbx;
+    const int x = bx << 3, y = by << 3;
+    return x <= b.x1 && x + 7 >= b.x0 && y <= b.y1 && y + 7 >= b.y0;
+}
+__device__ __forceinline__ Box load_box(const int* v) {
+    return Box{uniform(v[0]), uniform(v[1]), uniform(v[2]), uniform(v[3])};
+}
+
 // Value of a corner read that may leave the frame (masked path).
 __device__ __forceinline__ float masked(const float* buf, int x, int y, int dx, int dy, int M, int S, int P) {
     const int xx = x + dx, yy = y + dy;
@@ -150,12 +167,14 @@ __device__ __forceinline__ float gather_tap(float acc, const TapO& t, const floa
 // the loss terms of the chain output (NMSE, Eq. 11, or Charbonnier) and
 // dL/dK_syn written in place of K_syn.
 struct StoreOut {
+    static constexpr bool kEvery = false;   // blocks outside both boxes need no store
     float* dst;
     __device__ __forceinline__ void operator()(int base, int, int, bool act, float acc) {
         if (act) dst[base] = acc;
     }
 };
 struct LossOut {
+    static constexpr bool kEvery = true;    // every pixel enters the loss
     float* dst;
     const float* tgt;
     int M, charb;
@@ -183,16 +202,23 @@ struct LossOut {
 // forward gather; sgn = -1: the transpose, used for G_{l-1}).  Taps go four at
 // a time: when all four stay inside the zero frame their 16 reads are issued
 // together before the FMAs (same accumulation order as one tap at a time).
+// Blocks that miss `box` (where the sum is zero, or not needed) take 0 without
+// reading; of those, the ones that also miss `zbox` are skipped unless Out
+// needs every pixel.
 template <int SGN, class Out>
-__device__ void gather_layer(const float* __restrict__ src, const TapO* tp, int N, const Walk& wk, Out& out) {
+__device__ void gather_layer(const float* __restrict__ src, const TapO* tp, int N, const Walk& wk, Out& out,
+                             const Box& box, const Box& zbox) {
     const int wave = threadIdx.x >> 6;
     const int S = wk.S;
     for (int blk = wave; blk < wk.nblk; blk += kOptWaves) {
+        const bool hit = block_meets(wk, blk, box);
+        if (!hit && !Out::kEvery && !block_meets(wk, blk, zbox)) continue;
         int x, y;
         bool act;
         const int base = wk.pixel(blk, x, y, act);
         float acc = 0.0f;
         int i = 0;
+        if (!hit) i = N;
         for (; i + 4 <= N; i += 4) {
             TapO t[4];
 #pragma unroll
@@ -237,7 +263,7 @@ constexpr int kFuseS = 8;      // taps whose sums the fused pass accumulates
 constexpr int kFuseMax = 12;   // taps per layer up to which the fused pass runs
 template <int NS, int NT>
 __device__ __forceinline__ void fused_backward(const float* __restrict__ G, float* X, const TapO* tp, int N,
-                                               const Walk& wk, float (*sS)[4], float* red) {
+                                               const Walk& wk, float (*sS)[4], float* red, const Box& box) {
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int S = wk.S;
     float s[NS][4];
@@ -256,6 +282,8 @@ __device__ __forceinline__ void fused_backward(const float* __restrict__ G, floa
         }
     }
     for (int blk = wave; blk < wk.nblk; blk += kOptWaves) {
+        // outside the box of X: X = 0 (no sums) and G' is not needed
+        if (!block_meets(wk, blk, box)) continue;
         int x, y;
         bool act;
         const int base = wk.pixel(blk, x, y, act);
@@ -348,6 +376,8 @@ __global__ __launch_bounds__(kOptThreads, 4) void opt_kernel(OptArgs a) {
     __shared__ float red[kOptWaves * (kChunk > kFuseS ? kChunk : kFuseS) * 4];
     __shared__ int s_q;
     __shared__ int t0[DISK_MAX_LAYERS + 1];
+    // support boxes (x0, x1, y0, y1) of X_1..X_L this step and the last one
+    __shared__ int s_box[DISK_MAX_LAYERS + 1][4], s_pbox[DISK_MAX_LAYERS + 1][4];
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     float* slot = a.scratch + blockIdx.x * a.slot_floats;
 
@@ -400,6 +430,7 @@ __global__ __launch_bounds__(kOptThreads, 4) void opt_kernel(OptArgs a) {
             av[i] = 0.0f;
         }
         for (size_t i = tid; i < SS * L; i += kOptThreads) slot[i] = 0.0f;
+        if (tid < 4 * (DISK_MAX_LAYERS + 1)) s_box[tid >> 2][tid & 3] = (tid & 1) ? -1 : M;   // empty: the canvases are zero
         float pk = -INFINITY;
         for (int i = tid; i < M * M; i += kOptThreads) pk = fmaxf(pk, tgt[i]);
         pk = wg_max(pk, red);
@@ -426,26 +457,52 @@ __global__ __launch_bounds__(kOptThreads, 4) void opt_kernel(OptArgs a) {
                 tap[i] = t;
             }
             __syncthreads();
+            if (tid == 0) {
+                // last step's boxes: where the canvases may still hold values
+                for (int j = 0; j <= L; ++j)
+                    for (int k = 0; k < 4; ++k) s_pbox[j][k] = s_box[j][k];
+                int bx0 = 0, bx1 = -1, by0 = 0, by1 = -1;
+                for (int l = 0; l < L; ++l) {
+                    // X_{l+1} from X_l (l = 0: the impulse at (c, c))
+                    if (l == 0) {
+                        bx0 = bx1 = by0 = by1 = c;
+                    } else if (bx0 > bx1 || by0 > by1) {
+                        s_box[l + 1][0] = M, s_box[l + 1][1] = -1, s_box[l + 1][2] = M, s_box[l + 1][3] = -1;
+                        continue;
+                    }
+                    int mnx = tap[t0[l]].ix, mxx = mnx, mny = tap[t0[l]].iy, mxy = mny;
+                    for (int i = t0[l] + 1; i < t0[l + 1]; ++i) {
+                        mnx = min(mnx, tap[i].ix);
+                        mxx = max(mxx, tap[i].ix);
+                        mny = min(mny, tap[i].iy);
+                        mxy = max(mxy, tap[i].iy);
+                    }
+                    bx0 = max(bx0 - mxx - 1, 0);
+                    bx1 = min(bx1 - mnx, M - 1);
+                    by0 = max(by0 - mxy - 1, 0);
+                    by1 = min(by1 - mny, M - 1);
+                    const bool empty = bx0 > bx1 || by0 > by1;
+                    s_box[l + 1][0] = empty ? M : bx0;
+                    s_box[l + 1][1] = empty ? -1 : bx1;
+                    s_box[l + 1][2] = empty ? M : by0;
+                    s_box[l + 1][3] = empty ? -1 : by1;
+                }
+            }
+            __syncthreads();
 
             // ---- forward: X_1 = splats of layer 1 on the impulse ------------
             float* X1 = slot + (L == 1 ? 0 : SS);
-            // pixel x receives from tap i only at x = c - ix_i - {0, 1} (likewise
-            // y): blocks outside the box of all splats hold zeros and skip the taps
-            int sx0 = M, sx1 = -1, sy0 = M, sy1 = -1;
-            for (int i = 0; i < ntap[0]; ++i) {
-                const int ix = uniform(tap[i].ix), iy = uniform(tap[i].iy);
-                sx0 = min(sx0, c - ix - 1);
-                sx1 = max(sx1, c - ix);
-                sy0 = min(sy0, c - iy - 1);
-                sy1 = max(sy1, c - iy);
-            }
+            // blocks outside X_1's box hold zeros (written only where last step's
+            // values may remain; a one-layer chain's canvas holds G everywhere)
+            const Box b1 = load_box(s_box[1]);
+            const Box z1 = L == 1 ? Box{0, M - 1, 0, M - 1} : load_box(s_pbox[1]);
             for (int blk = wave; blk < wk.nblk; blk += kOptWaves) {
+                const bool hit = block_meets(wk, blk, b1);
+                if (!hit && !block_meets(wk, blk, z1)) continue;
                 int x, y;
                 bool act;
                 const int base = wk.pixel(blk, x, y, act);
                 float acc = 0.0f;
-                const int bx = uniform(x - (lane & 7)), by = uniform(y - (lane >> 3));   // block corner
-                const bool hit = bx <= sx1 && bx + 7 >= sx0 && by <= sy1 && by + 7 >= sy0;
                 for (int i = 0; hit && i < ntap[0]; ++i) {
                     const TapO t = tap[i];
                     // corner (a, b) of pixel p reads p + (ix+a, iy+b); the impulse is at c
@@ -462,12 +519,13 @@ __global__ __launch_bounds__(kOptThreads, 4) void opt_kernel(OptArgs a) {
             const float ce = a.p.charb_eps;
             for (int l = 1; l < L; ++l) {
                 const float* src = slot + l * SS;
+                const Box bo = load_box(s_box[l + 1]);
                 if (l < L - 1) {
                     StoreOut o{slot + (l + 1) * SS};
-                    gather_layer<1>(src, tap + t0[l], ntap[l], wk, o);
+                    gather_layer<1>(src, tap + t0[l], ntap[l], wk, o, bo, load_box(s_pbox[l + 1]));
                 } else {
                     LossOut o{slot, tgt, M, a.p.loss == DISK_LOSS_CHARBONNIER, pk, inv_pk2, n, ce, 0.0f, 0.0f};
-                    gather_layer<1>(src, tap + t0[l], ntap[l], wk, o);
+                    gather_layer<1>(src, tap + t0[l], ntap[l], wk, o, bo, bo);
                     se = o.se;
                     ch = o.ch;
                 }
@@ -520,6 +578,8 @@ __global__ __launch_bounds__(kOptThreads, 4) void opt_kernel(OptArgs a) {
                     // taps' sums; the rest (all of them for wider layers) come from
                     // the correlation pass here, which must precede it
                     const bool fuse = N <= kFuseMax;
+                    // p outside the output's box reads only zeros of X: G(p) X(p + d) = 0
+                    const Box ob = load_box(s_box[l + 1]);
                     for (int i0 = fuse ? kFuseS : 0; i0 < N; i0 += kChunk) {
                         const int nc = min(kChunk, N - i0);
                         float s[kChunk][4];
@@ -530,7 +590,7 @@ __global__ __launch_bounds__(kOptThreads, 4) void opt_kernel(OptArgs a) {
                         // the chunk's canvas offsets (wave-uniform); when all taps stay
                         // inside the zero frame the 4 kChunk reads of a pixel go out together
                         int off[kChunk];
-                        bool all_in = nc == kChunk;
+                        bool all_in = (nc & 3) == 0;
 #pragma unroll
                         for (int k = 0; k < kChunk; ++k) {
                             off[k] = 0;
@@ -542,12 +602,14 @@ __global__ __launch_bounds__(kOptThreads, 4) void opt_kernel(OptArgs a) {
                         }
                         if (all_in) {
                             for (int blk = wave; blk < wk.nblk; blk += kOptWaves) {
+                                if (!block_meets(wk, blk, ob)) continue;
                                 int x, y;
                                 bool act;
                                 const int base = wk.pixel(blk, x, y, act);
                                 const float g = act ? G[base] : 0.0f;
 #pragma unroll
                                 for (int k0 = 0; k0 < kChunk; k0 += 4) {
+                                    if (k0 >= nc) break;
                                     float v[4][4];
 #pragma unroll
                                     for (int k = 0; k < 4; ++k) {
@@ -566,6 +628,7 @@ __global__ __launch_bounds__(kOptThreads, 4) void opt_kernel(OptArgs a) {
                             }
                         } else {
                         for (int blk = wave; blk < wk.nblk; blk += kOptWaves) {
+                            if (!block_meets(wk, blk, ob)) continue;
                             int x, y;
                             bool act;
                             const int base = wk.pixel(blk, x, y, act);
@@ -614,7 +677,7 @@ __global__ __launch_bounds__(kOptThreads, 4) void opt_kernel(OptArgs a) {
                         __syncthreads();
                     }
                     // correlations of the first taps and G_l (1-based) in one pass; G_l replaces X_l
-                    if (fuse) fused_backward<kFuseS, kFuseMax>(G, slot + l * SS, tp, N, wk, sS, red);
+                    if (fuse) fused_backward<kFuseS, kFuseMax>(G, slot + l * SS, tp, N, wk, sS, red, load_box(s_box[l]));
                 }
                 __syncthreads();
                 // dTheta of this layer's taps
@@ -631,7 +694,9 @@ __global__ __launch_bounds__(kOptThreads, 4) void opt_kernel(OptArgs a) {
                 if (l > 0 && N > kFuseMax) {
                     // G_l (1-based) = transpose of layer l+1 applied to G_{l+1}, into X_l's canvas
                     StoreOut o{slot + l * SS};
-                    gather_layer<-1>(G, tp, N, wk, o);
+                    // needed (and written) only in X_l's box: the canvas keeps its zeros elsewhere
+                    const Box none{M, -1, M, -1};
+                    gather_layer<-1>(G, tp, N, wk, o, load_box(s_box[l]), none);
                 }
                 __syncthreads();
             }

@@ -137,6 +137,28 @@ def test_config1_300_steps_from_jittered_start(dev):
     assert st[0] == 300 and abs(ps[0] - ps_o) < 0.2
 
 
+def test_moving_support_trajectory(dev):
+    """Large steps (lr 0.2) move tap offsets by whole pixels, so the support
+    boxes of the chain's canvases (outside which the kernel skips blocks)
+    grow and shrink from step to step: PSNR after 1, 3 and 6 steps within
+    0.05 dB of the FP64 oracle, for 4 x 12 taps (fused backward) and 3 x 16
+    taps (separate correlation and transpose passes)."""
+    for seed, L, N in ((31, 4, 12), (32, 3, 16)):
+        batch = mixed_batch(3, seed=seed, side=(21, 41), fixed_L=L, fixed_N=N)
+        th0 = _theta0(batch)
+        desc, _, _ = pack_targets(batch)
+        for n in (1, 3, 6):
+            say("opt moving support", seed, n)
+            th, ps, st, stat = _run(batch, th0, max_steps=n, lr0=0.2, lr1=0.2)
+            p = Ad.OptParams(max_steps=n, lr0=0.2, lr1=0.2)
+            for b in range(batch.B):
+                o, T = int(desc[b, 3]), int(np.sum(batch.taps[b]))
+                _, ps_o, _ = Ad.optimize(batch.kernels[b].astype(np.float64), th0[o:o + T], batch.taps[b], p)
+                print(f"seed {seed} target {b} {n} steps: GPU {ps[b]:.4f} dB oracle {ps_o:.4f} dB")
+                assert st[b] == n and stat[b] == 0
+                assert abs(ps[b] - ps_o) < 0.05, (seed, b, n, ps[b], ps_o)
+
+
 def test_stopping_rule_and_invalid_target(dev):
     batch = mixed_batch(3, seed=5, side=(15, 31))
     th0 = _theta0(batch)
