@@ -493,6 +493,14 @@ def main():
     ws = disk.sv_filter_workspace(basis, C, H, W)
     stream = torch.cuda.current_stream()
 
+    # Settle: for about 20 ms after the basis fit (a second of persistent
+    # optimiser work) frames run ~7% slower (110.8 against 103.4 us, the
+    # same calls), so untimed frames run for 0.3 s before the warm-up steps.
+    t_settle = time.perf_counter()
+    while time.perf_counter() - t_settle < 0.3:
+        for _ in range(50):
+            disk.disk_sv_filter(basis, x, p, out=out, ws=ws)
+        torch.cuda.synchronize()
     for _ in range(a.warmup):
         disk.disk_sv_filter(basis, x, p, out=out, ws=ws)
     torch.cuda.synchronize()
