@@ -108,31 +108,36 @@ __global__ __launch_bounds__(256) void adjoint_taps_kernel(Src src, const float*
 }
 
 // One block per (tap, corner): fixed-order strided sums then a fixed tree.
-__global__ __launch_bounds__(256) void adjoint_reduce_kernel(const float* __restrict__ partial, int nblk, int N,
-                                                             float* __restrict__ sums) {
-    __shared__ float buf[256];
-    const int i = blockIdx.x >> 2, a = blockIdx.x & 3;
-    float v = 0.0f;
-    for (int b = threadIdx.x; b < nblk; b += 256) v += partial[(static_cast<size_t>(b) * N + i) * 4 + a];
-    buf[threadIdx.x] = v;
+// One work-group per tap: the four corner sums S_ab over the nblk block
+// partials (thread t adds blocks t, t + 256, ... in order, then a fixed tree),
+// and from them the tap's gradient (the bilinear weights' derivatives).
+__global__ __launch_bounds__(256) void adjoint_finish_kernel(const float* __restrict__ partial, int nblk, int N,
+                                                             const float* __restrict__ theta,
+                                                             float* __restrict__ dtheta) {
+    __shared__ float buf[4][256];
+    const int i = blockIdx.x, t = threadIdx.x;
+    float v[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    for (int b = t; b < nblk; b += 256) {
+        const float* q = partial + (static_cast<size_t>(b) * N + i) * 4;
+#pragma unroll
+        for (int a = 0; a < 4; ++a) v[a] += q[a];
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a) buf[a][t] = v[a];
     __syncthreads();
     for (int m = 128; m >= 1; m >>= 1) {
-        if (threadIdx.x < m) buf[threadIdx.x] += buf[threadIdx.x + m];
+        if (t < m)
+#pragma unroll
+            for (int a = 0; a < 4; ++a) buf[a][t] += buf[a][t + m];
         __syncthreads();
     }
-    if (threadIdx.x == 0) sums[i * 4 + a] = buf[0];
-}
-
-__global__ void adjoint_finish_kernel(const float* __restrict__ sums, const float* __restrict__ theta, int N,
-                                      float* __restrict__ dtheta) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= N) return;
+    if (t != 0) return;
     const float ox = theta[3 * i + 0], oy = theta[3 * i + 1], w = theta[3 * i + 2];
     int ix, iy;
     float fx, fy;
     floor_frac(-ox, ix, fx);
     floor_frac(-oy, iy, fy);
-    const float S00 = sums[4 * i + 0], S01 = sums[4 * i + 1], S10 = sums[4 * i + 2], S11 = sums[4 * i + 3];
+    const float S00 = buf[0][0], S01 = buf[1][0], S10 = buf[2][0], S11 = buf[3][0];
     const float gw = (1.0f - fy) * ((1.0f - fx) * S00 + fx * S01) + fy * ((1.0f - fx) * S10 + fx * S11);
     const float gx = -w * ((1.0f - fy) * (S01 - S00) + fy * (S11 - S10));
     const float gy = -w * ((1.0f - fx) * (S10 - S00) + fx * (S11 - S01));
@@ -178,13 +183,11 @@ hipError_t launch_adjoint_taps(int C, int boundary, int src_kind, const void* X,
     }
 }
 
-// `partial` holds nblk * N * 4 block partials followed by room for the N * 4
-// per-tap sums (the workspace carving reserves both).
+// `partial` holds nblk * N * 4 block partials (the workspace carving also
+// reserves N * 4 floats after them).
 hipError_t launch_adjoint_finish(float* partial, int nblk, const float* theta_layer, int N, float* dtheta_layer,
                                  hipStream_t s) {
-    float* sums = partial + static_cast<size_t>(nblk) * N * 4;
-    hipLaunchKernelGGL(adjoint_reduce_kernel, dim3(4 * N), dim3(256), 0, s, partial, nblk, N, sums);
-    hipLaunchKernelGGL(adjoint_finish_kernel, dim3((N + 63) / 64), dim3(64), 0, s, sums, theta_layer, N,
+    hipLaunchKernelGGL(adjoint_finish_kernel, dim3(N), dim3(256), 0, s, partial, nblk, N, theta_layer,
                        dtheta_layer);
     return hipGetLastError();
 }

@@ -86,7 +86,7 @@ hipError_t launch_chain_transpose(int C, const float* G, float* Gprev, const flo
 hipError_t launch_adjoint_input_border(int C, const float* G, const TapU* taps, int N, int H, int W, float* Gprev,
                                        hipStream_t s);
 // Tap correlations of one uniform layer (C = 3, 4) through the staged kernel:
-// partial[nblk][N][4] in the layout adjoint_reduce_kernel sums (*nblk set to
+// partial[nblk][N][4] in the layout adjoint_finish_kernel sums (*nblk set to
 // the grid, <= adjoint_tap_blocks(H, W)).  X: the layer input, G: its output
 // gradient (both FP32).
 hipError_t launch_adjoint_corr(int C, int boundary, const float* X, const float* G, const float* theta, int tap0,
