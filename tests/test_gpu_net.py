@@ -84,6 +84,29 @@ def test_predict_matches_oracle(dev, B):
     assert err.max() <= 1e-2
 
 
+def test_predict_bench_batch_sampled(dev):
+    """Batch 4096, the launch configuration bench.py times (first convolution
+    kernel, 64 x 64 GEMM tiles in XCD order over 16 384 rows of conv 2): 16
+    sampled samples, including the first and the last, against the oracle on
+    the same BF16 operands, to the tolerances of the small batches."""
+    B = 4096
+    rng = np.random.default_rng(77)
+    bits, xval = _bf16_bits(rng.uniform(0, 1, (B, 64, 64)) ** 3)
+    hw = rng.uniform(32, 64, B).astype(np.float32)
+    p = _params(5)
+    say("net predict", B)
+    th = disk.disk_init_predict(torch.as_tensor(p).cuda(), bits.cuda(), torch.as_tensor(hw).cuda())
+    got = th.cpu().numpy().astype(np.float64)
+    idx = np.unique(np.concatenate([[0, B - 1], rng.integers(1, B - 1, 14)]))
+    y, _ = N.forward(p.astype(np.float64), xval[idx])
+    want = np.stack([N.theta_of(y[k], float(hw[b])) for k, b in enumerate(idx)])
+    got = got.reshape(B, *want.shape[1:])[idx]
+    err = np.abs(got - want).reshape(len(idx), -1).max(axis=1) / np.abs(want).reshape(len(idx), -1).max(axis=1)
+    print(f"predict B={B}, {len(idx)} samples: max err median {np.median(err):.2e}, max {err.max():.2e}")
+    assert np.median(err) <= 1e-5
+    assert err.max() <= 1e-2
+
+
 def test_train_step_matches_oracle(dev):
     B = 37
     rng = np.random.default_rng(40)

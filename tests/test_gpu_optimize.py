@@ -159,6 +159,27 @@ def test_moving_support_trajectory(dev):
                 assert abs(ps[b] - ps_o) < 0.05, (seed, b, n, ps[b], ps_o)
 
 
+def test_bench_batch_sampled_trajectories(dev):
+    """The time-to-40 dB launch configuration: 4096 targets (odd sides
+    15..127, the five shape families, 4 x 12 taps, seed 7, radial init) in
+    one persistent launch.  After 20 steps, five sampled targets (sides 15,
+    43, 71, 101, 127) are within 0.1 dB of the oracle's 20-step trajectory
+    from the same Theta_0; every target ran its 20 steps."""
+    batch = mixed_batch(4096, seed=7, fixed_L=4, fixed_N=12)
+    th0 = _theta0(batch)
+    say("opt bench batch 4096 x 20 steps")
+    th, ps, st, stat = _run(batch, th0, max_steps=20, lr0=1e-2, lr1=1e-3)
+    assert np.all(st == 20) and np.all(stat == 0)
+    desc, _, _ = pack_targets(batch)
+    sides = np.array([k.shape[0] for k in batch.kernels])
+    p = Ad.OptParams(max_steps=20, lr0=1e-2, lr1=1e-3)
+    for b in np.argsort(sides, kind="stable")[[0, 1024, 2048, 3072, 4095]]:
+        o, T = int(desc[b, 3]), int(np.sum(batch.taps[b]))
+        _, ps_o, _ = Ad.optimize(batch.kernels[b].astype(np.float64), th0[o:o + T], batch.taps[b], p)
+        print(f"target {b} side {sides[b]}: GPU {ps[b]:.4f} dB oracle {ps_o:.4f} dB")
+        assert abs(ps[b] - ps_o) < 0.1, (b, sides[b], ps[b], ps_o)
+
+
 def test_stopping_rule_and_invalid_target(dev):
     batch = mixed_batch(3, seed=5, side=(15, 31))
     th0 = _theta0(batch)
