@@ -256,6 +256,22 @@ disk_status disk_backward(const disk_complex* cx, const float* theta, const floa
     for (int l = sp.L - 1; l >= 0; --l) {
         const void* X = l == 0 ? static_cast<const void*>(in) : static_cast<const void*>(saved + (l - 1) * n);
         const int src_kind = (l == 0 && impulse) ? 2 : 0;
+        if (grad_theta && (l > 0 || grad_in) && !impulse && chain_pass_ok(C, DISK_CLAMP)) {
+            // the input adjoint and the tap correlations in one staged pass
+            float* Gn = l == 0 ? grad_in : (G == g0 ? g1 : g0);
+            int rows = 0;
+            DISK_HIP(launch_chain_fused(C, boundary, G, static_cast<const float*>(X), Gn, theta, sp.tap0[l],
+                                        sp.taps[l], sp.T, H, W, partial, &rows, stream),
+                     "adjoint fused");
+            DISK_HIP(launch_adjoint_finish(partial, rows, theta + 3 * sp.tap0[l], sp.taps[l],
+                                           grad_theta + 3 * sp.tap0[l], stream),
+                     "adjoint finish");
+            if (boundary == DISK_CLAMP)
+                DISK_HIP(launch_adjoint_input_border(C, G, tapu + sp.tap0[l], sp.taps[l], H, W, Gn, stream),
+                         "adjoint input border");
+            G = Gn;
+            continue;
+        }
         if (grad_theta) {
             int nb = nblk;
             if (!impulse && chain_pass_ok(C, DISK_CLAMP)) {

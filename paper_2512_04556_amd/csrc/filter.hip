@@ -777,6 +777,81 @@ __device__ __forceinline__ void corr_tile_taps(float (&s)[kCorrTaps][4], const f
     }
 }
 
+// Staged transposed gather fused with the tap correlations (modes 5 and 6).
+// The tile holds G (zero outside the image).  For tap i with d = floor(-o_i)
+// and the forward's corner weights c_ab, the exact ZERO transpose is
+// G'(q) = sum_i sum_ab c_ab G(q - d - ab), and the same four values give the
+// part of S_ab(i) = sum_p G(p) X(p + d + ab) whose samples stay in the image:
+// with q = p + d + ab it is sum_q X(q) G(q - d - ab) (X at the lane's pixels,
+// zero outside the image).  All N taps enter G', the first NS <= kCorrTaps
+// taps the sums.
+template <int C, int PY, int ROWB>
+__device__ __forceinline__ void fused_tile_taps(float (&s)[kCorrTaps][4], float (&acc)[PY][C],
+                                                const float (&xq)[PY][C], int base0, int tabL, int N, int NS) {
+    float basef[PY];
+#pragma unroll
+    for (int j = 0; j < PY; ++j) {
+        basef[j] = static_cast<float>(base0 + j * 4 * ROWB);
+#pragma unroll
+        for (int c = 0; c < C; ++c) acc[j][c] = 0.0f;
+    }
+    // tap i: its weights, then for each of the lane's pixels the four G corners
+    // (corner (1, 1) = q - d - (1, 1); (0, 1) one pixel right, (1, 0) one row
+    // down), G' accumulated; `sum(j, q00, q01, q10, q11)` takes the corners
+    auto tap = [&](int i, auto&& sum) {
+        const v4f a = lds_ld4(tabL + i * kRowLB);
+        const v2f b = lds_ld2(tabL + i * kRowLB + 16);
+        const float flx = floorf(a.x), fly = floorf(a.z);
+        const float fx = a.x - flx, fy = a.z - fly, w = b.x;
+        const float wy1 = w * fy, wy0 = w - wy1;
+        const float c01 = wy0 * fx, c00 = wy0 - c01;
+        const float c11 = wy1 * fx, c10 = wy1 - c11;
+#pragma unroll
+        for (int j = 0; j < PY; ++j) {
+            const int a0 =
+                static_cast<int>(fmaf(-1.0f - flx, 16.0f, fmaf(-1.0f - fly, static_cast<float>(ROWB), basef[j])));
+            const v4f g11 = lds_ld4(a0), g10 = lds_ld4(a0 + 16), g01 = lds_ld4(a0 + ROWB),
+                      g00 = lds_ld4(a0 + ROWB + 16);
+            const float q00[4] = {g00.x, g00.y, g00.z, g00.w}, q01[4] = {g01.x, g01.y, g01.z, g01.w};
+            const float q10[4] = {g10.x, g10.y, g10.z, g10.w}, q11[4] = {g11.x, g11.y, g11.z, g11.w};
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                float v = acc[j][c];
+                v = fmaf(c00, q00[c], v);
+                v = fmaf(c01, q01[c], v);
+                v = fmaf(c10, q10[c], v);
+                v = fmaf(c11, q11[c], v);
+                acc[j][c] = v;
+            }
+            sum(j, q00, q01, q10, q11);
+        }
+    };
+    // the first kCorrTaps taps: sums of the first NS in registers (the loop is
+    // unrolled, so the sums' indices are fixed)
+#pragma unroll
+    for (int i = 0; i < kCorrTaps; ++i) {
+        if (i < N) {
+            const bool sums = i < NS;
+            tap(i, [&](int j, const float (&q00)[4], const float (&q01)[4], const float (&q10)[4],
+                       const float (&q11)[4]) {
+                if (sums) {
+                    float t0 = s[i][0], t1 = s[i][1], t2 = s[i][2], t3 = s[i][3];
+#pragma unroll
+                    for (int c = 0; c < C; ++c) {
+                        t0 = fmaf(xq[j][c], q00[c], t0);
+                        t1 = fmaf(xq[j][c], q01[c], t1);
+                        t2 = fmaf(xq[j][c], q10[c], t2);
+                        t3 = fmaf(xq[j][c], q11[c], t3);
+                    }
+                    s[i][0] = t0, s[i][1] = t1, s[i][2] = t2, s[i][3] = t3;
+                }
+            });
+        }
+    }
+    for (int i = kCorrTaps; i < N; ++i)
+        tap(i, [](int, const float (&)[4], const float (&)[4], const float (&)[4], const float (&)[4]) {});
+}
+
 // ROWB > 0 (C >= 3): the staged row stride in bytes, fixed at compile time
 // (rowW is then ROWB / 4).  TL (1-D bases): the layer's coefficient rows are
 // staged in LDS after the tile, at byte offset SY * rowB.
@@ -787,7 +862,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4, 4)))
     const TIn* __restrict__ X, TOut* __restrict__ Y, const float* __restrict__ P,
     const float* __restrict__ table, int tap0, int N, int T, int G0, int G1, int H, int W, int halo,
     int tiles_x, int per, int ntiles, const int* __restrict__ flag, int rowW, const float* __restrict__ raw,
-    int pN, int pofs) {
+    int pN, int pofs, float* __restrict__ part) {
     extern __shared__ float lds[];
     if (ROWB > 0) rowW = ROWB / 4;
     constexpr int PY = kPipePY;
@@ -800,7 +875,11 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4, 4)))
     // layer input, P = G (its output gradient), Y = the partial sums
     // [grid][pN][4]; taps tap0 .. tap0 + N - 1 (N <= kCorrTaps) are entries
     // pofs .. pofs + N - 1 of the layer.
-    constexpr bool corr = MODE >= 3;
+    // MODE 5, 6: the transpose of a chain layer (G' into Y; X = G, P = the
+    // layer input) fused with the in-image part of its tap correlations (for
+    // the first min(N, kCorrTaps) taps, into part [grid][pN][4]); the forward
+    // boundary is CLAMP (5) or ZERO (6): it only matters in the fallback.
+    constexpr bool corr = MODE >= 3, fused = MODE >= 5;
     float s[kCorrTaps][4];
     if constexpr (corr) {
 #pragma unroll
@@ -811,7 +890,10 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4, 4)))
     auto corr_finish = [&]() {
         if constexpr (corr) {
             __syncthreads();   // the LDS is free again
-            corr_block_reduce<NW>(s, N, lds, reinterpret_cast<float*>(Y), pN, pofs);
+            if constexpr (fused)
+                corr_block_reduce<NW>(s, min(N, kCorrTaps), lds, part, pN, pofs);
+            else
+                corr_block_reduce<NW>(s, N, lds, reinterpret_cast<float*>(Y), pN, pofs);
         }
     };
     if (tile >= tend) {
@@ -827,7 +909,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4, 4)))
     // outside the image (the input adjoint away from CLAMP-border pixels).  The
     // halo comes from the layer's own taps (every wave reads the N <= 32 taps):
     // ceil(max |offset|) + 1; beyond HMAX the tiles take the global path.
-    constexpr bool chain = MODE != 0, trans = MODE == 2, zstage = MODE == 2 || MODE == 4;
+    constexpr bool chain = MODE != 0, trans = MODE == 2, zstage = MODE == 2 || MODE == 4 || MODE >= 5;
     if constexpr (TL && chain) {
         float m = 0.0f;
         if (lane < N) {
@@ -837,7 +919,17 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4, 4)))
         }
         halo = uniform(static_cast<int>(ceilf(wave_max(m))) + 1);
         if (halo > HMAX) {
-            if constexpr (corr) {
+            if constexpr (fused) {
+                // the transpose as mode 2 does, the correlations (in-image and
+                // border samples alike) as mode 3 or 4 does
+                chain_tiles_global<C, TIn, TOut, PY, TH>(X, Y, raw, tap0, N, H, W, tile, tend, nwg, tiles_x, lx,
+                                                         lyb, true);
+                corr_tiles_global<C, TIn, PY, TH, MODE == 6>(reinterpret_cast<const TIn*>(P),
+                                                             reinterpret_cast<const float*>(X), raw, tap0,
+                                                             min(N, kCorrTaps), H, W, tile, tend, nwg, tiles_x,
+                                                             lx, lyb, s);
+                corr_finish();
+            } else if constexpr (corr) {
                 corr_tiles_global<C, TIn, PY, TH, zstage>(X, P, raw, tap0, N, H, W, tile, tend, nwg, tiles_x, lx, lyb,
                                                           s);
                 corr_finish();
@@ -1006,7 +1098,20 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4, 4)))
         __syncthreads();
         const int x = (tile % tiles_x) * kTW + lx, y0 = (tile / tiles_x) * TH + lyb;
         const int next = tile + nwg;
-        if constexpr (corr) {
+        if constexpr (fused) {
+            float xq[PY][C];
+#pragma unroll
+            for (int j = 0; j < PY; ++j)
+#pragma unroll
+                for (int c = 0; c < C; ++c) {
+                    xq[j][c] = gv[j][c];
+                    asm volatile("" ::"v"(xq[j][c]));   // this tile's X ahead of the prefetch
+                }
+            if (next < tend) issue(next);
+            float acc[PY][C];
+            fused_tile_taps<C, PY, ROWB>(s, acc, xq, base0, tabL, N, min(N, kCorrTaps));
+            sv_store<C, TOut, PY>(Y, plane, W, H, x, y0, acc);
+        } else if constexpr (corr) {
             float gc[PY][C];
 #pragma unroll
             for (int j = 0; j < PY; ++j)
@@ -1174,7 +1279,8 @@ static size_t pipe_lds_bytes(int halo, int G0, int N) {
 template <int C, int DIMS, typename TIn, typename TOut, int NW, int HMAX, int ROWB, bool TL, int MODE = 0>
 static hipError_t launch_pipe(const void* src, void* dst, const float* pmap, const float* table, int tap0, int N,
                               int T, int G0, int G1, int H, int W, int halo, const int* flag, const float* raw,
-                              hipStream_t s, int pN = 0, int pofs = 0, int* grid_out = nullptr) {
+                              hipStream_t s, int pN = 0, int pofs = 0, int* grid_out = nullptr,
+                              float* part = nullptr, int grid = 0) {
     constexpr int TH = PipeShape<NW, HMAX>::TH;
     const int tiles_x = (W + kTW - 1) / kTW, tiles_y = (H + TH - 1) / TH;
     const int ntiles = tiles_x * tiles_y;
@@ -1209,9 +1315,10 @@ static hipError_t launch_pipe(const void* src, void* dst, const float* pmap, con
     }
     int per_xcd = (cu_count() * occ) / 8;                 // work-groups per XCD
     per_xcd = std::max(1, std::min(per_xcd, per));
+    if (grid > 0) per_xcd = grid / 8;                     // a given grid (a multiple of 8): partials laid out alike
     hipLaunchKernelGGL(fn, dim3(8 * per_xcd), dim3(64 * NW), lds, s, static_cast<const TIn*>(src),
                        static_cast<TOut*>(dst), pmap, table, tap0, N, T, G0, G1, H, W, halo, tiles_x, per, ntiles,
-                       flag, rowW, raw, pN, pofs);
+                       flag, rowW, raw, pN, pofs, part);
     if (grid_out) *grid_out = 8 * per_xcd;
     return hipGetLastError();
 }
@@ -1328,29 +1435,124 @@ hipError_t launch_chain_transpose(int C, const float* G, float* Gprev, const flo
     return hipErrorInvalidValue;
 }
 // Tap correlations of one chain layer (C = 3, 4) into partial[grid][N][4]
-// (N taps, chunks of kCorrTaps per launch); *nblk = the grid (rows of partial).
+// (taps first .. N - 1, chunks of kCorrTaps per launch); *nblk = the grid
+// (rows of partial), or `grid` when given.
 template <int C, typename TIn, int MODE>
 static hipError_t corr_typed(const void* X, const float* G, const float* theta, int tap0, int N, int T, int H, int W,
-                             float* partial, int* nblk, hipStream_t s) {
-    for (int c0 = 0; c0 < N; c0 += kCorrTaps) {
+                             float* partial, int* nblk, hipStream_t s, int first, int grid) {
+    for (int c0 = first; c0 < N; c0 += kCorrTaps) {
         const hipError_t e = launch_pipe<C, 1, TIn, float, 16, kPipeHalo, kPipeRowB, true, MODE>(
             X, partial, G, nullptr, tap0 + c0, std::min(kCorrTaps, N - c0), T, 1, 1, H, W, 0, nullptr, theta, s, N,
-            c0, nblk);
+            c0, nblk, nullptr, grid);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
 }
 template <int C>
 static hipError_t corr_c(int zero, const float* X, const float* G, const float* theta, int tap0, int N, int T, int H,
-                         int W, float* partial, int* nblk, hipStream_t s) {
-    if (zero) return corr_typed<C, float, 4>(X, G, theta, tap0, N, T, H, W, partial, nblk, s);
-    return corr_typed<C, float, 3>(X, G, theta, tap0, N, T, H, W, partial, nblk, s);
+                         int W, float* partial, int* nblk, hipStream_t s, int first, int grid) {
+    if (zero) return corr_typed<C, float, 4>(X, G, theta, tap0, N, T, H, W, partial, nblk, s, first, grid);
+    return corr_typed<C, float, 3>(X, G, theta, tap0, N, T, H, W, partial, nblk, s, first, grid);
 }
 hipError_t launch_adjoint_corr(int C, int boundary, const float* X, const float* G, const float* theta, int tap0,
                                int N, int T, int H, int W, float* partial, int* nblk, hipStream_t s) {
     const int zero = boundary == DISK_ZERO;
-    if (C == 3) return corr_c<3>(zero, X, G, theta, tap0, N, T, H, W, partial, nblk, s);
-    if (C == 4) return corr_c<4>(zero, X, G, theta, tap0, N, T, H, W, partial, nblk, s);
+    if (C == 3) return corr_c<3>(zero, X, G, theta, tap0, N, T, H, W, partial, nblk, s, 0, 0);
+    if (C == 4) return corr_c<4>(zero, X, G, theta, tap0, N, T, H, W, partial, nblk, s, 0, 0);
+    return hipErrorInvalidValue;
+}
+
+// The CLAMP samples the fused pass leaves out: for tap i < NS and corner ab,
+// sum over the pixels p whose sample p + d + ab (d = floor(-o_i)) leaves the
+// image of G(p) X(clamp(p + d + ab)), over the channels.  The pixels (the
+// rows whose sample row leaves the image, whole, then the sample columns that
+// leave it in the other rows) are split into gridDim.y parts; work-group
+// (tap, corner) x part writes rows[part][4 i + ab] (rows of N * 4 floats):
+// zero for i >= NS, and for every tap when the layer's halo (computed as the
+// fused kernel does) exceeds hmax, since that kernel's fallback then reads
+// those samples itself.  Fixed-order sums.
+template <int C>
+__global__ __launch_bounds__(256) void corr_border_kernel(const float* __restrict__ G, const float* __restrict__ X,
+                                                          const float* __restrict__ theta, int N, int NS, int H,
+                                                          int W, int hmax, float* __restrict__ rows) {
+    __shared__ float red[256];
+    const int i = blockIdx.x >> 2, ab = blockIdx.x & 3, t = threadIdx.x;
+    const int part = blockIdx.y, nparts = gridDim.y;
+    float* row = rows + static_cast<size_t>(part) * N * 4;
+    float m = 0.0f;
+    for (int k = 0; k < N; ++k) {
+        float mk = fmaxf(fabsf(theta[3 * k]), fabsf(theta[3 * k + 1]));
+        if (!(mk <= 1.0e6f)) mk = 1.0e6f;   // non-finite or huge
+        m = fmaxf(m, mk);
+    }
+    const int halo = static_cast<int>(ceilf(m)) + 1;
+    float v = 0.0f;
+    if (i < NS && halo <= hmax) {
+        const int dx = static_cast<int>(floorf(-theta[3 * i])) + (ab & 1);
+        const int dy = static_cast<int>(floorf(-theta[3 * i + 1])) + (ab >> 1);
+        const int rlo = dy < 0 ? min(-dy, H) : 0, rhi = dy > 0 ? min(dy, H - rlo) : 0;
+        const int clo = dx < 0 ? min(-dx, W) : 0, chi = dx > 0 ? min(dx, W - clo) : 0;
+        const int ncol = clo + chi, nin = H - rlo - rhi;
+        const long n1 = static_cast<long>(rlo + rhi) * W, n = n1 + static_cast<long>(nin) * ncol;
+        const size_t plane = static_cast<size_t>(H) * W;
+        const long u0 = n * part / nparts, u1 = n * (part + 1) / nparts;
+        for (long u = u0 + t; u < u1; u += 256) {
+            int x, y;
+            if (u < n1) {
+                const int r = static_cast<int>(u / W);
+                x = static_cast<int>(u - static_cast<long>(r) * W);
+                y = r < rlo ? r : H - rhi + (r - rlo);
+            } else {
+                const long w = u - n1;
+                const int r = static_cast<int>(w / ncol), k = static_cast<int>(w - static_cast<long>(r) * ncol);
+                y = rlo + r;
+                x = k < clo ? k : W - chi + (k - clo);
+            }
+            const int sx = min(max(x + dx, 0), W - 1), sy = min(max(y + dy, 0), H - 1);
+            const size_t pg = static_cast<size_t>(y) * W + x, px = static_cast<size_t>(sy) * W + sx;
+#pragma unroll
+            for (int c = 0; c < C; ++c) v = fmaf(G[c * plane + pg], X[c * plane + px], v);
+        }
+    }
+    red[t] = v;
+    __syncthreads();
+    for (int h = 128; h >= 1; h >>= 1) {
+        if (t < h) red[t] += red[t + h];
+        __syncthreads();
+    }
+    if (t == 0) row[4 * i + ab] = red[0];
+}
+
+template <int C>
+static hipError_t fused_c(int zero, const float* G, const float* X, float* Gn, const float* theta, int tap0, int N,
+                          int T, int H, int W, float* partial, int* nrows, hipStream_t s) {
+    int nb = 0;
+    hipError_t e = zero ? launch_pipe<C, 1, float, float, 16, kPipeHalo, kPipeRowB, true, 6>(
+                              G, Gn, X, nullptr, tap0, N, T, 1, 1, H, W, 0, nullptr, theta, s, N, 0, &nb, partial)
+                        : launch_pipe<C, 1, float, float, 16, kPipeHalo, kPipeRowB, true, 5>(
+                              G, Gn, X, nullptr, tap0, N, T, 1, 1, H, W, 0, nullptr, theta, s, N, 0, &nb, partial);
+    if (e != hipSuccess) return e;
+    if (N > kCorrTaps) {   // the other taps' correlations, on the same grid (rows of partial)
+        int nb2 = 0;
+        e = corr_c<C>(zero, X, G, theta, tap0, N, T, H, W, partial, &nb2, s, kCorrTaps, nb);
+        if (e != hipSuccess) return e;
+    }
+    *nrows = nb;
+    if (!zero) {
+        // up to 16 rows after the grid's (the partial buffer holds at least
+        // adjoint_tap_blocks(H, W) + 1 rows of the layer's widest N)
+        const int parts = std::max(1, std::min(16, adjoint_tap_blocks(H, W) + 1 - nb));
+        hipLaunchKernelGGL(corr_border_kernel<C>, dim3(4 * N, parts), dim3(256), 0, s, G, X, theta + 3 * tap0, N,
+                           std::min(N, kCorrTaps), H, W, kPipeHalo, partial + static_cast<size_t>(nb) * N * 4);
+        *nrows = nb + parts;
+    }
+    return hipGetLastError();
+}
+hipError_t launch_chain_fused(int C, int boundary, const float* G, const float* X, float* Gn, const float* theta,
+                              int tap0, int N, int T, int H, int W, float* partial, int* nrows, hipStream_t s) {
+    const int zero = boundary == DISK_ZERO;
+    if (C == 3) return fused_c<3>(zero, G, X, Gn, theta, tap0, N, T, H, W, partial, nrows, s);
+    if (C == 4) return fused_c<4>(zero, G, X, Gn, theta, tap0, N, T, H, W, partial, nrows, s);
     return hipErrorInvalidValue;
 }
 

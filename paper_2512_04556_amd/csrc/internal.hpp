@@ -91,6 +91,14 @@ hipError_t launch_adjoint_input_border(int C, const float* G, const TapU* taps, 
 // gradient (both FP32).
 hipError_t launch_adjoint_corr(int C, int boundary, const float* X, const float* G, const float* theta, int tap0,
                                int N, int T, int H, int W, float* partial, int* nblk, hipStream_t s);
+// The transpose of a chain layer (C = 3, 4; ZERO or CLAMP forward) fused with
+// its tap correlations: G' into Gn and the correlation partials into
+// partial[*nrows][N][4] (the in-image part of the first taps from the fused
+// pass, the other taps from correlation passes on the same grid, and for
+// CLAMP one last row with the samples that leave the image).  CLAMP border
+// pixels of Gn still need launch_adjoint_input_border.
+hipError_t launch_chain_fused(int C, int boundary, const float* G, const float* X, float* Gn, const float* theta,
+                              int tap0, int N, int T, int H, int W, float* partial, int* nrows, hipStream_t s);
 hipError_t launch_chain_pass(int C, int src_bf16, const void* src, int dst_bf16, void* dst, const float* theta,
                              int tap0, int N, int T, int H, int W, hipStream_t s);
 
