@@ -325,8 +325,9 @@ def gradient_chain(torch, disk, steps=20):
     autograd): 1920 x 1080 x 3 FP32, uniform 4 x 8 taps (offsets up to ~12 px),
     CLAMP; forward with saved intermediates, then the gradients of Theta and
     of the input.  Algorithmic HBM bytes per pixel and layer: forward 12 in +
-    12 out; adjoint 12 (X_{l-1}) + 12 (G_l) for the tap sums and 12 + 12 for
-    G_{l-1}."""
+    12 out; adjoint 12 (X_{l-1}) + 12 (G_l) in and 12 (G_{l-1}) out: the
+    least any implementation moves (the tap sums and G_{l-1} read the same
+    G_l, and one pass takes both)."""
     from synth import random_theta, noise_image
     taps = [8, 8, 8, 8]
     th = torch.as_tensor(random_theta(taps, 6.0, seed=21).astype(np.float32)).cuda()
@@ -351,7 +352,7 @@ def gradient_chain(torch, disk, steps=20):
     torch.cuda.synchronize()
     bw = e0.elapsed_time(e1) / steps
     px, L = H * W, len(taps)
-    fb, bb = L * 24 * px, L * 48 * px
+    fb, bb = L * 24 * px, L * 36 * px
     return {"workload": "chain_1080p_f32_4x8_clamp", "forward_ms": round(fw, 4), "backward_ms": round(bw, 4),
             "forward_gbs": round(fb / (fw * 1e-3) / 1e9, 1), "backward_gbs": round(bb / (bw * 1e-3) / 1e9, 1),
             "backward_hbm_frac": round(bb / (bw * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
