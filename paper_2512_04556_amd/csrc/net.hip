@@ -122,6 +122,49 @@ struct LdIm2colT : Im2col {  // Op(j, m) = im2col(m, j): rows j..j+7 at reductio
     __device__ uint4 fetch(int r, int k) const { return fetch8(k, r); }
 };
 
+// Input gradient of a 3 x 3 / stride 2 / padding 1 convolution by parity
+// class: input pixel (iy, ix) = (2 j + py, 2 i + px) receives from the taps
+// with iy + 1 - ky even, i.e. ky = 1 (py = 0) or ky = 0, 2 (py = 1), from
+// output row oy = (iy + 1 - ky) / 2 (likewise x).  Per class (py, px) the
+// gradient is a GEMM with rows m = (b, j, i) over B * Ho * Ho pixels, columns
+// ci, and reduction index k = t * Cout + co over the class's (1 + py)(1 + px)
+// taps t (ty = t / nx, tx = t % nx, nx = 1 + px).
+struct SubpixTap {
+    int py, px, lgHo, lgCo, Ho, Co;
+    __device__ __forceinline__ void tap(int t, int& ky, int& kx) const {
+        const int ty = px ? t >> 1 : t, tx = px ? t & 1 : 0;
+        ky = py ? 2 * ty : 1;
+        kx = px ? 2 * tx : 1;
+    }
+};
+struct LdSubpixG : SubpixTap {   // Op(m, k) = g(b, oy, ox, co): 8 consecutive co
+    const uint16_t* g;           // output gradient, NHWC [B][Ho][Ho][Co]
+    int M, K;
+    static constexpr bool kContig = true;
+    __device__ void limit(int ke) { K = min(K, ke); }
+    __device__ uint4 fetch(int m, int k) const {
+        const int b = m >> (2 * lgHo), j = (m >> lgHo) & (Ho - 1), i = m & (Ho - 1);
+        const int t = k >> lgCo, co = k & (Co - 1);
+        int ky, kx;
+        tap(t, ky, kx);
+        const int oy = (2 * j + py + 1 - ky) >> 1, ox = (2 * i + px + 1 - kx) >> 1;
+        return load8_or_zero(g, ((static_cast<size_t>(b) * Ho + oy) * Ho + ox) * Co + co,
+                             m < M && k < K && oy < Ho && ox < Ho);
+    }
+};
+struct LdSubpixW : SubpixTap {   // Op(ci, k) = W(co, ky, kx, ci): rows ci..ci+7 at k
+    const uint16_t* wp;          // packed weights [Co][Kp], k = (ky 3 + kx) Cin + ci
+    int Kp, Cin, K;
+    static constexpr bool kContig = false;
+    __device__ void limit(int ke) { K = min(K, ke); }
+    __device__ uint4 fetch(int ci, int k) const {
+        const int t = k >> lgCo, co = k & (Co - 1);
+        int ky, kx;
+        tap(t, ky, kx);
+        return load8_or_zero(wp, static_cast<size_t>(co) * Kp + (ky * 3 + kx) * Cin + ci, ci < Cin && k < K);
+    }
+};
+
 template <class LD>
 __device__ __forceinline__ uint4 tile_fetch(const LD& ld, int row0, int k0, int t) {
     if constexpr (LD::kContig)
@@ -188,6 +231,21 @@ struct EpMaskGrad {  // FC input gradient: g = acc * [x > 0], kept in FP32 and B
         const float g = (x[i] & 0x7fffu) != 0 && !(x[i] & 0x8000u) ? acc : 0.0f;
         g32[i] = g;
         gq[i] = f32_to_bf16(g);
+    }
+};
+
+struct EpSubpix {   // conv input gradient of one parity class: g = acc * [x > 0] at (b, 2j+py, 2i+px, ci)
+    float* g32;
+    uint16_t* gq;
+    const uint16_t* x;   // the layer input, NHWC [B][Hin][Hin][Cin]
+    int py, px, lgHo, Ho, Cin;
+    static constexpr bool kStaged = false;
+    __device__ void put(int m, int ci, float acc, int) const {
+        const int b = m >> (2 * lgHo), j = (m >> lgHo) & (Ho - 1), i = m & (Ho - 1);
+        const size_t idx = ((static_cast<size_t>(b) * 2 * Ho + 2 * j + py) * 2 * Ho + 2 * i + px) * Cin + ci;
+        const float g = (x[idx] & 0x7fffu) != 0 && !(x[idx] & 0x8000u) ? acc : 0.0f;
+        g32[idx] = g;
+        gq[idx] = f32_to_bf16(g);
     }
 };
 
@@ -556,40 +614,6 @@ __global__ __launch_bounds__(256) void wgrad_reduce_kernel(Layer L, const float*
     }
 }
 
-// Conv input gradient: transpose of im2col over dcol [M][Kp], times [x > 0].
-__global__ __launch_bounds__(256) void col2im_kernel(Layer L, int B, const float* __restrict__ dcol,
-                                                     const uint16_t* __restrict__ x, float* __restrict__ g32,
-                                                     uint16_t* __restrict__ gq) {
-    const long n = static_cast<long>(B) * L.hin * L.hin * L.cin;
-    for (long i = blockIdx.x * 256L + threadIdx.x; i < n; i += static_cast<long>(gridDim.x) * 256) {
-        const int ci = static_cast<int>(i % L.cin);
-        const long p = i / L.cin;
-        const int ix = static_cast<int>(p % L.hin);
-        const long q = p / L.hin;
-        const int iy = static_cast<int>(q % L.hin);
-        const int b = static_cast<int>(q / L.hin);
-        float s = 0.0f;
-        for (int ky = 0; ky < 3; ++ky) {
-            const int ty = iy + 1 - ky;
-            if (ty < 0 || (ty & 1)) continue;
-            const int oy = ty >> 1;
-            if (oy >= L.hout) continue;
-            for (int kx = 0; kx < 3; ++kx) {
-                const int tx = ix + 1 - kx;
-                if (tx < 0 || (tx & 1)) continue;
-                const int ox = tx >> 1;
-                if (ox >= L.hout) continue;
-                const long m = (static_cast<long>(b) * L.hout + oy) * L.hout + ox;
-                s += dcol[m * L.Kp + (ky * 3 + kx) * L.cin + ci];
-            }
-        }
-        const uint16_t xv = x[i];
-        const float g = ((xv & 0x7fffu) != 0 && !(xv & 0x8000u)) ? s : 0.0f;
-        g32[i] = g;
-        gq[i] = f32_to_bf16(g);
-    }
-}
-
 __global__ __launch_bounds__(256) void adam_kernel(long n, float* __restrict__ p, float* __restrict__ m,
                                                    float* __restrict__ v, const float* __restrict__ g, float lr,
                                                    float bc1, float bc2) {
@@ -698,12 +722,11 @@ NetWs net_ws_layout(int B, bool train) {
         return w;
     }
     // gradient buffers: the largest layer output (layer 1: 32 x 32 x 32 per sample)
-    size_t gmax = 0, dcol = 0, part = 0, cpart = 0;
+    size_t gmax = 0, part = 0, cpart = 0;
     for (int i = 0; i < 8; ++i) {
         const Layer& L = T.l[i];
         const size_t M = static_cast<size_t>(B) * L.hout * L.hout;
         gmax = std::max(gmax, M * L.cout);
-        if (i > 0 && L.conv) dcol = std::max(dcol, M * L.Kp);
         int S, kc;
         net_wgrad_splits(L.cout, L.Kp, static_cast<int>(M), &S, &kc);
         part = std::max(part, static_cast<size_t>(S) * L.cout * L.Kp);
@@ -713,7 +736,6 @@ NetWs net_ws_layout(int B, bool train) {
     w.g32[1] = take(gmax * 4);
     w.gq[0] = take(gmax * 2);
     w.gq[1] = take(gmax * 2);
-    w.dcol = take(dcol * 4);
     w.part = take(part * 4);
     w.cpart = take(cpart * 4);
     w.grad = take(T.params * 4);
@@ -784,7 +806,6 @@ hipError_t net_backward(const float* params, const uint16_t* x0, const float* re
     const float* yhat = reinterpret_cast<const float*>(ws + w.yhat);
     float* g32[2] = {reinterpret_cast<float*>(ws + w.g32[0]), reinterpret_cast<float*>(ws + w.g32[1])};
     uint16_t* gq[2] = {reinterpret_cast<uint16_t*>(ws + w.gq[0]), reinterpret_cast<uint16_t*>(ws + w.gq[1])};
-    float* dcol = reinterpret_cast<float*>(ws + w.dcol);
     float* part = reinterpret_cast<float*>(ws + w.part);
     float* cpart = reinterpret_cast<float*>(ws + w.cpart);
     {
@@ -829,11 +850,22 @@ hipError_t net_backward(const float* params, const uint16_t* x0, const float* re
         LdRow gr{gq[cur], L.cout, M, L.cout};
         LdCol wc{wp + L.wp_off, L.Kp, L.Kp, L.cout};
         if (L.conv) {
-            EpStore dc{dcol, L.Kp, 0};
-            e = gemm(gr, wc, dc, M, L.Kp, L.cout, 1, L.cout, s);
-            if (e != hipSuccess) return e;
-            const long n = static_cast<long>(B) * L.hin * L.hin * L.cin;
-            hipLaunchKernelGGL(col2im_kernel, dim3(grid_for(n)), dim3(256), 0, s, L, B, dcol, xin, g32[nxt], gq[nxt]);
+            // four parity classes of input pixels, each a GEMM over its taps
+            const int lgHo = lg2(L.hout), lgCo = lg2(L.cout);
+            for (int py = 0; py < 2; ++py)
+                for (int px = 0; px < 2; ++px) {
+                    const SubpixTap st{py, px, lgHo, lgCo, L.hout, L.cout};
+                    const int Kc = (1 + py) * (1 + px) * L.cout;
+                    LdSubpixG a;
+                    static_cast<SubpixTap&>(a) = st;
+                    a.g = gq[cur]; a.M = M; a.K = Kc;
+                    LdSubpixW wb;
+                    static_cast<SubpixTap&>(wb) = st;
+                    wb.wp = wp + L.wp_off; wb.Kp = L.Kp; wb.Cin = L.cin; wb.K = Kc;
+                    EpSubpix ep{g32[nxt], gq[nxt], xin, py, px, lgHo, L.hout, L.cin};
+                    e = gemm(a, wb, ep, M, L.cin, Kc, 1, Kc, s);
+                    if (e != hipSuccess) return e;
+                }
         } else {
             EpMaskGrad ep{g32[nxt], gq[nxt], xin, L.K};
             e = gemm(gr, wc, ep, M, L.K, L.cout, 1, L.cout, s);
