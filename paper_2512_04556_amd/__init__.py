@@ -198,9 +198,27 @@ def disk_backward(theta, taps, inp, saved, grad_out, *, boundary=CLAMP, need_the
     """Adjoint.  Returns (grad_theta [T][3] or None, grad_in [C][H][W] or None)."""
     _dev(theta, "theta")
     _dev(grad_out, "grad_out")
+    _dev(inp, "inp")
+    _dev(saved, "saved")
+    # the C entry point reads every one of these as float*
+    _f32(theta, "theta")
+    _f32(grad_out, "grad_out")
+    _f32(inp, "inp")
+    _f32(saved, "saved")
     dev = theta.device
     cx = _complex(taps)
-    C, H, W = grad_out.shape
+    if grad_out.dim() != 3:
+        raise DiskError(f"grad_out must be [C][H][W] (got shape {tuple(grad_out.shape)})")
+    C, H, W = (int(v) for v in grad_out.shape)
+    T = sum(int(t) for t in taps)
+    if tuple(theta.shape) != (T, 3):
+        raise DiskError(f"theta must be [{T}][3] (got {tuple(theta.shape)})")
+    if inp is not None and tuple(inp.shape) != (C, H, W):
+        raise DiskError(f"inp shape {tuple(inp.shape)} differs from grad_out shape {(C, H, W)}")
+    if cx.L > 1:
+        if saved is None or saved.dim() != 4 or tuple(saved.shape[1:]) != (C, H, W) or saved.shape[0] < cx.L - 1:
+            raise DiskError(f"saved must be [{cx.L - 1}][{C}][{H}][{W}] "
+                            f"(got {None if saved is None else tuple(saved.shape)})")
     if inp is None:
         boundary = ZERO
     gt = torch.empty_like(theta) if need_theta else None
@@ -513,9 +531,13 @@ def disk_net_prepare_inputs(batch: Batch):
 
 
 def disk_net_scatter_theta(batch: Batch, theta48, theta=None):
-    dev = batch.desc.device
+    """Write the network's [B][48][3] prediction into the batch's Theta for
+    the targets of 4 layers x 12 taps.  The call leaves every other target's
+    rows as they are, so when ``theta`` is None they start from the radial
+    initialisation (Eq. 6), the fallback for targets the network does not
+    cover."""
     if theta is None:
-        theta = torch.empty((batch.T_total, 3), dtype=torch.float32, device=dev)
+        theta = disk_init_radial(batch)
     _check(lib().disk_net_scatter_theta(ctypes.byref(batch.meta), _ptr(batch.desc), _ptr(batch.taps), _ptr(theta48),
                                         _ptr(theta), _stream()))
     return theta

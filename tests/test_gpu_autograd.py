@@ -88,3 +88,42 @@ def test_image_autograd_gradients(dev):
     ei = np.abs(x.grad.cpu().numpy() - wi).max() / np.abs(wi).max()
     print(f"image autograd: dtheta {et:.2e} dinput {ei:.2e}")
     assert et <= 1e-4 and ei <= 1e-5
+
+
+def test_image_autograd_bf16_input(dev):
+    """A BF16 image: the forward reads BF16 and writes BF16; the adjoint reads
+    the image widened to FP32 (exact), so dTheta and dX equal the oracle's on
+    the BF16-rounded image; dX comes back in BF16."""
+    from tests.gpu_util import bf16_round, rel_err, TOL_F32
+    taps = [6, 5, 4]
+    th = random_theta(taps, 3.0, seed=14)
+    img = uniform_image(37, 70, 3, seed=8)
+    G = np.random.default_rng(6).standard_normal((3, 37, 70)).astype(np.float32)
+    theta = torch.as_tensor(th).cuda().requires_grad_(True)
+    x = torch.as_tensor(img).cuda().bfloat16().requires_grad_(True)
+    say("autograd image bf16")
+    y = DiskChain.apply(theta, x, taps, disk.CLAMP)
+    assert y.dtype == torch.bfloat16
+    (y.float() * torch.as_tensor(G).cuda()).sum().backward()
+    assert x.grad.dtype == torch.bfloat16
+    wt, wi = A.chain_vjp(bf16_round(img), th.astype(np.float64), taps, 1, G.astype(np.float64))
+    et = rel_err(theta.grad.cpu().numpy(), wt)
+    ei = rel_err(x.grad.float().cpu().numpy(), bf16_round(wi))
+    print(f"image autograd bf16: dtheta {et:.2e} dinput (BF16 output) {ei:.2e}")
+    assert et <= TOL_F32 and ei <= 5e-3
+
+
+def test_backward_refuses_non_fp32_operands(dev):
+    """The C adjoint reads the input, the saved intermediates, the output
+    gradient and Theta as FP32: the binding refuses anything else before a
+    launch."""
+    taps = [4, 4]
+    th = torch.as_tensor(random_theta(taps, 2.0, seed=3)).cuda()
+    x = torch.as_tensor(uniform_image(16, 16, 3, seed=1)).cuda()
+    out, saved = disk.disk_forward(th, taps, x, save=True)
+    g = torch.ones_like(out)
+    for args in ((th, taps, x.bfloat16(), saved, g), (th, taps, x, saved.bfloat16(), g),
+                 (th, taps, x, saved, g.bfloat16()), (th.double(), taps, x, saved, g),
+                 (th, taps, x[:, :8], saved, g), (th, taps, x, saved[:, :, :8], g)):
+        with pytest.raises(disk.DiskError):
+            disk.disk_backward(*args)

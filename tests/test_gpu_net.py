@@ -247,3 +247,26 @@ def test_scatter_theta(dev):
     for b in range(6):
         o = int(desc[b, 3])
         np.testing.assert_array_equal(got[o:o + 48], th48[b].cpu().numpy())
+
+
+def test_scatter_theta_falls_back_to_radial_for_other_structures(dev):
+    """Without a Theta to write into, the prediction lands on the 4 x 12
+    targets and every other target keeps the radial initialisation (Eq. 6)."""
+    batch = mixed_batch(40, seed=29, side=(15, 63))
+    desc, taps, tg = pack_targets(batch)
+    bt = disk.make_batch(desc, taps, tg)
+    th48 = torch.arange(40 * 144, dtype=torch.float32, device="cuda").view(40, 48, 3)
+    say("net scatter fallback", 40)
+    got = disk.disk_net_scatter_theta(bt, th48).cpu().numpy()
+    radial = disk.disk_init_radial(bt).cpu().numpy()
+    n44 = 0
+    for b in range(40):
+        o, L = int(desc[b, 3]), int(desc[b, 1])
+        tb = taps[int(desc[b, 2]):int(desc[b, 2]) + L]
+        T = int(np.sum(tb))
+        if L == 4 and np.all(tb == 12):
+            n44 += 1
+            np.testing.assert_array_equal(got[o:o + 48], th48[b].cpu().numpy())
+        else:
+            np.testing.assert_array_equal(got[o:o + T], radial[o:o + T])
+    assert n44 < 40

@@ -75,3 +75,38 @@ def test_dense_sv_uses_each_pixels_kernel():
         K = disk_kernel(1.0 + 4.0 * P[0, y, x], 13)
         ref = D.dense_uniform(img, K, rows=slice(y, y + 1), cols=slice(x, x + 1))
         assert abs(out[y, x] - ref[0, 0]) < 1e-13
+
+
+def _coverage_grid(cov, P, h):
+    q = np.arange(-h, h + 1)
+    return np.array([[float(np.ravel(cov(P, qx, qy))[0]) for qx in q] for qy in q])
+
+
+def test_ellipse_coverage_reduces_to_the_disk_at_unit_aspect():
+    """At aspect a = 1 both semi-axes equal r, the ray distance to the boundary
+    is |q| - r, and the elliptical coverage is the disk's clamp(r + 1/2 - |q|)."""
+    for r in (2.0, 5.3, 11.75, 24.0):
+        P = np.array([[r], [1.0]])
+        e = _coverage_grid(D.ellipse_coverage(lambda p: p, lambda p: p), P, 27)
+        d = _coverage_grid(D.disk_coverage(lambda p: p), P[:1], 27)
+        np.testing.assert_allclose(e, d, rtol=0, atol=1e-12)
+
+
+def test_ellipse_coverage_axes_mass_and_second_moments():
+    """Semi-axes (r sqrt(a), r / sqrt(a)): along the x axis the coverage is a
+    1-D disk of radius r sqrt(a), along y one of radius r / sqrt(a); the mass
+    approaches the area pi r^2 (area-preserving); the second moments have the
+    ratio E[qx^2] / E[qy^2] = a^2 of a uniform ellipse.  Swapping the axes or
+    mis-scaling the boundary distance fails each of these."""
+    r, a = 9.0, 2.0
+    ax, ay = r * np.sqrt(a), r / np.sqrt(a)
+    P = np.array([[r], [a]])
+    h = 20
+    K = _coverage_grid(D.ellipse_coverage(lambda p: p, lambda p: p), P, h)
+    q = np.arange(-h, h + 1)
+    np.testing.assert_allclose(K[h, :], np.clip(ax + 0.5 - np.abs(q), 0, 1), atol=1e-12)
+    np.testing.assert_allclose(K[:, h], np.clip(ay + 0.5 - np.abs(q), 0, 1), atol=1e-12)
+    assert abs(K.sum() / (np.pi * r * r) - 1.0) < 0.01
+    qy, qx = np.mgrid[-h:h + 1, -h:h + 1]
+    ratio = (K * qx * qx).sum() / (K * qy * qy).sum()
+    assert abs(ratio / (a * a) - 1.0) < 0.03

@@ -174,3 +174,56 @@ def test_continuation_follows_exact_dilations():
     # and a wrong-direction scale does need steps
     _, _, steps2 = Ad.fit_continuation(targets, th_true, taps, [1.0] + [1 / s] * 3, p)
     assert steps2[1] > 0
+
+
+def test_optimize_loop_is_evaluate_then_adam_with_step_indexed_lr():
+    """The loop of Sec. 4.4 / Sec. 5.1: evaluate, then one Adam update with
+    the learning rate of step s (linear from lr0 at s = 0 to lr1 at s = S-1)
+    and bias correction t = s + 1; after S updates one more evaluation.
+    Compared with torch.optim.Adam (float64) driven by the oracle's own
+    gradients and a schedule written out here; an off-by-one in the lr index,
+    the bias-correction step or the final evaluation fails."""
+    taps = [5, 4]
+    M = 15
+    th_true = random_theta(taps, 2.5, seed=41).astype(np.float64)
+    target = S.impulse_response(M, th_true, taps)
+    start = th_true + np.random.default_rng(3).normal(0, 0.3, th_true.shape) * [1, 1, 0.05]
+    S_, lr0, lr1 = 3, 4e-2, 1e-2
+    p = Ad.OptParams(max_steps=S_, lr0=lr0, lr1=lr1)
+    trace = []
+    th, ps, steps = Ad.optimize(target, start, taps, p, trace)
+    q = torch.nn.Parameter(torch.tensor(start, dtype=torch.float64))
+    opt = torch.optim.Adam([q], lr=lr0, betas=(0.9, 0.999), eps=1e-8)
+    for s in range(S_):
+        loss, _, g = A.impulse_loss_grad(target, q.detach().numpy(), taps)
+        assert loss == trace[s][0]
+        for grp in opt.param_groups:
+            grp["lr"] = lr0 + (lr1 - lr0) * s / (S_ - 1)
+        q.grad = torch.tensor(g, dtype=torch.float64)
+        opt.step()
+    np.testing.assert_allclose(th, q.detach().numpy(), rtol=1e-13, atol=1e-15)
+    assert steps == S_ and len(trace) == S_ + 1
+    _, ps_end, _ = A.impulse_loss_grad(target, th, taps)
+    assert ps == ps_end == trace[-1][1]
+
+
+def test_optimize_stops_before_the_update_that_would_pass_the_threshold():
+    """Stop rule: a threshold between the PSNR after k and after k + 1
+    updates stops with exactly k + 1 updates applied and Theta equal to the
+    (k + 1)-update iterate of an unstopped run."""
+    taps = [4, 4]
+    M = 15
+    th_true = random_theta(taps, 2.0, seed=43).astype(np.float64)
+    target = S.impulse_response(M, th_true, taps)
+    start = th_true + np.random.default_rng(5).normal(0, 0.2, th_true.shape) * [1, 1, 0.05]
+    full = []
+    Ad.optimize(target, start, taps, Ad.OptParams(max_steps=12, lr0=2e-2, lr1=2e-2), full)
+    k = int(np.argmax([b[1] > a[1] for a, b in zip(full[4:], full[5:])])) + 4
+    thr = 0.5 * (full[k][1] + full[k + 1][1])
+    assert max(f[1] for f in full[:k + 1]) < thr
+    th_stop, ps, steps = Ad.optimize(target, start, taps, Ad.OptParams(max_steps=12, lr0=2e-2, lr1=2e-2,
+                                                                          psnr_stop_db=thr))
+    assert steps == k + 1 and ps == full[k + 1][1]
+    th_k, _, _ = Ad.optimize(target, start, taps, Ad.OptParams(max_steps=k + 1, lr0=2e-2, lr1=2e-2))
+    # the same k + 1 updates (constant lr, so the schedule length does not matter)
+    np.testing.assert_array_equal(th_stop, th_k)

@@ -203,3 +203,22 @@ def test_rotate_basis_quarter_turn_rotates_the_response():
     np.testing.assert_allclose(Kq, np.rot90(K, k=-1), atol=1e-15)
     twice = IP.rotate_basis(r[3][None], [np.pi / 6])[0]
     np.testing.assert_allclose(twice, r[2], atol=1e-13)
+
+
+def test_ss_init_layer1_weights_follow_the_target_at_the_rounded_points():
+    """Eq. 7's first layer: each tap's weight is the target value at the pixel
+    nearest to its sample point, normalised to unit sum.  The target's values
+    are all distinct (a ramp over the support), so equal weights, a wrong
+    rounding or a transposed lookup all change them."""
+    M = 41
+    c = (M - 1) // 2
+    y, x = np.mgrid[0:M, 0:M]
+    K = np.where(np.hypot(x - c, y - c) <= 15.0, 1.0 + 0.37 * x + 0.011 * y * y, 0.0)
+    taps = [10, 8, 8]
+    th, _ = I.ss_init(K, taps, seed=12, index=5)
+    first = th[:10]
+    rx = np.floor(first[:, 0] + c + 0.5).astype(int)
+    ry = np.floor(first[:, 1] + c + 0.5).astype(int)
+    want = K[ry, rx] / K[ry, rx].sum()
+    assert np.ptp(want) > 0.05                       # the weights really differ
+    np.testing.assert_allclose(first[:, 2], want, rtol=1e-14, atol=0)
