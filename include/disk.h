@@ -57,6 +57,10 @@ typedef enum {
 typedef enum { DISK_ZERO = 0, DISK_CLAMP = 1 } disk_boundary;
 typedef enum { DISK_F32 = 0, DISK_BF16 = 1 } disk_dtype;
 typedef enum { DISK_LOSS_NMSE = 0, DISK_LOSS_CHARBONNIER = 1 } disk_loss;
+/* Unit in which the learning rate moves tap offsets (Sec. 5.1 leaves it
+ * unstated): pixels, or the target's half-width (M - 1) / 2, the unit of
+ * normalised sampling coordinates.  Weights always move in their own unit. */
+typedef enum { DISK_OFFSETS_PIXELS = 0, DISK_OFFSETS_HALF_WIDTH = 1 } disk_offset_units;
 
 /* Layer structure of one sparse kernel complex (Eq. 5). */
 typedef struct {
@@ -137,7 +141,21 @@ typedef struct {
     float psnr_stop_db;      /* stop a target once PSNR >= this (INFINITY: never) */
     int32_t loss;            /* disk_loss */
     float charb_eps;         /* Charbonnier epsilon on the peak-normalised difference */
+    int32_t offset_units;    /* disk_offset_units: the offsets' learning rate is lr_t times this unit */
 } disk_opt_params;
+
+/* Optimiser state carried across calls, and the loss of the result.  Every
+ * field may be NULL / 0. */
+typedef struct {
+    float* adam_m;             /* device float [*][3] like theta: in = Adam first moments to resume from
+                                  (NULL: zeros), out = the moments after the last update */
+    float* adam_v;             /* the same for the second moments */
+    const int32_t* start_step; /* device int32 [B]: updates already applied to each target (NULL: 0); the
+                                  learning-rate schedule and the bias corrections continue from there;
+                                  a negative entry makes that target invalid (status 3) */
+    float* loss;               /* device float [B]: out, the loss of the returned Theta */
+    int32_t max_updates;       /* > 0: at most this many updates per target in this call; 0: no limit */
+} disk_opt_state;
 
 /*
  * Fits every target's Theta by Adam on the impulse-response loss, all targets
@@ -146,9 +164,11 @@ typedef struct {
  *   targets  device float (packed kernels);
  *   theta    device float [*][3]: in = Theta_0, out = the fitted Theta;
  *   psnr_db  device float [B]: PSNR of the returned Theta, 10 log10(max(K)^2 / MSE);
- *   steps    device int32 [B]: Adam updates applied;
+ *   steps    device int32 [B]: position reached in the learning-rate schedule,
+ *            i.e. the Adam updates applied including state->start_step;
  *   status   device int32 [B]: 0 ok, 1 stopped at the PSNR threshold,
- *            2 diverged (non-finite loss; Theta left at the last finite value),
+ *            2 diverged (non-finite loss, e.g. a target holding NaN; Theta is
+ *            the last one evaluated and no update is applied from it),
  *            3 invalid descriptor (even or out-of-range side, L outside
  *            1..DISK_MAX_LAYERS, a layer with 0 or more than DISK_MAX_TAPS taps,
  *            side or total taps above meta's maxima, a negative offset
@@ -158,19 +178,34 @@ typedef struct {
  *   finish_ticks  device uint64 [B + 1] or NULL: the device's constant-rate
  *            clock (disk_clock_rate_khz) when each target finished; entry B
  *            holds the clock at the start of the launch.
+ *   params   host: Adam hyper-parameters, schedule, stopping rule, loss.
+ *   state    host struct of device pointers, or NULL: resume from given Adam
+ *            moments and schedule positions, report the loss, limit the
+ *            updates of this call.  Splitting a run into calls that carry
+ *            the state gives the same result, bit for bit, as one call.
+ *   tune     host, or NULL for the built-in table (see disk_opt_tune).
+ *   ws       device scratch of disk_optimize_workspace_size(meta, tune) bytes.
  *   meta     host: B, the maximum side and total taps, used to size the launch.
  * Loss: normalised MSE, mean((K_syn - K)^2) / max(K)^2, or Charbonnier.
+ * The two launches (queue order, persistent optimiser) contain no memset or
+ * copy, so the call may be captured into a HIP graph and replayed.
  */
 typedef struct {
     int32_t B;
     int32_t max_side;
     int32_t max_T;
 } disk_batch_meta;
-size_t disk_optimize_workspace_size(const disk_batch_meta* meta);
+/* Launch shape of the persistent optimiser, chosen per batch by the built-in
+ * table (tune = NULL, written by the project's autotuner) or given here. */
+typedef struct {
+    int32_t wgs_per_cu;        /* resident work-groups (one target each) per compute unit, 1..4 */
+} disk_opt_tune;
+size_t disk_optimize_workspace_size(const disk_batch_meta* meta, const disk_opt_tune* tune);
 disk_status disk_optimize_batch(const disk_batch_meta* meta, const disk_target* desc,
                                 const int32_t* taps, const float* targets, float* theta,
                                 float* psnr_db, int32_t* steps, int32_t* status,
-                                uint64_t* finish_ticks, const disk_opt_params* params, void* ws,
+                                uint64_t* finish_ticks, const disk_opt_params* params,
+                                const disk_opt_state* state, const disk_opt_tune* tune, void* ws,
                                 size_t ws_bytes, hipStream_t stream);
 
 /*
@@ -270,6 +305,7 @@ size_t disk_sv_filter_workspace_size(const disk_basis* b, int32_t C, int32_t H, 
 disk_status disk_sv_filter(const disk_basis* b, const float* basis_theta, const void* image,
                            const float* pmap, void* out, int32_t C, int32_t H, int32_t W,
                            disk_dtype io, void* ws, size_t ws_bytes, hipStream_t stream);
+
 
 /*
  * Angle axis for a 2-D basis (the angle-driven effects, rotational bokeh and

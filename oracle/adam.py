@@ -9,6 +9,11 @@ Readings:
   and weights.
 * Linear decay: at step s = 0..S-1, lr_s = lr0 + (lr1 - lr0) * s / (S - 1)
   (constant when lr0 == lr1 or S == 1).
+* The unit in which the learning rate moves tap offsets is unstated (Sec.
+  5.1): pixels (offset_units = 0), or the target's half-width (M - 1) / 2
+  (offset_units = 1), the unit of normalised sampling coordinates in which
+  an M x M window spans [-1, 1]; the offsets' learning rate is then
+  lr_s * (M - 1) / 2 pixels.  Weights always move at lr_s.
 * The loop evaluates F_Theta(delta) before every update and stops as soon as
   the PSNR reaches the stop threshold, without updating; ``steps`` is the
   number of Adam updates applied.  After S updates the final Theta is
@@ -37,6 +42,7 @@ class OptParams:
     psnr_stop_db: float = float("inf")
     loss: int = _loss.NMSE
     charb_eps: float = 1e-3
+    offset_units: int = 0
 
 
 def lr_at(s, S, lr0, lr1):
@@ -46,7 +52,9 @@ def lr_at(s, S, lr0, lr1):
 
 
 def adam_update(theta, g, m, v, t, lr, beta1=0.9, beta2=0.999, eps=1e-8):
-    """One Adam update (t is 1-based).  Returns new (theta, m, v)."""
+    """One Adam update (t is 1-based).  ``lr`` is a scalar, or an array that
+    broadcasts against theta (one rate per coordinate).  Returns new
+    (theta, m, v)."""
     theta = np.asarray(theta, dtype=np.float64)
     g = np.asarray(g, dtype=np.float64)
     m = beta1 * m + (1.0 - beta1) * g
@@ -56,6 +64,12 @@ def adam_update(theta, g, m, v, t, lr, beta1=0.9, beta2=0.999, eps=1e-8):
     return theta - lr * mh / (np.sqrt(vh) + eps), m, v
 
 
+def rate_units(side, offset_units):
+    """Per-coordinate multiplier of the learning rate for (ox, oy, w)."""
+    u = 0.5 * (side - 1) if offset_units == 1 else 1.0
+    return np.array([u, u, 1.0])
+
+
 def optimize(target, theta0, taps, p: OptParams, trace=None):
     """Fit Theta to a dense target by Adam on the impulse-response loss.
     Returns (theta, psnr_db, steps).  If ``trace`` is a list, the loss and
@@ -63,13 +77,14 @@ def optimize(target, theta0, taps, p: OptParams, trace=None):
     theta = np.array(theta0, dtype=np.float64).reshape(-1, 3)
     m = np.zeros_like(theta)
     v = np.zeros_like(theta)
+    unit = rate_units(np.asarray(target).shape[0], p.offset_units)
     for s in range(p.max_steps):
         loss, ps, g = impulse_loss_grad(target, theta, taps, p.loss, p.charb_eps)
         if trace is not None:
             trace.append((loss, ps))
         if ps >= p.psnr_stop_db:
             return theta, ps, s
-        theta, m, v = adam_update(theta, g, m, v, s + 1, lr_at(s, p.max_steps, p.lr0, p.lr1),
+        theta, m, v = adam_update(theta, g, m, v, s + 1, lr_at(s, p.max_steps, p.lr0, p.lr1) * unit,
                                   p.beta1, p.beta2, p.eps)
     loss, ps, _ = impulse_loss_grad(target, theta, taps, p.loss, p.charb_eps)
     if trace is not None:

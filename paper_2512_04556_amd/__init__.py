@@ -16,7 +16,8 @@ import torch
 __all__ = [
     "lib", "DiskError", "ZERO", "CLAMP", "F32", "BF16", "LOSS_NMSE", "LOSS_CHARBONNIER",
     "disk_forward", "disk_backward", "disk_sv_filter", "disk_sv_prepare", "disk_sv_apply", "Basis", "make_basis",
-    "disk_optimize_batch", "disk_init_radial", "disk_init_random", "disk_fit_basis", "pack_targets", "fit_basis", "disk_init_shape", "OptParams", "Batch", "make_batch",
+    "disk_optimize_batch", "Captured", "OptState", "opt_tune", "optimize_workspace_size", "OFFSETS_PIXELS",
+    "OFFSETS_HALF_WIDTH", "disk_init_radial", "disk_init_random", "disk_fit_basis", "pack_targets", "fit_basis", "disk_init_shape", "OptParams", "Batch", "make_batch",
     "disk_init_predict", "disk_net_train_step", "disk_net_prepare_inputs", "disk_net_scatter_theta",
     "disk_net_param_count", "net_workspace", "clock_rate_khz",
     "disk_dense_sv", "DENSE_DISK", "DENSE_ELLIPSE", "disk_basis_rotate",
@@ -46,7 +47,16 @@ class DiskBasis(ctypes.Structure):
 class DiskOptParams(ctypes.Structure):
     _fields_ = [("max_steps", c_int32), ("lr0", c_float), ("lr1", c_float), ("beta1", c_float),
                 ("beta2", c_float), ("eps", c_float), ("psnr_stop_db", c_float), ("loss", c_int32),
-                ("charb_eps", c_float)]
+                ("charb_eps", c_float), ("offset_units", c_int32)]
+
+
+class DiskOptState(ctypes.Structure):
+    _fields_ = [("adam_m", c_void_p), ("adam_v", c_void_p), ("start_step", c_void_p), ("loss", c_void_p),
+                ("max_updates", c_int32)]
+
+
+class DiskOptTune(ctypes.Structure):
+    _fields_ = [("wgs_per_cu", c_int32)]
 
 
 class DiskDenseParams(ctypes.Structure):
@@ -76,9 +86,9 @@ def lib():
         "disk_forward": (c_int32, [POINTER(DiskComplex), P, P, P, c_int32, c_int32, c_int32, c_int32, c_int32, P, P, c_size_t, P]),
         "disk_backward_workspace_size": (c_size_t, [POINTER(DiskComplex), c_int32, c_int32, c_int32]),
         "disk_backward": (c_int32, [POINTER(DiskComplex), P, P, P, P, P, P, c_int32, c_int32, c_int32, c_int32, P, c_size_t, P]),
-        "disk_optimize_workspace_size": (c_size_t, [POINTER(DiskBatchMeta)]),
-        "disk_optimize_batch": (c_int32, [POINTER(DiskBatchMeta), P, P, P, P, P, P, P, P, POINTER(DiskOptParams), P,
-                                          c_size_t, P]),
+        "disk_optimize_workspace_size": (c_size_t, [POINTER(DiskBatchMeta), POINTER(DiskOptTune)]),
+        "disk_optimize_batch": (c_int32, [POINTER(DiskBatchMeta), P, P, P, P, P, P, P, P, POINTER(DiskOptParams),
+                                          POINTER(DiskOptState), POINTER(DiskOptTune), P, c_size_t, P]),
         "disk_clock_rate_khz": (c_int64, []),
         "disk_basis_rotate": (c_int32, [P, c_int32, c_int32, POINTER(c_double), c_int32, P, P]),
         "disk_dense_sv": (c_int32, [POINTER(DiskDenseParams), P, P, P, c_int32, c_int32, c_int32, c_int32, P]),
@@ -312,10 +322,36 @@ def disk_sv_apply(basis: Basis, table, image, pmap, out=None, ws=None):
 # ---------------------------------------------------------------------------
 # batched optimisation and initialisers
 # ---------------------------------------------------------------------------
+OFFSETS_PIXELS, OFFSETS_HALF_WIDTH = 0, 1
+
+
 class OptParams:
     def __init__(self, max_steps=1000, lr0=1e-2, lr1=1e-3, beta1=0.9, beta2=0.999, eps=1e-8,
-                 psnr_stop_db=float("inf"), loss=LOSS_NMSE, charb_eps=1e-3):
-        self.c = DiskOptParams(int(max_steps), lr0, lr1, beta1, beta2, eps, psnr_stop_db, int(loss), charb_eps)
+                 psnr_stop_db=float("inf"), loss=LOSS_NMSE, charb_eps=1e-3, offset_units=OFFSETS_PIXELS):
+        self.c = DiskOptParams(int(max_steps), lr0, lr1, beta1, beta2, eps, psnr_stop_db, int(loss), charb_eps,
+                               int(offset_units))
+
+
+class OptState:
+    """Adam state carried across disk_optimize_batch calls (resume), the loss
+    of the returned Theta, and a cap on the updates of one call.  adam_m,
+    adam_v: float32 [*][3] like theta (in/out, given together or not at all);
+    start_step: int32 [B] (in); loss: float32 [B] (out)."""
+
+    def __init__(self, adam_m=None, adam_v=None, start_step=None, loss=None, max_updates=0):
+        for t, name in ((adam_m, "adam_m"), (adam_v, "adam_v"), (loss, "loss")):
+            _dev(t, name)
+            _f32(t, name)
+        _dev(start_step, "start_step")
+        if start_step is not None and start_step.dtype != torch.int32:
+            raise DiskError("start_step must be int32")
+        self.tensors = (adam_m, adam_v, start_step, loss)
+        self.c = DiskOptState(*[None if t is None else _ptr(t) for t in self.tensors], int(max_updates))
+
+
+def opt_tune(wgs_per_cu):
+    """A launch shape for disk_optimize_batch (None selects the built-in table)."""
+    return DiskOptTune(int(wgs_per_cu))
 
 
 class Batch:
@@ -346,22 +382,34 @@ def make_batch(desc, taps, targets, device="cuda"):
     return bt
 
 
-def disk_optimize_batch(batch: Batch, theta, params: OptParams, ticks=None):
+def disk_optimize_batch(batch: Batch, theta, params: OptParams, ticks=None, state: OptState = None, tune=None,
+                        ws=None):
     """Optimise every target of ``batch`` in place on ``theta`` [*][3].
     Returns (psnr_db [B], steps [B], status [B]).  ``ticks`` (optional,
     int64 [B + 1]) receives the device clock at each target's finish and, in
-    entry B, at the launch's start."""
+    entry B, at the launch's start.  ``state``: an OptState (resume, loss);
+    ``tune``: opt_tune(...) or None for the built-in table; ``ws``: a
+    workspace to reuse (uint8, at least optimize_workspace_size bytes)."""
+    _dev(theta, "theta")
+    _f32(theta, "theta")
     dev = theta.device
     B = batch.B
     psnr = torch.empty(B, dtype=torch.float32, device=dev)
     steps = torch.empty(B, dtype=torch.int32, device=dev)
     status = torch.empty(B, dtype=torch.int32, device=dev)
     L = lib()
-    ws = _workspace(L.disk_optimize_workspace_size(ctypes.byref(batch.meta)), dev)
+    tn = None if tune is None else ctypes.byref(tune)
+    if ws is None:
+        ws = _workspace(L.disk_optimize_workspace_size(ctypes.byref(batch.meta), tn), dev)
+    st = None if state is None else ctypes.byref(state.c)
     _check(L.disk_optimize_batch(ctypes.byref(batch.meta), _ptr(batch.desc), _ptr(batch.taps), _ptr(batch.targets),
                                  _ptr(theta), _ptr(psnr), _ptr(steps), _ptr(status), _ptr(ticks),
-                                 ctypes.byref(params.c), _ptr(ws), ws.numel(), _stream()))
+                                 ctypes.byref(params.c), st, tn, _ptr(ws), ws.numel(), _stream()))
     return psnr, steps, status
+
+
+def optimize_workspace_size(batch: Batch, tune=None):
+    return int(lib().disk_optimize_workspace_size(ctypes.byref(batch.meta), None if tune is None else ctypes.byref(tune)))
 
 
 def disk_basis_rotate(base, angles):
@@ -541,6 +589,31 @@ def disk_net_scatter_theta(batch: Batch, theta48, theta=None):
     _check(lib().disk_net_scatter_theta(ctypes.byref(batch.meta), _ptr(batch.desc), _ptr(batch.taps), _ptr(theta48),
                                         _ptr(theta), _stream()))
     return theta
+
+
+class Captured:
+    """Library calls captured once into a HIP graph (torch.cuda.CUDAGraph over
+    the current device) and replayed as one launch.  ``fn`` is called once on a
+    side stream to warm up, then once under capture; its return value (the
+    output tensors, which live in the graph's memory pool) is kept in
+    ``outputs``.  Every buffer the calls read or write must stay alive and in
+    place between replays; the library's launches contain no memset or copy
+    nodes, so replays recompute from the buffers' current contents."""
+
+    def __init__(self, fn, warmup=True):
+        self.graph = torch.cuda.CUDAGraph()
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        if warmup:
+            with torch.cuda.stream(side):
+                fn()
+            torch.cuda.current_stream().wait_stream(side)
+        with torch.cuda.graph(self.graph):
+            self.outputs = fn()
+
+    def replay(self):
+        self.graph.replay()
+        return self.outputs
 
 
 from .autograd import DiskChain  # noqa: E402  (torch.autograd.Function over disk_forward/backward)

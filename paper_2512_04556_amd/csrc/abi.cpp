@@ -482,12 +482,24 @@ static disk_status check_opt_params(const disk_opt_params* params) {
     if (!std::isfinite(p.lr0) || !std::isfinite(p.lr1)) return fail(DISK_INVALID_ARG, "non-finite learning rate");
     if (p.loss != DISK_LOSS_NMSE && p.loss != DISK_LOSS_CHARBONNIER) return fail(DISK_INVALID_ARG, "bad loss %d", p.loss);
     if (p.loss == DISK_LOSS_CHARBONNIER && !(p.charb_eps > 0.0f)) return fail(DISK_INVALID_ARG, "charb_eps must be > 0");
+    if (p.offset_units != DISK_OFFSETS_PIXELS && p.offset_units != DISK_OFFSETS_HALF_WIDTH)
+        return fail(DISK_INVALID_ARG, "bad offset_units %d", p.offset_units);
     return DISK_OK;
 }
 
-static size_t optimize_ws(const disk_batch_meta* m, Carve& cv, int** order, int** queue, float** scratch,
-                          size_t* slot, int* nwg) {
-    *nwg = opt_workgroups(m->B);
+static disk_status check_tune(const disk_opt_tune* t) {
+    if (t && (t->wgs_per_cu < 1 || t->wgs_per_cu > 4))
+        return fail(DISK_INVALID_ARG, "tune->wgs_per_cu=%d must be in 1..4", t->wgs_per_cu);
+    return DISK_OK;
+}
+
+static int wgs_per_cu(const disk_batch_meta* m, const disk_opt_tune* t) {
+    return t ? t->wgs_per_cu : opt_default_wgs_per_cu(*m);
+}
+
+static size_t optimize_ws(const disk_batch_meta* m, const disk_opt_tune* t, Carve& cv, int** order, int** queue,
+                          float** scratch, size_t* slot, int* nwg) {
+    *nwg = opt_workgroups(m->B, wgs_per_cu(m, t));
     *slot = opt_slot_floats(m->max_side, std::min(m->max_T, DISK_MAX_LAYERS));
     *order = cv.take<int>(m->B);
     *queue = cv.take<int>(64);
@@ -495,19 +507,20 @@ static size_t optimize_ws(const disk_batch_meta* m, Carve& cv, int** order, int*
     return cv.used;
 }
 
-size_t disk_optimize_workspace_size(const disk_batch_meta* meta) {
+size_t disk_optimize_workspace_size(const disk_batch_meta* meta, const disk_opt_tune* tune) {
     if (!meta || meta->B < 1 || meta->max_side < 1 || meta->max_T < 1) return 0;
+    if (tune && (tune->wgs_per_cu < 1 || tune->wgs_per_cu > 4)) return 0;
     Carve cv(nullptr, 0);
     int *o, *q, nwg;
     float* sc;
     size_t slot;
-    return optimize_ws(meta, cv, &o, &q, &sc, &slot, &nwg) + 256;
+    return optimize_ws(meta, tune, cv, &o, &q, &sc, &slot, &nwg) + 256;
 }
 
 disk_status disk_optimize_batch(const disk_batch_meta* meta, const disk_target* desc, const int32_t* taps,
                                 const float* targets, float* theta, float* psnr_db, int32_t* steps, int32_t* status,
-                                uint64_t* finish_ticks, const disk_opt_params* params, void* ws, size_t ws_bytes,
-                                hipStream_t stream) {
+                                uint64_t* finish_ticks, const disk_opt_params* params, const disk_opt_state* state,
+                                const disk_opt_tune* tune, void* ws, size_t ws_bytes, hipStream_t stream) {
     DISK_TRY(check_meta(meta));
     DISK_TRY(check_ptr(desc, "desc"));
     DISK_TRY(check_ptr(taps, "taps"));
@@ -517,18 +530,34 @@ disk_status disk_optimize_batch(const disk_batch_meta* meta, const disk_target* 
     DISK_TRY(check_ptr(steps, "steps"));
     DISK_TRY(check_ptr(status, "status"));
     DISK_TRY(check_opt_params(params));
+    DISK_TRY(check_tune(tune));
     const disk_opt_params& p = *params;
     Carve cv(ws, ws_bytes);
     int *order, *queue, nwg;
     float* scratch;
     size_t slot;
-    optimize_ws(meta, cv, &order, &queue, &scratch, &slot, &nwg);
+    optimize_ws(meta, tune, cv, &order, &queue, &scratch, &slot, &nwg);
     if (!ws || cv.used > ws_bytes)
         return fail(DISK_WORKSPACE_TOO_SMALL, "workspace %zu < %zu bytes", ws_bytes, cv.used);
     DISK_TRY(check_ptr(finish_ticks, "finish_ticks", true));
+    OptExtra x;
+    x.ticks = reinterpret_cast<unsigned long long*>(finish_ticks);
+    if (state) {
+        if ((state->adam_m == nullptr) != (state->adam_v == nullptr))
+            return fail(DISK_INVALID_ARG, "state: adam_m and adam_v must be given together");
+        if (state->max_updates < 0) return fail(DISK_INVALID_ARG, "state->max_updates=%d < 0", state->max_updates);
+        DISK_TRY(check_ptr(state->adam_m, "state->adam_m", true));
+        DISK_TRY(check_ptr(state->adam_v, "state->adam_v", true));
+        DISK_TRY(check_ptr(state->start_step, "state->start_step", true));
+        DISK_TRY(check_ptr(state->loss, "state->loss", true));
+        x.adam_m = state->adam_m;
+        x.adam_v = state->adam_v;
+        x.start = state->start_step;
+        x.loss = state->loss;
+        x.max_updates = state->max_updates;
+    }
     DISK_HIP(launch_optimize(meta->B, desc, taps, targets, theta, psnr_db, steps, status, p, order, queue, scratch,
-                             slot, nwg, meta->max_side, meta->max_T,
-                             reinterpret_cast<unsigned long long*>(finish_ticks), stream),
+                             slot, nwg, meta->max_side, meta->max_T, x, stream),
              "optimize");
     return ok();
 }
@@ -555,13 +584,13 @@ disk_status disk_fit_basis(const disk_batch_meta* meta, const disk_target* desc,
     int *order, *queue, nwg;
     float* scratch;
     size_t slot;
-    optimize_ws(&one, cv, &order, &queue, &scratch, &slot, &nwg);
+    optimize_ws(&one, nullptr, cv, &order, &queue, &scratch, &slot, &nwg);
     if (!ws || cv.used > ws_bytes)
         return fail(DISK_WORKSPACE_TOO_SMALL, "workspace %zu < %zu bytes", ws_bytes, cv.used);
     for (int k = 0; k < meta->B; ++k) {
         if (k > 0) DISK_HIP(launch_continue(desc, taps, theta, k, scale[k], stream), "continuation start");
         DISK_HIP(launch_optimize(1, desc + k, taps, targets, theta, psnr_db + k, steps + k, status + k, *params,
-                                 order, queue, scratch, slot, nwg, meta->max_side, meta->max_T, nullptr, stream),
+                                 order, queue, scratch, slot, nwg, meta->max_side, meta->max_T, OptExtra{}, stream),
                  "optimize");
     }
     return ok();
@@ -574,7 +603,7 @@ size_t disk_fit_basis_workspace_size(const disk_batch_meta* meta) {
     int *order, *queue, nwg;
     float* scratch;
     size_t slot;
-    optimize_ws(&one, cv, &order, &queue, &scratch, &slot, &nwg);
+    optimize_ws(&one, nullptr, cv, &order, &queue, &scratch, &slot, &nwg);
     return cv.used;
 }
 
@@ -718,3 +747,4 @@ disk_status disk_net_scatter_theta(const disk_batch_meta* meta, const disk_targe
 }
 
 }  // extern "C"
+

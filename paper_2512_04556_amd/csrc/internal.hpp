@@ -103,12 +103,22 @@ hipError_t launch_chain_pass(int C, int src_bf16, const void* src, int dst_bf16,
                              int tap0, int N, int T, int H, int W, hipStream_t s);
 
 // ---- optimize.hip: batched optimiser and radial init --------------------------
-int opt_workgroups(int B);
+// optional outputs and resumed state of one optimiser launch
+struct OptExtra {
+    unsigned long long* ticks = nullptr;
+    float* adam_m = nullptr;
+    float* adam_v = nullptr;
+    const int* start = nullptr;
+    float* loss = nullptr;
+    int max_updates = 0;
+};
+int opt_workgroups(int B, int per_cu);
+int opt_default_wgs_per_cu(const disk_batch_meta& m);
 size_t opt_slot_floats(int max_side, int max_L);
 hipError_t launch_optimize(int B, const disk_target* desc, const int* taps, const float* targets, float* theta,
                            float* psnr, int* steps, int* status, const disk_opt_params& p, int* order, int* queue,
                            float* scratch, size_t slot_floats, int nwg, int max_side, int max_T,
-                           unsigned long long* ticks, hipStream_t s);
+                           const OptExtra& x, hipStream_t s);
 hipError_t launch_continue(const disk_target* desc, const int* taps, float* theta, int k, float scale,
                            hipStream_t s);
 hipError_t launch_init_radial(int B, const disk_target* desc, const int* taps, const float* targets, float* theta,

@@ -50,6 +50,12 @@ struct OptArgs {
     size_t slot_floats;
     int max_side, max_T;
     unsigned long long* ticks;   // optional: device clock when each target finished
+    // optional Adam state carried across calls, per Theta row like theta
+    float* adam_m;
+    float* adam_v;
+    const int* start;            // optional: updates already applied per target
+    float* loss;                 // optional: loss of the returned Theta per target
+    int max_updates;             // > 0: at most this many updates per target in this call
 };
 
 struct TapO {
@@ -402,11 +408,14 @@ __global__ __launch_bounds__(kOptThreads, 4) void opt_kernel(OptArgs a) {
                 T += ntap[l];
             }
         bad |= T > a.max_T || static_cast<size_t>(M + 2 * P) * (M + 2 * P) * L > a.slot_floats;
+        const int s0 = a.start ? a.start[b] : 0;   // resumed schedule position
+        bad |= s0 < 0;
         if (bad) {
             if (tid == 0) {
                 a.psnr[b] = 0.0f;
                 a.steps[b] = 0;
                 a.status[b] = 3;
+                if (a.loss) a.loss[b] = 0.0f;
                 if (a.ticks) a.ticks[b] = wall_clock64();
             }
             __syncthreads();
@@ -424,23 +433,33 @@ __global__ __launch_bounds__(kOptThreads, 4) void opt_kernel(OptArgs a) {
         const float n = static_cast<float>(M) * M;
 
         // ---- target setup: parameters, moments, zeroed canvases, peak -------
+        float* am_g = a.adam_m ? a.adam_m + 3 * static_cast<size_t>(d.theta_off) : nullptr;
+        float* av_g = a.adam_v ? a.adam_v + 3 * static_cast<size_t>(d.theta_off) : nullptr;
         for (int i = tid; i < 3 * T; i += kOptThreads) {
             th[i] = theta_g[i];
-            am[i] = 0.0f;
-            av[i] = 0.0f;
+            am[i] = am_g ? am_g[i] : 0.0f;
+            av[i] = av_g ? av_g[i] : 0.0f;
         }
+        // learning-rate unit of the offsets: pixels, or the target's half-width
+        const float ounit = a.p.offset_units == DISK_OFFSETS_HALF_WIDTH ? 0.5f * static_cast<float>(M - 1) : 1.0f;
         for (size_t i = tid; i < SS * L; i += kOptThreads) slot[i] = 0.0f;
         if (tid < 4 * (DISK_MAX_LAYERS + 1)) s_box[tid >> 2][tid & 3] = (tid & 1) ? -1 : M;   // empty: the canvases are zero
         float pk = -INFINITY;
         for (int i = tid; i < M * M; i += kOptThreads) pk = fmaxf(pk, tgt[i]);
         pk = wg_max(pk, red);
         const float inv_pk2 = 1.0f / (pk * pk);
+        // beta^t after the s0 updates already applied (the same products an
+        // uninterrupted run forms one step at a time)
         float b1t = 1.0f, b2t = 1.0f;
-        float psnr = 0.0f;
+        for (int k = 0; k < s0; ++k) {
+            b1t *= a.p.beta1;
+            b2t *= a.p.beta2;
+        }
+        float psnr = 0.0f, loss = 0.0f;
         int status = 0, step = 0;
         __syncthreads();
 
-        for (step = 0;; ++step) {
+        for (step = s0;; ++step) {
             // ---- taps of the current Theta --------------------------------
             for (int i = tid; i < T; i += kOptThreads) {
                 const float ox = th[3 * i], oy = th[3 * i + 1], w = th[3 * i + 2];
@@ -545,7 +564,7 @@ __global__ __launch_bounds__(kOptThreads, 4) void opt_kernel(OptArgs a) {
             se = wg_sum(se, red);
             if (a.p.loss == DISK_LOSS_CHARBONNIER) ch = wg_sum(ch, red);
             const float nmse = se * inv_pk2 / n;
-            const float loss = a.p.loss == DISK_LOSS_CHARBONNIER ? ch / n : nmse;
+            loss = a.p.loss == DISK_LOSS_CHARBONNIER ? ch / n : nmse;
             psnr = nmse > 0.0f ? -10.0f * log10f(nmse) : INFINITY;
             if (!isfinite(loss)) {
                 status = 2;
@@ -555,7 +574,7 @@ __global__ __launch_bounds__(kOptThreads, 4) void opt_kernel(OptArgs a) {
                 status = 1;
                 break;
             }
-            if (step >= a.p.max_steps) break;
+            if (step >= a.p.max_steps || (a.max_updates > 0 && step - s0 >= a.max_updates)) break;
 
             // ---- backward ----------------------------------------------------
             for (int l = L - 1; l >= 0; --l) {
@@ -709,22 +728,28 @@ __global__ __launch_bounds__(kOptThreads, 4) void opt_kernel(OptArgs a) {
             b1t *= a.p.beta1;
             b2t *= a.p.beta2;
             const float bc1 = 1.0f - b1t, bc2 = 1.0f - b2t;
+            const float lr_o = lr * ounit;
             for (int i = tid; i < 3 * T; i += kOptThreads) {
                 const float g = gr[i];
                 const float m = fmaf(a.p.beta1, am[i], (1.0f - a.p.beta1) * g);
                 const float v = fmaf(a.p.beta2, av[i], (1.0f - a.p.beta2) * g * g);
                 am[i] = m;
                 av[i] = v;
-                th[i] -= lr * (m / bc1) / (sqrtf(v / bc2) + a.p.eps);
+                th[i] -= (i % 3 == 2 ? lr : lr_o) * (m / bc1) / (sqrtf(v / bc2) + a.p.eps);
             }
             __syncthreads();
         }
 
-        for (int i = tid; i < 3 * T; i += kOptThreads) theta_g[i] = th[i];
+        for (int i = tid; i < 3 * T; i += kOptThreads) {
+            theta_g[i] = th[i];
+            if (am_g) am_g[i] = am[i];
+            if (av_g) av_g[i] = av[i];
+        }
         if (tid == 0) {
             a.psnr[b] = psnr;
             a.steps[b] = step;
             a.status[b] = status;
+            if (a.loss) a.loss[b] = loss;
             if (a.ticks) a.ticks[b] = wall_clock64();
         }
         __syncthreads();
@@ -792,19 +817,14 @@ hipError_t launch_continue(const disk_target* desc, const int* taps, float* thet
     return hipGetLastError();
 }
 
-// Resident work-groups: `per_cu` per compute unit (DISK_OPT_WGS_PER_CU, a
-// tuning override read once; default 4: 16 waves per CU hide the canvas
-// reads' latency; 2 per CU ran 1.5x slower, 8 no faster).
-int opt_workgroups(int B) {
+// Resident work-groups: `per_cu` per compute unit (each owns one target at a
+// time), at most one per target.
+int opt_workgroups(int B, int per_cu) {
     int dev = 0, n = 0;
     if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
         n <= 0)
         n = 256;
-    static const int per_cu = [] {
-        const char* e = std::getenv("DISK_OPT_WGS_PER_CU");
-        const int v = e ? std::atoi(e) : 4;
-        return v >= 1 && v <= 16 ? v : 4;
-    }();
+    per_cu = std::max(1, std::min(per_cu, 4));
     return std::max(1, std::min(B, per_cu * n));
 }
 
@@ -816,10 +836,11 @@ size_t opt_slot_floats(int max_side, int max_L) {
 hipError_t launch_optimize(int B, const disk_target* desc, const int* taps, const float* targets, float* theta,
                            float* psnr, int* steps, int* status, const disk_opt_params& p, int* order, int* queue,
                            float* scratch, size_t slot_floats, int nwg, int max_side, int max_T,
-                           unsigned long long* ticks, hipStream_t s) {
-    hipLaunchKernelGGL(opt_order_kernel, dim3(1), dim3(1024), 0, s, B, desc, taps, order, queue, ticks);
-    OptArgs a{B,     desc,  taps,    targets,     theta,    psnr,  steps, status, p,
-              order, queue, scratch, slot_floats, max_side, max_T, ticks};
+                           const OptExtra& x, hipStream_t s) {
+    hipLaunchKernelGGL(opt_order_kernel, dim3(1), dim3(1024), 0, s, B, desc, taps, order, queue, x.ticks);
+    OptArgs a{B,     desc,  taps,    targets,     theta,    psnr,     steps,   status, p,
+              order, queue, scratch, slot_floats, max_side, max_T,    x.ticks, x.adam_m, x.adam_v,
+              x.start, x.loss, x.max_updates};
     hipLaunchKernelGGL(opt_kernel, dim3(nwg), dim3(kOptThreads), 0, s, a);
     return hipGetLastError();
 }

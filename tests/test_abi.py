@@ -121,7 +121,8 @@ def test_optimiser_and_basis_fit_validation():
     args = (ctypes.byref(meta), fake, fake, fake, fake, fake, fake, fake)
     # even max_side, B < 1
     bad = disk.DiskBatchMeta(4, 30, 24)
-    assert L.disk_optimize_batch(ctypes.byref(bad), *args[1:], None, ctypes.byref(prm), fake, ws, None) == -2
+    assert L.disk_optimize_batch(ctypes.byref(bad), *args[1:], None, ctypes.byref(prm), None, None, fake, ws,
+                                 None) == -2
     assert L.disk_fit_basis(ctypes.byref(disk.DiskBatchMeta(0, 31, 24)), *args[1:], sc, ctypes.byref(prm),
                             fake, ws, None) == -2
     # scale missing or not positive
@@ -132,9 +133,25 @@ def test_optimiser_and_basis_fit_validation():
     # Adam hyper-parameters
     bad_p = disk.OptParams(max_steps=10, beta1=1.0).c
     assert L.disk_fit_basis(*args, sc, ctypes.byref(bad_p), fake, ws, None) == -1
-    assert L.disk_optimize_batch(*args, None, ctypes.byref(bad_p), fake, ws, None) == -1
+    assert L.disk_optimize_batch(*args, None, ctypes.byref(bad_p), None, None, fake, ws, None) == -1
+    bad_u = disk.OptParams(max_steps=10, offset_units=2).c
+    assert L.disk_optimize_batch(*args, None, ctypes.byref(bad_u), None, None, fake, ws, None) == -1
+    assert b"offset_units" in L.disk_last_error()
     # misaligned finish_ticks
-    assert L.disk_optimize_batch(*args, P(0x1008), ctypes.byref(prm), fake, ws, None) == -1
+    assert L.disk_optimize_batch(*args, P(0x1008), ctypes.byref(prm), None, None, fake, ws, None) == -1
+    # launch shape out of range; Adam moments given without the other
+    for w in (0, 5):
+        tune = disk.DiskOptTune(w)
+        assert L.disk_optimize_batch(*args, None, ctypes.byref(prm), None, ctypes.byref(tune), fake, ws, None) == -1
+        assert L.disk_optimize_workspace_size(ctypes.byref(meta), ctypes.byref(tune)) == 0
+    st = disk.DiskOptState(fake, None, None, None, 0)
+    assert L.disk_optimize_batch(*args, None, ctypes.byref(prm), ctypes.byref(st), None, fake, ws, None) == -1
+    st = disk.DiskOptState(fake, fake, None, None, -1)
+    assert L.disk_optimize_batch(*args, None, ctypes.byref(prm), ctypes.byref(st), None, fake, ws, None) == -1
+    # more resident work-groups need more workspace
+    t1, t4 = disk.DiskOptTune(1), disk.DiskOptTune(4)
+    assert (L.disk_optimize_workspace_size(ctypes.byref(meta), ctypes.byref(t1)) <=
+            L.disk_optimize_workspace_size(ctypes.byref(meta), ctypes.byref(t4)))
     # workspace too small
     need = L.disk_fit_basis_workspace_size(ctypes.byref(meta))
     assert need > 0

@@ -68,7 +68,7 @@ def test_impulse_autograd_fd_and_oracle(dev):
     worst_gpu = max(abs(g[r, c] - f) / max(abs(f), scale) for (r, c), f in zip(idx, gpu_fd))
     print(f"FD on the GPU FP32 forward (reported): worst rel err {worst_gpu:.2e}")
     print(f"autograd: vs oracle {e_or:.2e}, worst FD rel err {worst:.2e}")
-    assert e_or <= 1e-4
+    assert e_or <= 1e-5
     assert worst <= 1e-3
 
 
@@ -87,13 +87,14 @@ def test_image_autograd_gradients(dev):
     et = np.abs(theta.grad.cpu().numpy() - wt).max() / np.abs(wt).max()
     ei = np.abs(x.grad.cpu().numpy() - wi).max() / np.abs(wi).max()
     print(f"image autograd: dtheta {et:.2e} dinput {ei:.2e}")
-    assert et <= 1e-4 and ei <= 1e-5
+    assert et <= 1e-5 and ei <= 1e-5
 
 
 def test_image_autograd_bf16_input(dev):
     """A BF16 image: the forward reads BF16 and writes BF16; the adjoint reads
     the image widened to FP32 (exact), so dTheta and dX equal the oracle's on
-    the BF16-rounded image; dX comes back in BF16."""
+    the BF16-rounded image and the BF16 output gradient; dX comes back in
+    BF16."""
     from tests.gpu_util import bf16_round, rel_err, TOL_F32
     taps = [6, 5, 4]
     th = random_theta(taps, 3.0, seed=14)
@@ -106,7 +107,9 @@ def test_image_autograd_bf16_input(dev):
     assert y.dtype == torch.bfloat16
     (y.float() * torch.as_tensor(G).cuda()).sum().backward()
     assert x.grad.dtype == torch.bfloat16
-    wt, wi = A.chain_vjp(bf16_round(img), th.astype(np.float64), taps, 1, G.astype(np.float64))
+    # autograd hands the chain the gradient of its BF16 output in BF16, so the
+    # adjoint's G_L is G rounded to BF16
+    wt, wi = A.chain_vjp(bf16_round(img), th.astype(np.float64), taps, 1, bf16_round(G))
     et = rel_err(theta.grad.cpu().numpy(), wt)
     ei = rel_err(x.grad.float().cpu().numpy(), bf16_round(wi))
     print(f"image autograd bf16: dtheta {et:.2e} dinput (BF16 output) {ei:.2e}")

@@ -89,7 +89,7 @@ def test_image_backward_parity(dev, boundary, C, H, W):
     wt, wi = A.chain_vjp(img.astype(np.float64), th.astype(np.float64), taps, boundary, G.astype(np.float64))
     et, ei = rel_err(to_np(gt), wt), rel_err(to_np(gi), wi)
     print(f"backward b={boundary}: dtheta {et:.2e} dinput {ei:.2e}")
-    assert et <= 1e-4 and ei <= TOL_F32
+    assert et <= TOL_F32 and ei <= TOL_F32
 
 
 @pytest.mark.parametrize("boundary,C,H,W,radius", [
@@ -114,7 +114,7 @@ def test_image_backward_staged_input_adjoint(dev, boundary, C, H, W, radius):
     wt, wi = A.chain_vjp(img.astype(np.float64), th.astype(np.float64), taps, boundary, G.astype(np.float64))
     et, ei = rel_err(to_np(gt), wt), rel_err(to_np(gi), wi)
     print(f"staged backward b={boundary} C={C} {H}x{W} r={radius}: dtheta {et:.2e} dinput {ei:.2e}")
-    assert et <= 1e-4 and ei <= TOL_F32
+    assert et <= TOL_F32 and ei <= TOL_F32
 
 
 @pytest.mark.parametrize("boundary,taps", [(S.CLAMP, [12, 9, 17]), (S.ZERO, [16, 3])])
@@ -129,7 +129,7 @@ def test_image_backward_many_taps(dev, boundary, taps):
     out, saved = disk.disk_forward(to_dev(th), taps, to_dev(img), boundary=boundary, save=True)
     gt, gi = disk.disk_backward(to_dev(th), taps, to_dev(img), saved, to_dev(G), boundary=boundary)
     wt, wi = A.chain_vjp(img.astype(np.float64), th.astype(np.float64), taps, boundary, G.astype(np.float64))
-    assert rel_err(to_np(gt), wt) <= 1e-4 and rel_err(to_np(gi), wi) <= TOL_F32
+    assert rel_err(to_np(gt), wt) <= TOL_F32 and rel_err(to_np(gi), wi) <= TOL_F32
 
 
 @pytest.mark.parametrize("M,taps", [(31, [8, 8, 8]), (63, [12, 12, 12, 12]), (101, [7, 9, 5, 11, 6])])
@@ -142,7 +142,7 @@ def test_impulse_backward_parity(dev, M, taps):
     wt, _ = A.chain_vjp(S.impulse(M)[None], th.astype(np.float64), taps, S.ZERO, G.astype(np.float64))
     e = rel_err(to_np(gt), wt)
     print(f"impulse backward M={M}: {e:.2e}")
-    assert e <= 1e-4
+    assert e <= TOL_F32
 
 
 @pytest.mark.parametrize("C,io", [(3, torch.float32), (4, torch.float32), (3, torch.bfloat16)])
@@ -186,7 +186,7 @@ def test_image_chain_1080p_bench_configuration(dev):
     wt, wi = A.chain_vjp(img.astype(np.float64), th.astype(np.float64), taps, S.CLAMP, G.astype(np.float64))
     et, ei = rel_err(got_t, wt), rel_err(got_i, wi)
     print(f"1080p backward: dtheta {et:.2e} dinput {ei:.2e}")
-    assert et <= 1e-4 and ei <= TOL_F32
+    assert et <= TOL_F32 and ei <= TOL_F32
 
 
 def test_backward_deterministic(dev):

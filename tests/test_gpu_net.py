@@ -168,10 +168,12 @@ def _exact_inputs(B, seed):
     return np.random.default_rng(seed).integers(0, 16, (B, 64, 64)).astype(np.float32)
 
 
-def test_predict_exact_integer_network_bitwise(dev):
+@pytest.mark.parametrize("B", [67, 4096])
+def test_predict_exact_integer_network_bitwise(dev, B):
     """Integer-valued network (exact arithmetic on both sides): the GPU output
-    equals the oracle's bit for bit; hw = 32 keeps the offset scaling exact."""
-    B = 67
+    equals the oracle's bit for bit; hw = 32 keeps the offset scaling exact.
+    B = 4096 is the launch the benchmark times (first-convolution kernel, XCD
+    tile order over 16 384 rows of conv 2)."""
     p = _exact_params(50)
     x = _exact_inputs(B, 51)
     bits, xval = _bf16_bits(x)
@@ -185,12 +187,15 @@ def test_predict_exact_integer_network_bitwise(dev):
     np.testing.assert_array_equal(th.cpu().numpy().astype(np.float64), want)
 
 
-def test_train_step_exact_integer_network_bitwise(dev):
+@pytest.mark.parametrize("B", [37, 4096])
+def test_train_step_exact_integer_network_bitwise(dev, B):
     """Same integer network; labels chosen (from the oracle's own forward) so
     that dL/dy_hat = r / 4 with small integers r: loss gradient, every weight
     and bias gradient match the oracle bit for bit, and the Adam update agrees
-    to FP32 rounding."""
-    B = 37
+    to FP32 rounding.  B = 4096 is the benchmark's training launch (split-K
+    weight-gradient reduction over 4096 samples, parity-class input-gradient
+    GEMMs over the full batch).  Every gradient term is a multiple of 1/4, and
+    the FP64 gradient is checked to be FP32-exact, as in the smaller case."""
     n = B * 144
     p = _exact_params(52)
     x = _exact_inputs(B, 53)

@@ -180,6 +180,162 @@ def test_bench_batch_sampled_trajectories(dev):
         assert abs(ps[b] - ps_o) < 0.1, (b, sides[b], ps[b], ps_o)
 
 
+def test_bench_batch_one_step_all_targets(dev):
+    """The time-to-40 dB launch (4096 targets, odd sides 15..127, 4 x 12 taps,
+    seed 7, radial init), one Adam step, every target against the oracle:
+    components whose gradient is above 1e-3 of the target's largest move by
+    exactly lr in the oracle's direction (1e-6), every component within lr."""
+    from tests import oracle_pool
+    batch = mixed_batch(4096, seed=7, fixed_L=4, fixed_N=12)
+    th0 = _theta0(batch)
+    desc, _, _ = pack_targets(batch)
+    say("opt bench batch 4096 x 1 step")
+    th, ps, st, stat = _run(batch, th0, max_steps=1, lr0=1e-2, lr1=1e-3)
+    assert np.all(st == 1) and np.all(stat == 0)
+    rows = [(int(desc[b, 3]), int(np.sum(batch.taps[b]))) for b in range(batch.B)]
+    res = oracle_pool.one_step_all([k for k in batch.kernels], [th0[o:o + T] for o, T in rows], batch.taps, 1e-2)
+    worst = 0.0
+    for b, ((o, T), (want, g)) in enumerate(zip(rows, res)):
+        got = th[o:o + T]
+        big = np.abs(g) > 1e-3 * np.abs(g).max()
+        e = float(np.abs(got[big] - want[big]).max())
+        worst = max(worst, e)
+        assert e <= 1e-6, (b, e)
+        assert np.abs(got - want).max() <= 1e-2 + 1e-6, b
+    print(f"4096 targets, one step: worst |dTheta| on well-determined components {worst:.2e}")
+
+
+def _jittered(batch, seed, sd=0.3):
+    th0 = _theta0(batch)
+    j = np.random.default_rng(seed).normal(0.0, sd, th0.shape).astype(np.float32)
+    j[:, 2] = 0.0
+    return th0 + j
+
+
+@pytest.mark.parametrize("loss", [Lo.NMSE, Lo.CHARBONNIER])
+def test_loss_and_theta_trajectory_vs_oracle(dev, loss):
+    """Three targets (sides 21..45, 4 x 12 and 3 x 8 taps) from a jittered
+    radial start (no symmetric zero gradients): after 5, 10 and 20 steps the
+    reported loss agrees with the oracle's to 2e-5 relative, the PSNR to
+    0.01 dB, and Theta element by element (offsets 1e-3 px, weights 2e-6).
+    Bars: FP32 gradients perturbed by 1e-6 relative move the FP64 iterate by
+    <= 2e-4 px and 3e-7 in the weights over 20 steps; a Charbonnier epsilon
+    10 % off moves the weights by 5e-6 and the loss by 1e-5 relative."""
+    for seed, L, N in ((61, 4, 12), (62, 3, 8)):
+        batch = mixed_batch(3, seed=seed, side=(21, 45), fixed_L=L, fixed_N=N)
+        th0 = _jittered(batch, seed)
+        desc, tp, tg = pack_targets(batch)
+        bt = disk.make_batch(desc, tp, tg)
+        for n in (5, 10, 20):
+            say("opt trajectory", loss, seed, n)
+            th = torch.as_tensor(th0).cuda().contiguous()
+            lo = torch.empty(batch.B, device="cuda")
+            ps, st, stat = disk.disk_optimize_batch(bt, th, disk.OptParams(max_steps=n, lr0=1e-2, lr1=1e-3,
+                                                                           loss=loss),
+                                                    state=disk.OptState(loss=lo))
+            th, ps, lo = th.cpu().numpy().astype(np.float64), ps.cpu().numpy(), lo.cpu().numpy()
+            p = Ad.OptParams(max_steps=n, lr0=1e-2, lr1=1e-3, loss=loss)
+            for b in range(batch.B):
+                o, T = int(desc[b, 3]), int(np.sum(batch.taps[b]))
+                K = batch.kernels[b].astype(np.float64)
+                tho, ps_o, st_o = Ad.optimize(K, th0[o:o + T], batch.taps[b], p)
+                lo_o, _, _ = A.impulse_loss_grad(K, tho, batch.taps[b], loss)
+                d = np.abs(th[o:o + T] - tho)
+                print(f"loss {loss} seed {seed} target {b} {n} steps: loss {lo[b]:.7e} / {lo_o:.7e}, "
+                      f"PSNR {ps[b]:.4f} / {ps_o:.4f}, dOffsets {d[:, :2].max():.1e} dWeights {d[:, 2].max():.1e}")
+                assert abs(lo[b] - lo_o) <= 2e-5 * lo_o
+                assert abs(ps[b] - ps_o) <= 0.01
+                assert d[:, :2].max() <= 1e-3 and d[:, 2].max() <= 2e-6
+
+
+def test_half_width_offset_units_vs_oracle(dev):
+    """Offsets' learning rate in units of the target's half-width: 10 steps on
+    four mixed targets against the oracle (PSNR 0.01 dB, offsets 1e-3 px,
+    weights 2e-6)."""
+    batch = mixed_batch(4, seed=63, side=(15, 63), fixed_L=4, fixed_N=12)
+    th0 = _jittered(batch, 63)
+    desc, _, _ = pack_targets(batch)
+    say("opt half-width units")
+    th, ps, st, stat = _run(batch, th0, max_steps=10, lr0=3e-3, lr1=1e-3, offset_units=disk.OFFSETS_HALF_WIDTH)
+    p = Ad.OptParams(max_steps=10, lr0=3e-3, lr1=1e-3, offset_units=1)
+    for b in range(batch.B):
+        o, T = int(desc[b, 3]), int(np.sum(batch.taps[b]))
+        tho, ps_o, _ = Ad.optimize(batch.kernels[b].astype(np.float64), th0[o:o + T], batch.taps[b], p)
+        d = np.abs(th[o:o + T] - tho)
+        print(f"half-width units target {b} side {batch.kernels[b].shape[0]}: PSNR {ps[b]:.4f} / {ps_o:.4f}, "
+              f"dOffsets {d[:, :2].max():.1e} dWeights {d[:, 2].max():.1e}")
+        assert st[b] == 10 and abs(ps[b] - ps_o) <= 0.01
+        assert d[:, :2].max() <= 1e-3 and d[:, 2].max() <= 2e-6
+
+
+def test_resume_and_launch_shapes_are_bitwise(dev):
+    """A 20-step run split into 7 + 13 updates that carry the Adam moments and
+    the schedule position equals the uninterrupted run bit for bit (Theta,
+    moments, PSNR, loss, steps); so does every launch shape (1..4 resident
+    work-groups per CU: each target's arithmetic is independent of which
+    work-group runs it)."""
+    batch = mixed_batch(40, seed=64, side=(15, 95))
+    th0 = _jittered(batch, 64)
+    desc, tp, tg = pack_targets(batch)
+    bt = disk.make_batch(desc, tp, tg)
+    B = batch.B
+    prm = disk.OptParams(max_steps=20, lr0=1e-2, lr1=1e-3)
+
+    def fresh():
+        th = torch.as_tensor(th0).cuda().contiguous()
+        return th, torch.zeros_like(th), torch.zeros_like(th), torch.empty(B, device="cuda")
+
+    say("opt resume: uninterrupted")
+    th_a, m_a, v_a, lo_a = fresh()
+    ps_a, st_a, stat_a = disk.disk_optimize_batch(bt, th_a, prm, state=disk.OptState(m_a, v_a, loss=lo_a))
+    say("opt resume: 7 + 13")
+    th_b, m_b, v_b, lo_b = fresh()
+    _, st1, _ = disk.disk_optimize_batch(bt, th_b, prm, state=disk.OptState(m_b, v_b, loss=lo_b, max_updates=7))
+    assert np.all(st1.cpu().numpy() == 7)
+    ps_b, st_b, stat_b = disk.disk_optimize_batch(bt, th_b, prm, state=disk.OptState(m_b, v_b, start_step=st1,
+                                                                                      loss=lo_b))
+    for x, y in ((th_a, th_b), (m_a, m_b), (v_a, v_b), (lo_a, lo_b), (ps_a, ps_b), (st_a, st_b)):
+        np.testing.assert_array_equal(x.cpu().numpy(), y.cpu().numpy())
+    assert np.all(st_b.cpu().numpy() == 20)
+    for w in (1, 2, 3, 4):
+        say("opt launch shape", w)
+        th_c = torch.as_tensor(th0).cuda().contiguous()
+        ps_c, st_c, _ = disk.disk_optimize_batch(bt, th_c, prm, tune=disk.opt_tune(w))
+        np.testing.assert_array_equal(th_c.cpu().numpy(), th_a.cpu().numpy())
+        np.testing.assert_array_equal(ps_c.cpu().numpy(), ps_a.cpu().numpy())
+
+
+def test_nan_target_diverges_alone(dev):
+    """A target holding NaN: status 2 (non-finite loss) at its first
+    evaluation, no update applied, its Theta unchanged; the other targets of
+    the batch finish exactly as they do without it."""
+    batch = mixed_batch(6, seed=65, side=(15, 45))
+    th0 = _theta0(batch)
+    desc, tp, tg = pack_targets(batch)
+    tg_nan = tg.copy()
+    o2, M2 = int(desc[2, 4]), int(desc[2, 0])
+    tg_nan[o2 + (M2 * M2) // 2] = np.nan
+    prm = disk.OptParams(max_steps=15, lr0=1e-2, lr1=1e-3)
+    out = []
+    for t in (tg, tg_nan):
+        bt = disk.make_batch(desc, tp, t)
+        th = torch.as_tensor(th0).cuda().contiguous()
+        lo = torch.empty(6, device="cuda")
+        say("opt nan target", t is tg_nan)
+        ps, st, stat = disk.disk_optimize_batch(bt, th, prm, state=disk.OptState(loss=lo))
+        out.append((th.cpu().numpy(), ps.cpu().numpy(), st.cpu().numpy(), stat.cpu().numpy(), lo.cpu().numpy()))
+    (th_a, ps_a, st_a, sa, _), (th_b, ps_b, st_b, sb, lo_b) = out
+    o, T = int(desc[2, 3]), int(np.sum(batch.taps[2]))
+    assert sb[2] == 2 and st_b[2] == 0 and not np.isfinite(lo_b[2])
+    np.testing.assert_array_equal(th_b[o:o + T], th0[o:o + T])
+    keep = np.ones(len(th0), bool)
+    keep[o:o + T] = False
+    np.testing.assert_array_equal(th_b[keep], th_a[keep])
+    others = [b for b in range(6) if b != 2]
+    assert np.all(sb[others] == 0) and np.all(st_b[others] == 15)
+    np.testing.assert_array_equal(ps_b[others], ps_a[others])
+
+
 def test_stopping_rule_and_invalid_target(dev):
     batch = mixed_batch(3, seed=5, side=(15, 31))
     th0 = _theta0(batch)
@@ -278,3 +434,32 @@ def test_fit_basis_exact_dilations_take_no_steps(dev):
                                        disk.OptParams(max_steps=50, psnr_stop_db=100.0))
     assert list(st.cpu().numpy()) == [0, 0, 0, 0], (st, ps)
     assert list(stat.cpu().numpy()) == [1, 1, 1, 1]
+
+
+def test_graph_captured_batch_replays(dev):
+    """The persistent optimiser captured once into a HIP graph (queue order +
+    optimiser launch) and replayed three times, each replay after eager work
+    and a fresh Theta_0 copied into the captured buffer: every replay equals
+    the eager call bit for bit (Theta, PSNR, steps, status)."""
+    batch = mixed_batch(64, seed=66, side=(15, 127), fixed_L=4, fixed_N=12)
+    th0 = torch.as_tensor(_theta0(batch)).cuda()
+    desc, tp, tg = pack_targets(batch)
+    bt = disk.make_batch(desc, tp, tg)
+    prm = disk.OptParams(max_steps=30, lr0=1e-2, lr1=1e-3, psnr_stop_db=25.0)
+    say("opt eager for the graph")
+    th_e = th0.clone()
+    ps_e, st_e, sa_e = disk.disk_optimize_batch(bt, th_e, prm)
+    want = [t.cpu().numpy() for t in (th_e, ps_e, st_e, sa_e)]
+    th_g = th0.clone()
+    ws = torch.empty(disk.optimize_workspace_size(bt), dtype=torch.uint8, device="cuda")
+    say("opt graph capture")
+    cap = disk.Captured(lambda: disk.disk_optimize_batch(bt, th_g, prm, ws=ws), warmup=False)
+    for r in range(3):
+        th_g.copy_(th0)
+        disk.disk_init_radial(bt)                      # unrelated eager work between replays
+        torch.cuda.synchronize()
+        say("opt graph replay", r)
+        ps, st, sa = cap.replay()
+        torch.cuda.synchronize()
+        for got, w in zip((th_g, ps, st, sa), want):
+            np.testing.assert_array_equal(got.cpu().numpy(), w)

@@ -227,3 +227,34 @@ def test_optimize_stops_before_the_update_that_would_pass_the_threshold():
     th_k, _, _ = Ad.optimize(target, start, taps, Ad.OptParams(max_steps=k + 1, lr0=2e-2, lr1=2e-2))
     # the same k + 1 updates (constant lr, so the schedule length does not matter)
     np.testing.assert_array_equal(th_stop, th_k)
+
+
+def test_optimize_half_width_offset_units_match_torch_param_groups():
+    """Offsets' learning rate in units of the half-width (M - 1) / 2, weights
+    at the plain rate: equal to torch.optim.Adam (float64) with two parameter
+    groups (offsets at lr * (M - 1) / 2, weights at lr) driven by the oracle's
+    gradients; a unit applied to the weights, or a wrong half-width, fails."""
+    taps = [5, 4]
+    M = 21
+    th_true = random_theta(taps, 3.0, seed=44).astype(np.float64)
+    target = S.impulse_response(M, th_true, taps)
+    start = th_true + np.random.default_rng(6).normal(0, 0.3, th_true.shape) * [1, 1, 0.05]
+    S_, lr0, lr1 = 4, 3e-3, 1e-3
+    th, ps, steps = Ad.optimize(target, start, taps, Ad.OptParams(max_steps=S_, lr0=lr0, lr1=lr1, offset_units=1))
+    off = torch.nn.Parameter(torch.tensor(start[:, :2], dtype=torch.float64))
+    w = torch.nn.Parameter(torch.tensor(start[:, 2], dtype=torch.float64))
+    opt = torch.optim.Adam([{"params": [off]}, {"params": [w]}], lr=lr0, betas=(0.9, 0.999), eps=1e-8)
+    for s in range(S_):
+        cur = np.concatenate([off.detach().numpy(), w.detach().numpy()[:, None]], axis=1)
+        _, _, g = A.impulse_loss_grad(target, cur, taps)
+        lr = lr0 + (lr1 - lr0) * s / (S_ - 1)
+        opt.param_groups[0]["lr"] = lr * (M - 1) / 2
+        opt.param_groups[1]["lr"] = lr
+        off.grad = torch.tensor(g[:, :2], dtype=torch.float64)
+        w.grad = torch.tensor(g[:, 2], dtype=torch.float64)
+        opt.step()
+    want = np.concatenate([off.detach().numpy(), w.detach().numpy()[:, None]], axis=1)
+    np.testing.assert_allclose(th, want, rtol=1e-13, atol=1e-15)
+    # and the offsets did move further than the pixel-unit run's
+    th_px, _, _ = Ad.optimize(target, start, taps, Ad.OptParams(max_steps=S_, lr0=lr0, lr1=lr1))
+    assert np.abs(th[:, :2] - start[:, :2]).sum() > 5 * np.abs(th_px[:, :2] - start[:, :2]).sum()
