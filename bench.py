@@ -41,6 +41,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--frames", type=int, default=8, help="frames per step (one captured call over all of them)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--basis", choices=["fitted", "random"], default="fitted")
     ap.add_argument("--no-time-to-40db", action="store_true")
@@ -80,15 +81,98 @@ def build_basis(torch, disk, kind):
     return theta.contiguous(), info
 
 
-def cpu_baseline(basis_np, img, P):
-    """The FP64 oracle on a bounded sample of the same workload: the whole
-    frame, all 4 passes, single-threaded."""
+def _oracle_band(job):
+    """One row band of the FP64 oracle's SV chain (the bench's CPU-baseline
+    leg; spawned worker, single-threaded)."""
+    img, P, basis, y0, y1, m = job
     from oracle import svfilter as SV
+    a, b = max(0, y0 - m), min(img.shape[1], y1 + m)
+    out = SV.sv_chain(img[:, a:b], P[:, a:b], basis, [G], TAPS)
+    return y0, out[:, y0 - a:y1 - a]
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(basis_np, img, P, halo):
+    """The FP64 oracle on the whole frame, all 4 passes, over row bands on
+    every host core (spawned single-threaded processes; each band carries a
+    margin of the summed halos, which the CLAMP edge of a band cannot reach
+    through, so the interior rows are the full-frame oracle's)."""
+    import multiprocessing as mp
+    from concurrent.futures import ProcessPoolExecutor
+    workers = max(1, min(16, os.cpu_count() or 1))
+    m = int(sum(halo))
+    bands = np.linspace(0, H, workers + 1).astype(int)
+    jobs = [(img.astype(np.float64), P.astype(np.float64), basis_np.astype(np.float64), int(bands[i]),
+             int(bands[i + 1]), m) for i in range(workers)]
+    env = {k: os.environ.get(k) for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS")}
+    for k in env:
+        os.environ[k] = "1"
+    try:
+        with ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("spawn")) as ex:
+            ex.submit(int, 0).result()          # workers up before the clock starts
+            t = time.perf_counter()
+            parts = list(ex.map(_oracle_band, jobs))
+            dt = time.perf_counter() - t
+    finally:
+        for k, v in env.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+    return {"value": H * W / dt / 1e6, "unit": "Mpix/s", "cores": workers, "kind": "oracle",
+            "cpu": cpu_model(), "host_cpus": os.cpu_count(),
+            "sample": f"the full frame ({H}x{W}x{C}), 4 passes, FP64 numpy, {workers} row bands with "
+                      f"{m}-row margins on {workers} single-threaded processes, {dt:.1f} s"}
+
+
+def oracle_timings():
+    """The FP64 oracle on bounded samples of the other workloads, one process
+    (single-threaded numpy), extrapolated per target-step where the whole run
+    would take hours; the GPU figures sit beside them in the result."""
+    from oracle import adam as Ad, adjoint as A, init as I, sparse as S
+    from synth import gaussian_kernel, mixed_batch, shape_batch, uniform_image
+    out = {"cores": 1, "cpu": cpu_model()}
+    # tiny: one 31 x 31 Gaussian, 3 x 8 taps, 300 steps, then a 256 x 256 image (whole run)
+    K = gaussian_kernel(31, 6.0).astype(np.float64)
+    taps = [8, 8, 8]
     t = time.perf_counter()
-    SV.sv_chain(img.astype(np.float64), P.astype(np.float64), basis_np.astype(np.float64), [G], TAPS)
-    dt = time.perf_counter() - t
-    return {"value": H * W / dt / 1e6, "unit": "Mpix/s", "cores": 1, "kind": "oracle",
-            "sample": f"the full frame ({H}x{W}x{C}), 4 passes, FP64 numpy, {dt:.1f} s single-threaded"}
+    th, ps, _ = Ad.optimize(K, I.radial_init(K, taps), taps, Ad.OptParams(max_steps=300, lr0=1e-2, lr1=1e-2))
+    S.chain(uniform_image(256, 256, 1, seed=1).astype(np.float64), th, taps, S.CLAMP)
+    out["tiny_31x31_3x8_300_steps"] = {"seconds": round(time.perf_counter() - t, 2), "psnr_db": round(ps, 2),
+                                       "sample": "the whole run"}
+    # shapes: 2 targets x 10 steps of the 256 x 500-step run
+    b = shape_batch(2, 63, 4, 12, seed=4)
+    t = time.perf_counter()
+    for k in b.kernels:
+        k = k.astype(np.float64)
+        Ad.optimize(k, I.radial_init(k, [12] * 4), [12] * 4, Ad.OptParams(max_steps=10, lr0=1e-2, lr1=1e-3,
+                                                                           offset_units=1))
+    per = (time.perf_counter() - t) / 20
+    out["shapes_63x63_x256_500_steps"] = {"seconds_per_target_step": round(per, 4),
+                                          "extrapolated_seconds": round(per * 256 * 500, 1),
+                                          "sample": "2 targets x 10 steps"}
+    # batch: 16 targets of the 4096-target batch, 2 gradient evaluations each
+    mb = mixed_batch(16, seed=7, fixed_L=4, fixed_N=12)
+    t = time.perf_counter()
+    for k, tp in zip(mb.kernels, mb.taps):
+        k = k.astype(np.float64)
+        th0 = I.radial_init(k, tp)
+        for _ in range(2):
+            A.impulse_loss_grad(k, th0, tp)
+    per = (time.perf_counter() - t) / 32
+    out["batch_4096_x1000_steps"] = {"seconds_per_target_step": round(per, 4),
+                                     "extrapolated_seconds": round(per * 4096 * 1000, 1),
+                                     "sample": "16 targets x 2 steps (sides 15..127)"}
+    return out
 
 
 def source_code_bytes(path):
@@ -160,7 +244,8 @@ def sv2d_4k(torch, disk, steps=20):
     t = time.perf_counter()
     xin, hw = disk.disk_net_prepare_inputs(bt)
     theta = disk.disk_net_scatter_theta(bt, disk.disk_init_predict(train_init.load(), xin, hw))
-    ps, _, _ = disk.disk_optimize_batch(bt, theta, disk.OptParams(max_steps=300, lr0=1e-2, lr1=1e-3))
+    ps, _, _ = disk.disk_optimize_batch(bt, theta, disk.OptParams(max_steps=300, lr0=1e-2, lr1=1e-3,
+                                                                  offset_units=disk.OFFSETS_HALF_WIDTH))
     torch.cuda.synchronize()
     build_s = time.perf_counter() - t
     basis = disk.make_basis(theta.view(64, 48, 3).contiguous(), taps, [8, 8])
@@ -192,7 +277,7 @@ def small_workloads(torch, disk):
     (sigma 6), 3 x 8 taps, radial init, 300 Adam steps at lr 1e-2, then the
     fitted filter on a 256 x 256 U[0,1) image (CLAMP).  shapes: 256 polygon /
     ring / star targets of 63 x 63, 4 x 12 taps, shape-aware init (host), 500
-    steps, lr 1e-2 -> 1e-3."""
+    steps, lr 1e-2 -> 1e-3 (offsets' rate in half-width units)."""
     from synth import gaussian_kernel, shape_batch, uniform_image
     out = {}
     taps = [8, 8, 8]
@@ -220,7 +305,8 @@ def small_workloads(torch, disk):
     th = th.cuda().contiguous()
     torch.cuda.synchronize()
     t = time.perf_counter()
-    ps, st, _ = disk.disk_optimize_batch(bt, th, disk.OptParams(max_steps=500, lr0=1e-2, lr1=1e-3))
+    ps, st, _ = disk.disk_optimize_batch(bt, th, disk.OptParams(max_steps=500, lr0=1e-2, lr1=1e-3,
+                                                                offset_units=disk.OFFSETS_HALF_WIDTH))
     torch.cuda.synchronize()
     sec = time.perf_counter() - t
     ps = ps.cpu().numpy()
@@ -234,13 +320,14 @@ def ablations(torch, disk):
     paper's init comparison and its layers x samples trade-off), and the
     paper's own optimisation recipe.  Targets: 256 hexagon / pentagon / ring /
     star kernels of 63 x 63 (seed 4), 4 x 12 taps, 500 Adam steps at lr
-    1e-2 -> 1e-3, normalised MSE, unless stated."""
+    1e-2 -> 1e-3 with the offsets' rate in half-width units, normalised MSE,
+    unless stated."""
     from synth import shape_batch
     from paper_2512_04556_amd import train_init
     taps = [12, 12, 12, 12]
     b = shape_batch(256, 63, 4, 12, seed=4)
     bt = disk.make_batch(*disk.pack_targets(b.kernels, taps))
-    prm = disk.OptParams(max_steps=500, lr0=1e-2, lr1=1e-3)
+    prm = disk.OptParams(max_steps=500, lr0=1e-2, lr1=1e-3, offset_units=disk.OFFSETS_HALF_WIDTH)
 
     def run(theta, p=prm, batch=bt):
         th = theta.cuda().contiguous()
@@ -260,8 +347,10 @@ def ablations(torch, disk):
     except (OSError, ValueError):
         pass
     out["init"] = {k: run(v) for k, v in inits.items()}
-    # the paper's recipe: Charbonnier loss, lr 1e-3 -> 1e-4 over 1000 steps (shape-aware init)
-    paper = disk.OptParams(max_steps=1000, lr0=1e-3, lr1=1e-4, loss=disk.LOSS_CHARBONNIER, charb_eps=1e-3)
+    # the paper's recipe: Charbonnier loss, lr 1e-3 -> 1e-4 over 1000 steps (shape-aware init,
+    # offsets in half-width units, i.e. normalised sampling coordinates)
+    paper = disk.OptParams(max_steps=1000, lr0=1e-3, lr1=1e-4, loss=disk.LOSS_CHARBONNIER, charb_eps=1e-3,
+                           offset_units=disk.OFFSETS_HALF_WIDTH)
     out["paper_recipe_charbonnier_1e-3"] = run(inits["shape_aware"], paper)
     # layers x samples at a fixed budget of 48 taps, rings (radial init)
     rings = shape_batch(64, 63, 4, 12, seed=9, kinds=("ring",))
@@ -408,53 +497,71 @@ def network_mfma(torch, disk, steps=20):
 def time_to_40db(torch, disk, n=4096):
     """Batched optimisation of n fresh targets (odd sides 15..127, the shape
     families of the batching workload, 4 layers x 12 taps, seed 7) to 40 dB or
-    1000 Adam steps, from the radial initialisation and from the learned one
-    (its inference included).  Times come from the device clock stamped at
-    each target's finish, plus the initialisation time."""
+    1000 Adam steps (lr 1e-2 -> 1e-3, offsets' rate in half-width units), from
+    the radial initialisation and from the learned one (its inference
+    included), in one persistent launch each.  Finish times come from the
+    device clock stamped at each target's finish, plus the initialisation
+    time.  With K the smaller of the two counts of targets that reach 40 dB,
+    the comparison is the time until K/4, K/2 and K targets of each path have
+    reached it; PSNR after 100 steps is reported for both as well."""
     from synth import mixed_batch, pack_targets
     from paper_2512_04556_amd import train_init
     b = mixed_batch(n, seed=7, fixed_L=4, fixed_N=12)
     bt = disk.make_batch(*pack_targets(b))
-    prm = disk.OptParams(max_steps=1000, lr0=1e-2, lr1=1e-3, psnr_stop_db=40.0)
+    prm = disk.OptParams(max_steps=1000, **train_init.FIT)
     rate = disk.clock_rate_khz() * 1e3
-    res = {"targets": n, "max_steps": 1000, "stop_db": 40.0}
+    res = {"targets": n, "max_steps": 1000, "stop_db": 40.0, "lr": [prm.c.lr0, prm.c.lr1],
+           "offset_units": "half-width"}
     try:
         weights = train_init.load()
     except (OSError, ValueError) as e:
         weights = None
         res["learned_missing"] = str(e)
+    fins = {}
+    ws = torch.empty(disk.optimize_workspace_size(bt), dtype=torch.uint8, device="cuda")
     for kind in ("radial", "learned"):
         if kind == "learned" and weights is None:
             continue
         stream = torch.cuda.current_stream()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         ticks = torch.zeros(n + 1, dtype=torch.int64, device="cuda")
+
+        def init():
+            if kind == "radial":
+                return disk.disk_init_radial(bt)
+            x, hw = disk.disk_net_prepare_inputs(bt)
+            return disk.disk_net_scatter_theta(bt, disk.disk_init_predict(weights, x, hw))
+
+        th100 = init()
+        ps100, _, _ = disk.disk_optimize_batch(bt, th100, disk.OptParams(max_steps=100, **train_init.FIT), ws=ws)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         e0.record(stream)
-        if kind == "radial":
-            th = disk.disk_init_radial(bt)
-        else:
-            x, hw = disk.disk_net_prepare_inputs(bt)
-            th = disk.disk_net_scatter_theta(bt, disk.disk_init_predict(weights, x, hw))
+        th = init()
         e1.record(stream)
-        ps, st, status = disk.disk_optimize_batch(bt, th, prm, ticks)
+        ps, st, status = disk.disk_optimize_batch(bt, th, prm, ticks, ws=ws)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         init_s = e0.elapsed_time(e1) * 1e-3
         tk = ticks.cpu().numpy()
         fin = init_s + (tk[:n] - tk[n]) / rate
-        ps, st = ps.cpu().numpy(), st.cpu().numpy()
-        ok = np.sort(fin[ps >= 40.0])
-
-        def t_frac(f):
-            k = int(np.ceil(f * n))
-            return round(float(ok[k - 1]), 4) if len(ok) >= k else None
-
+        ps, st, ps100 = ps.cpu().numpy(), st.cpu().numpy(), ps100.cpu().numpy()
+        fins[kind] = np.sort(fin[ps >= 40.0])
         res[kind] = {"wall_s": round(wall, 3), "init_ms": round(init_s * 1e3, 3),
                      "reached_40db": int(np.sum(ps >= 40.0)), "median_steps": float(np.median(st)),
-                     "t50_s": t_frac(0.5), "t90_s": t_frac(0.9), "t_last_40db_s": round(float(ok[-1]), 4) if len(ok) else None,
-                     "median_psnr_db": round(float(np.median(ps)), 2), "mean_psnr_db": round(float(np.mean(ps)), 2)}
+                     "median_steps_of_reached": float(np.median(st[ps >= 40.0])) if np.any(ps >= 40.0) else None,
+                     "median_psnr_db": round(float(np.median(ps)), 2), "mean_psnr_db": round(float(np.mean(ps)), 2),
+                     "median_psnr_db_after_100_steps": round(float(np.median(ps100)), 2),
+                     "reached_40db_after_100_steps": int(np.sum(ps100 >= 40.0))}
+    if len(fins) == 2:
+        K = min(len(fins["radial"]), len(fins["learned"]))
+        if K > 0:
+            cmp = {"K": K}
+            for name, k in (("quarter", max(1, K // 4)), ("half", max(1, K // 2)), ("all", K)):
+                r, l = float(fins["radial"][k - 1]), float(fins["learned"][k - 1])
+                cmp[f"t_{name}_s"] = {"radial": round(r, 4), "learned": round(l, 4),
+                                      "learned_speedup": round(r / l, 3)}
+            res["time_to_K_targets_at_40db"] = cmp
     return res
 
 
@@ -502,48 +609,71 @@ def main():
         for _ in range(50):
             disk.disk_sv_filter(basis, x, p, out=out, ws=ws)
         torch.cuda.synchronize()
+
+    # single frames, eager calls (one disk_sv_filter per frame)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     for _ in range(a.warmup):
         disk.disk_sv_filter(basis, x, p, out=out, ws=ws)
     torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    t0 = time.perf_counter()
     e0.record(stream)
     for _ in range(a.steps):
         disk.disk_sv_filter(basis, x, p, out=out, ws=ws)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    single_ms = e0.elapsed_time(e1) / a.steps
+
+    # The step: F frames (a panning sequence: frame f is the image shifted by
+    # 37 f px) in one disk_sv_filter_frames call, captured once into a HIP
+    # graph and replayed; each of the 4 passes covers all F frames in one
+    # launch.
+    F = a.frames
+    xf = torch.stack([torch.roll(x, shifts=37 * f, dims=2) for f in range(F)]).contiguous()
+    outf = torch.empty_like(xf)
+    wsf = disk.sv_frames_workspace(basis, F, C, H, W)
+    cap = disk.Captured(lambda: disk.disk_sv_filter_frames(basis, xf, p, out=outf, ws=wsf))
+    for _ in range(a.warmup):
+        cap.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(a.steps):
+        cap.replay()
     e1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms = wall * 1e3 / a.steps
     ev_ms = e0.elapsed_time(e1) / a.steps
 
-    # the dominant kernel: the gather pass, timed alone (prepared table, L passes per call)
-    table = disk.disk_sv_prepare(basis)
-    aws = torch.empty(int(ws.numel()), dtype=torch.uint8, device="cuda")
-    for _ in range(5):
-        disk.disk_sv_apply(basis, table, x, p, out=out, ws=aws)
+    # the dominant kernel: the gather pass over the F frames, timed alone on
+    # the launch stream (4 launches per call)
+    for _ in range(3):
+        disk.disk_sv_filter_frames(basis, xf, p, out=outf, ws=wsf)
     torch.cuda.synchronize()
     e0.record(stream)
     for _ in range(a.steps):
-        disk.disk_sv_apply(basis, table, x, p, out=out, ws=aws)
+        disk.disk_sv_filter_frames(basis, xf, p, out=outf, ws=wsf)
     e1.record(stream)
     torch.cuda.synchronize()
     pass_ms = e0.elapsed_time(e1) / (a.steps * len(TAPS))
-    pass_bytes = PASS_BYTES_PER_PX * H * W
+    pass_bytes = PASS_BYTES_PER_PX * H * W * F
     achieved = pass_bytes / (pass_ms * 1e-3) / 1e9
-    ops_per_launch = OPS_PER_PX_TAP * TAPS[0] * H * W
+    ops_per_launch = OPS_PER_PX_TAP * TAPS[0] * H * W * F
     ops_achieved = ops_per_launch / (pass_ms * 1e-3) / 1e12
 
-    mpix = H * W / (ms * 1e-3) / 1e6
-    frame_bytes = len(TAPS) * pass_bytes
+    mpix = F * H * W / (ms * 1e-3) / 1e6
+    frame_bytes = len(TAPS) * PASS_BYTES_PER_PX * H * W
     res = {
         "metric": METRIC, "value": round(mpix, 1), "unit": "Mpix/s", "n_gpus": 1, "steps": a.steps,
         "warmup": a.warmup, "ms_per_step": round(ms, 5), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "sv_filter_1080p_f32", "H": H, "W": W, "C": C, "layers": len(TAPS),
                    "taps_per_layer": TAPS[0], "basis_entries": G, "basis": a.basis,
-                   "halo": basis.halo},
-        "hbm_frac_frame": round(frame_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                   "halo": basis.halo, "frames_per_step": F, "launch": "hip graph replay, 4 launches per step"},
+        "hbm_frac_frame": round(F * frame_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
         "event_ms_per_step": round(ev_ms, 5),
+        "single_frame": {"ms_per_frame": round(single_ms, 5), "mpix_s": round(H * W / single_ms / 1e3, 1),
+                         "hbm_frac": round(frame_bytes / (single_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                         "launch": "eager disk_sv_filter per frame"},
         # Arithmetic intensity 28 ops x 8 taps / 28 bytes = 8 ops/B, just below
         # the machine balance 78.6 T / 8 TB/s = 9.8 ops/B: the HBM roof is the
         # lower one (barely); the ALU figures are reported beside it.
@@ -556,7 +686,7 @@ def main():
     }
     if fit_info:
         res["config"]["basis_fit"] = fit_info
-    res["dense_reference"] = dense_reference(torch, disk, x, p, out, ms)
+    res["dense_reference"] = dense_reference(torch, disk, x, p, out, single_ms)
     res["small_workloads"] = small_workloads(torch, disk)
     if not a.no_2d:
         res["angle_effects_1080p"] = angle_effects(torch, disk)
@@ -573,7 +703,8 @@ def main():
     if not a.no_time_to_40db:
         res["time_to_40db"] = time_to_40db(torch, disk)
     if not a.no_cpu_baseline:
-        res["cpu_baseline"] = cpu_baseline(basis_t.cpu().numpy(), img, P)
+        res["cpu_baseline"] = cpu_baseline(basis_t.cpu().numpy(), img, P, basis.halo)
+        res["oracle_timings"] = oracle_timings()
     print(json.dumps(res), flush=True)
 
 

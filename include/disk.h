@@ -306,6 +306,24 @@ disk_status disk_sv_filter(const disk_basis* b, const float* basis_theta, const 
                            const float* pmap, void* out, int32_t C, int32_t H, int32_t W,
                            disk_dtype io, void* ws, size_t ws_bytes, hipStream_t stream);
 
+/*
+ * The same filter over F frames at once (a video's frames, or a batch of
+ * images of one size): images and outs are device [F][C][H][W] of dtype io;
+ * pmaps is device float [F][dims][H][W] (pmap_per_frame != 0) or one
+ * [dims][H][W] map shared by every frame.  Each of the L passes covers all F
+ * frames in one launch, so a launch's start-up and tail are paid once per F
+ * frames (the chain of Sec. 4.3 applied frame by frame; results identical to
+ * F calls of disk_sv_filter).  1 <= F <= DISK_MAX_FRAMES; ws holds the two
+ * FP32 intermediates of all F frames.
+ */
+#define DISK_MAX_FRAMES 64
+size_t disk_sv_filter_frames_workspace_size(const disk_basis* b, int32_t F, int32_t C, int32_t H,
+                                            int32_t W, disk_dtype io);
+disk_status disk_sv_filter_frames(const disk_basis* b, const float* basis_theta, const void* images,
+                                  const float* pmaps, int32_t pmap_per_frame, void* outs, int32_t F,
+                                  int32_t C, int32_t H, int32_t W, disk_dtype io, void* ws,
+                                  size_t ws_bytes, hipStream_t stream);
+
 
 /*
  * Angle axis for a 2-D basis (the angle-driven effects, rotational bokeh and

@@ -15,7 +15,7 @@ import torch
 
 __all__ = [
     "lib", "DiskError", "ZERO", "CLAMP", "F32", "BF16", "LOSS_NMSE", "LOSS_CHARBONNIER",
-    "disk_forward", "disk_backward", "disk_sv_filter", "disk_sv_prepare", "disk_sv_apply", "Basis", "make_basis",
+    "disk_forward", "disk_backward", "disk_sv_filter", "disk_sv_filter_frames", "sv_frames_workspace", "disk_sv_prepare", "disk_sv_apply", "Basis", "make_basis",
     "disk_optimize_batch", "Captured", "OptState", "opt_tune", "optimize_workspace_size", "OFFSETS_PIXELS",
     "OFFSETS_HALF_WIDTH", "disk_init_radial", "disk_init_random", "disk_fit_basis", "pack_targets", "fit_basis", "disk_init_shape", "OptParams", "Batch", "make_batch",
     "disk_init_predict", "disk_net_train_step", "disk_net_prepare_inputs", "disk_net_scatter_theta",
@@ -101,6 +101,10 @@ def lib():
         "disk_basis_set_halo": (c_int32, [POINTER(DiskBasis), P]),
         "disk_sv_filter_workspace_size": (c_size_t, [POINTER(DiskBasis), c_int32, c_int32, c_int32, c_int32]),
         "disk_sv_filter": (c_int32, [POINTER(DiskBasis), P, P, P, P, c_int32, c_int32, c_int32, c_int32, P, c_size_t, P]),
+        "disk_sv_filter_frames_workspace_size": (c_size_t, [POINTER(DiskBasis), c_int32, c_int32, c_int32, c_int32,
+                                                            c_int32]),
+        "disk_sv_filter_frames": (c_int32, [POINTER(DiskBasis), P, P, P, c_int32, P, c_int32, c_int32, c_int32,
+                                            c_int32, c_int32, P, c_size_t, P]),
         "disk_sv_table_bytes": (c_size_t, [POINTER(DiskBasis)]),
         "disk_sv_prepare": (c_int32, [POINTER(DiskBasis), P, P, c_size_t, P]),
         "disk_sv_apply_workspace_size": (c_size_t, [POINTER(DiskBasis), c_int32, c_int32, c_int32, c_int32]),
@@ -284,6 +288,36 @@ def disk_sv_filter(basis: Basis, image, pmap, out=None, ws=None):
     _check(L.disk_sv_filter(ctypes.byref(basis.desc), _ptr(basis.theta), _ptr(image), _ptr(pmap), _ptr(out),
                             C, H, W, io, _ptr(ws), ws.numel(), _stream()))
     return out
+
+
+def disk_sv_filter_frames(basis: Basis, images, pmaps, out=None, ws=None):
+    """The filter over F frames in one call: ``images`` [F][C][H][W]
+    (f32/bf16); ``pmaps`` [dims][H][W] (shared by every frame) or
+    [F][dims][H][W]."""
+    _dev(images, "images")
+    _dev(pmaps, "pmaps")
+    _f32(pmaps, "pmaps")
+    if images.dim() != 4:
+        raise DiskError("images must be [F][C][H][W]")
+    F, C, H, W = (int(v) for v in images.shape)
+    per_frame = pmaps.dim() == 4
+    if (per_frame and (int(pmaps.shape[0]) != F or tuple(pmaps.shape[2:]) != (H, W))) or \
+            (not per_frame and tuple(pmaps.shape[1:]) != (H, W)):
+        raise DiskError(f"pmaps shape {tuple(pmaps.shape)} does not fit images {tuple(images.shape)}")
+    io = _io_dtype(images)
+    if out is None:
+        out = torch.empty_like(images)
+    L = lib()
+    nws = L.disk_sv_filter_frames_workspace_size(ctypes.byref(basis.desc), F, C, H, W, io)
+    if ws is None or ws.numel() < nws:
+        ws = _workspace(nws, images.device)
+    _check(L.disk_sv_filter_frames(ctypes.byref(basis.desc), _ptr(basis.theta), _ptr(images), _ptr(pmaps),
+                                   int(per_frame), _ptr(out), F, C, H, W, io, _ptr(ws), ws.numel(), _stream()))
+    return out
+
+
+def sv_frames_workspace(basis: Basis, F, C, H, W, io=F32, device="cuda"):
+    return _workspace(lib().disk_sv_filter_frames_workspace_size(ctypes.byref(basis.desc), F, C, H, W, io), device)
 
 
 def sv_filter_workspace(basis: Basis, C, H, W, io=F32, device="cuda"):

@@ -349,10 +349,10 @@ static size_t sv_table_bytes_of(const disk_basis* b) {
     return ((sv_table_floats(b->dims, basis_entries(b), sp.T) * sizeof(float) + 255) & ~size_t(255)) + 256;
 }
 
-static size_t sv_apply_ws(const disk_basis* b, int C, int H, int W, Carve& cv, float** b0, float** b1) {
+static size_t sv_apply_ws(const disk_basis* b, int C, int H, int W, Carve& cv, float** b0, float** b1, int F = 1) {
     const int nbuf = std::min(b->cx.L - 1, 2);
-    *b0 = nbuf >= 1 ? cv.take<float>(image_floats(C, H, W)) : nullptr;
-    *b1 = nbuf >= 2 ? cv.take<float>(image_floats(C, H, W)) : nullptr;
+    *b0 = nbuf >= 1 ? cv.take<float>(image_floats(C, H, W) * F) : nullptr;
+    *b1 = nbuf >= 2 ? cv.take<float>(image_floats(C, H, W) * F) : nullptr;
     return cv.used;
 }
 
@@ -393,7 +393,7 @@ disk_status disk_sv_prepare(const disk_basis* b, const float* basis_theta, void*
 // and its flag, or (raw != nullptr) derived by each pass from the basis.
 static disk_status sv_passes(const disk_basis* b, const void* image, const float* pmap, void* out, int C, int H,
                              int W, disk_dtype io, float* b0, float* b1, const float* tab, const int* flag,
-                             const float* raw, hipStream_t stream) {
+                             const float* raw, hipStream_t stream, Frames fr = Frames{}) {
     const LayerSpec sp = make_spec(b->cx);
     const int G0 = b->grid[0], G1 = b->dims == 2 ? b->grid[1] : 1;
     for (int l = 0; l < sp.L; ++l) {
@@ -402,7 +402,7 @@ static disk_status sv_passes(const disk_basis* b, const void* image, const float
         const int sb = (l == 0 && io == DISK_BF16) ? 1 : 0;
         const int db = (l == sp.L - 1 && io == DISK_BF16) ? 1 : 0;
         DISK_HIP(launch_sv_pass(C, b->dims, sb, src, db, dst, pmap, tab, sp.tap0[l], sp.taps[l], sp.T, G0, G1, H, W,
-                                b->halo[l], flag, raw, stream),
+                                b->halo[l], flag, raw, stream, fr),
                  "sv pass");
     }
     return ok();
@@ -430,34 +430,53 @@ disk_status disk_sv_apply(const disk_basis* b, const void* table, const void* im
     return sv_passes(b, image, pmap, out, C, H, W, io, b0, b1, tab, flag, nullptr, stream);
 }
 
-disk_status disk_sv_filter(const disk_basis* b, const float* basis_theta, const void* image, const float* pmap,
-                           void* out, int32_t C, int32_t H, int32_t W, disk_dtype io, void* ws, size_t ws_bytes,
-                           hipStream_t stream) {
+size_t disk_sv_filter_frames_workspace_size(const disk_basis* b, int32_t F, int32_t C, int32_t H, int32_t W,
+                                            disk_dtype) {
+    const size_t t = disk_sv_table_bytes(b);
+    if (!t || F < 1 || F > DISK_MAX_FRAMES) return 0;
+    Carve cv(nullptr, 0);
+    float *a, *c;
+    return t + sv_apply_ws(b, C, H, W, cv, &a, &c, F) + 256;
+}
+
+disk_status disk_sv_filter_frames(const disk_basis* b, const float* basis_theta, const void* images,
+                                  const float* pmaps, int32_t pmap_per_frame, void* outs, int32_t F, int32_t C,
+                                  int32_t H, int32_t W, disk_dtype io, void* ws, size_t ws_bytes,
+                                  hipStream_t stream) {
     DISK_TRY(check_basis(b));
     DISK_TRY(check_image(C, H, W));
+    if (F < 1 || F > DISK_MAX_FRAMES) return fail(DISK_BAD_SHAPE, "F=%d out of [1,%d]", F, DISK_MAX_FRAMES);
+    DISK_TRY(check_ptr(basis_theta, "basis_theta"));
+    DISK_TRY(check_ptr(images, "images"));
+    DISK_TRY(check_ptr(pmaps, "pmaps"));
+    DISK_TRY(check_ptr(outs, "outs"));
     DISK_TRY(check_ptr(ws, "ws", true));
+    if (io != DISK_F32 && io != DISK_BF16) return fail(DISK_INVALID_ARG, "bad dtype %d", int(io));
     const size_t tb = sv_table_bytes_of(b);
-    const size_t need = disk_sv_filter_workspace_size(b, C, H, W, io);
+    const size_t need = disk_sv_filter_frames_workspace_size(b, F, C, H, W, io);
     if (!ws || ws_bytes < need) return fail(DISK_WORKSPACE_TOO_SMALL, "workspace %zu < %zu bytes", ws_bytes, need);
-    if (image == out) return fail(DISK_INVALID_ARG, "image and out must not alias");
-    // One-shot call on a 1-D basis with C >= 3: every pass derives its layer's
-    // coefficients from the basis itself (no separate preparation launch).
+    if (images == outs) return fail(DISK_INVALID_ARG, "images and outs must not alias");
+    const Frames fr{F, pmap_per_frame ? 0 : 1};
+    Carve cv(static_cast<char*>(ws) + tb, ws_bytes - tb);
+    float *b0, *b1;
+    sv_apply_ws(b, C, H, W, cv, &b0, &b1, F);
+    // 1-D basis with C >= 3: every pass derives its layer's coefficients from
+    // the basis itself (no separate preparation launch); otherwise the table
+    // is prepared at the start of the workspace.
     const LayerSpec sp = make_spec(b->cx);
     bool raw = true;
     for (int l = 0; l < sp.L; ++l) raw = raw && sv_pass_raw_ok(C, b->dims, b->halo[l], b->grid[0], sp.taps[l]);
-    if (raw) {
-        DISK_TRY(check_ptr(basis_theta, "basis_theta"));
-        DISK_TRY(check_ptr(image, "image"));
-        DISK_TRY(check_ptr(pmap, "pmap"));
-        DISK_TRY(check_ptr(out, "out"));
-        if (io != DISK_F32 && io != DISK_BF16) return fail(DISK_INVALID_ARG, "bad dtype %d", int(io));
-        Carve cv(static_cast<char*>(ws) + tb, ws_bytes - tb);
-        float *b0, *b1;
-        sv_apply_ws(b, C, H, W, cv, &b0, &b1);
-        return sv_passes(b, image, pmap, out, C, H, W, io, b0, b1, nullptr, nullptr, basis_theta, stream);
-    }
+    if (raw) return sv_passes(b, images, pmaps, outs, C, H, W, io, b0, b1, nullptr, nullptr, basis_theta, stream, fr);
     DISK_TRY(disk_sv_prepare(b, basis_theta, ws, tb, stream));
-    return disk_sv_apply(b, ws, image, pmap, out, C, H, W, io, static_cast<char*>(ws) + tb, ws_bytes - tb, stream);
+    const float* tab = static_cast<const float*>(ws);
+    const int* flag = reinterpret_cast<const int*>(static_cast<const char*>(ws) + tb - 256);
+    return sv_passes(b, images, pmaps, outs, C, H, W, io, b0, b1, tab, flag, nullptr, stream, fr);
+}
+
+disk_status disk_sv_filter(const disk_basis* b, const float* basis_theta, const void* image, const float* pmap,
+                           void* out, int32_t C, int32_t H, int32_t W, disk_dtype io, void* ws, size_t ws_bytes,
+                           hipStream_t stream) {
+    return disk_sv_filter_frames(b, basis_theta, image, pmap, 0, out, 1, C, H, W, io, ws, ws_bytes, stream);
 }
 
 // ---------------------------------------------------------------------------

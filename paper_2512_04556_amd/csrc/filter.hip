@@ -862,7 +862,10 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4, 4)))
     const TIn* __restrict__ X, TOut* __restrict__ Y, const float* __restrict__ P,
     const float* __restrict__ table, int tap0, int N, int T, int G0, int G1, int H, int W, int halo,
     int tiles_x, int per, int ntiles, const int* __restrict__ flag, int rowW, const float* __restrict__ raw,
-    int pN, int pofs, float* __restrict__ part) {
+    int pN, int pofs, float* __restrict__ part, int ntf, int pfs) {
+    // Frames: tiles run over F stacked frames of C planes each (ntiles = F
+    // ntf); a tile's frame is tile / ntf.  The parameter map is shared by
+    // every frame (pfs = 0) or one per frame (pfs = DIMS planes apart).
     extern __shared__ float lds[];
     if (ROWB > 0) rowW = ROWB / 4;
     constexpr int PY = kPipePY;
@@ -999,8 +1002,11 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4, 4)))
         float nan[PY][C];
         for (int j = 0; j < PY; ++j)
             for (int c = 0; c < C; ++c) nan[j][c] = __builtin_nanf("");
-        for (; tile < tend; tile += nwg)
-            sv_store<C, TOut, PY>(Y, plane, W, H, (tile % tiles_x) * kTW + lx, (tile / tiles_x) * TH + lyb, nan);
+        for (; tile < tend; tile += nwg) {
+            const int f = tile / ntf, tt = tile - f * ntf;
+            sv_store<C, TOut, PY>(Y + static_cast<size_t>(f) * C * plane, plane, W, H, (tt % tiles_x) * kTW + lx,
+                                  (tt / tiles_x) * TH + lyb, nan);
+        }
         return;
     }
     const int nr = (SY - wv + NW - 1) / NW;      // staged rows of this wave, <= kPipeRPW
@@ -1017,7 +1023,9 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4, 4)))
     float pv[PY][DIMS];
     float gv[PY][C];   // corr: the tile's output gradient at the lane's pixels
     auto issue = [&](int t) {
-        const int tx0 = (t % tiles_x) * kTW, ty0 = (t / tiles_x) * TH;
+        const int f = t / ntf, tt = t - f * ntf;
+        const size_t xfo = static_cast<size_t>(f) * C * plane, pfo = static_cast<size_t>(f) * pfs * plane;
+        const int tx0 = (tt % tiles_x) * kTW, ty0 = (tt / tiles_x) * TH;
         uint32_t gx[kPipeNQ];
         bool vx[kPipeNQ];
 #pragma unroll
@@ -1038,7 +1046,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4, 4)))
                         const uint32_t off = (grow + gx[q]) * static_cast<uint32_t>(sizeof(TIn));   // bytes
 #pragma unroll
                         for (int c = 0; c < C; ++c) {
-                            const float v = IO<TIn>::load(byte_at(Xc[c], off), 0);
+                            const float v = IO<TIn>::load(byte_at(Xc[c] + xfo, off), 0);
                             if constexpr (zstage)
                                 stg[rr][q][c] = (vy && vx[q]) ? v : 0.0f;
                             else
@@ -1070,7 +1078,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4, 4)))
                 if constexpr (chain)
                     pv[j][d] = 0.0f;
                 else
-                    pv[j][d] = *byte_at(Pd[d], pi);
+                    pv[j][d] = *byte_at(Pd[d] + pfo, pi);
             }
         }
     };
@@ -1096,7 +1104,9 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4, 4)))
 #pragma unroll
         for (int j = 0; j < PY; ++j) asm volatile("" ::"v"(ta[j]), "v"(tb[j]), "v"(kk[j]));
         __syncthreads();
-        const int x = (tile % tiles_x) * kTW + lx, y0 = (tile / tiles_x) * TH + lyb;
+        const int fr = tile / ntf, tr = tile - fr * ntf;
+        TOut* const Yf = Y + static_cast<size_t>(fr) * C * plane;
+        const int x = (tr % tiles_x) * kTW + lx, y0 = (tr / tiles_x) * TH + lyb;
         const int next = tile + nwg;
         if constexpr (fused) {
             float xq[PY][C];
@@ -1110,7 +1120,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4, 4)))
             if (next < tend) issue(next);
             float acc[PY][C];
             fused_tile_taps<C, PY, ROWB>(s, acc, xq, base0, tabL, N, min(N, kCorrTaps));
-            sv_store<C, TOut, PY>(Y, plane, W, H, x, y0, acc);
+            sv_store<C, TOut, PY>(Yf, plane, W, H, x, y0, acc);
         } else if constexpr (corr) {
             float gc[PY][C];
 #pragma unroll
@@ -1126,7 +1136,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4, 4)))
             if (next < tend) issue(next);
             float acc[PY][C];
             sv_tile_taps<C, DIMS, PY, ROWB, TL>(acc, ta, tb, kk, base0, rowB, table, tap0, N, T, tabL);
-            sv_store<C, TOut, PY>(Y, plane, W, H, x, y0, acc);
+            sv_store<C, TOut, PY>(Yf, plane, W, H, x, y0, acc);
         }
         if (next >= tend) break;
         tile = next;
@@ -1280,10 +1290,11 @@ template <int C, int DIMS, typename TIn, typename TOut, int NW, int HMAX, int RO
 static hipError_t launch_pipe(const void* src, void* dst, const float* pmap, const float* table, int tap0, int N,
                               int T, int G0, int G1, int H, int W, int halo, const int* flag, const float* raw,
                               hipStream_t s, int pN = 0, int pofs = 0, int* grid_out = nullptr,
-                              float* part = nullptr, int grid = 0) {
+                              float* part = nullptr, int grid = 0, Frames fr = Frames{}) {
     constexpr int TH = PipeShape<NW, HMAX>::TH;
     const int tiles_x = (W + kTW - 1) / kTW, tiles_y = (H + TH - 1) / TH;
-    const int ntiles = tiles_x * tiles_y;
+    const int ntf = tiles_x * tiles_y;
+    const int ntiles = ntf * fr.F;
     const int per = (ntiles + 7) / 8;
     const int hs = MODE != 0 ? HMAX : halo;   // chain layers size the tile for HMAX
     const size_t lds = pipe_lds_bytes<C, DIMS, TIn, TOut, NW, HMAX, ROWB, TL>(hs, G0, N);
@@ -1318,7 +1329,7 @@ static hipError_t launch_pipe(const void* src, void* dst, const float* pmap, con
     if (grid > 0) per_xcd = grid / 8;                     // a given grid (a multiple of 8): partials laid out alike
     hipLaunchKernelGGL(fn, dim3(8 * per_xcd), dim3(64 * NW), lds, s, static_cast<const TIn*>(src),
                        static_cast<TOut*>(dst), pmap, table, tap0, N, T, G0, G1, H, W, halo, tiles_x, per, ntiles,
-                       flag, rowW, raw, pN, pofs, part);
+                       flag, rowW, raw, pN, pofs, part, ntf, fr.pmap_shared ? 0 : DIMS);
     if (grid_out) *grid_out = 8 * per_xcd;
     return hipGetLastError();
 }
@@ -1346,7 +1357,7 @@ static hipError_t launch_tiles(const void* src, void* dst, const float* pmap, co
 template <int C, int DIMS, typename TIn, typename TOut>
 static hipError_t launch_typed(const void* src, void* dst, const float* pmap, const float* table, int tap0, int N,
                                int T, int G0, int G1, int H, int W, int halo, const int* flag, const float* raw,
-                               hipStream_t s) {
+                               hipStream_t s, Frames fr) {
     static const int pipe = env_int("DISK_SV_PIPE", 1);
     // small halos: 8-wave work-groups of 64 x 16 tiles, two per CU, whose
     // staging and gather phases drift apart and overlap; larger ones: 16-wave
@@ -1357,7 +1368,7 @@ static hipError_t launch_typed(const void* src, void* dst, const float* pmap, co
     if (pipe && halo <= HMAX &&                                                                              \
         pipe_lds_bytes<C, DIMS, TIn, TOut, NW, HMAX, ROWB, TL>(halo, G0, N) <= static_cast<size_t>(BUDGET)) \
         return launch_pipe<C, DIMS, TIn, TOut, NW, HMAX, ROWB, TL>(src, dst, pmap, table, tap0, N, T, G0, G1, H, W, \
-                                                                  halo, flag, raw, s);
+                                                                  halo, flag, raw, s, 0, 0, nullptr, nullptr, 0, fr);
     if constexpr (C >= 3 && DIMS == 1) {
         SV_TRY_PIPE(8, kPipeHalo8, kPipeRowB, true, 80 * 1024)
         SV_TRY_PIPE(16, kPipeHalo, kPipeRowB, true, 160 * 1024)
@@ -1375,34 +1386,45 @@ static hipError_t launch_typed(const void* src, void* dst, const float* pmap, co
     // they fit; below that the halo rows dominate (measured: an 8-row tile at
     // halo 33 is slower than reading the corners through L1), so larger halos
     // take the one-pixel-per-thread kernel.
-    if (sv_rows_per_wave(halo, C) == 4)
-        return launch_tiles<C, DIMS, TIn, TOut, 4, 8>(src, dst, pmap, table, tap0, N, T, G0, G1, H, W, halo, flag, s);
-    const long px = static_cast<long>(H) * W;
-    hipLaunchKernelGGL((sv_pass_global_kernel<C, DIMS, TIn, TOut>), dim3(static_cast<unsigned>((px + 255) / 256)),
-                       dim3(256), 0, s, static_cast<const TIn*>(src), static_cast<TOut*>(dst), pmap, table, tap0, N,
-                       T, G0, G1, H, W, flag);
-    return hipGetLastError();
+    // the kernels below take one frame per launch
+    const size_t fsz = static_cast<size_t>(C) * H * W, psz = fr.pmap_shared ? 0 : static_cast<size_t>(DIMS) * H * W;
+    for (int f = 0; f < fr.F; ++f) {
+        const TIn* xs = static_cast<const TIn*>(src) + f * fsz;
+        TOut* ys = static_cast<TOut*>(dst) + f * fsz;
+        const float* ps = pmap + f * psz;
+        hipError_t e;
+        if (sv_rows_per_wave(halo, C) == 4) {
+            e = launch_tiles<C, DIMS, TIn, TOut, 4, 8>(xs, ys, ps, table, tap0, N, T, G0, G1, H, W, halo, flag, s);
+        } else {
+            const long px = static_cast<long>(H) * W;
+            hipLaunchKernelGGL((sv_pass_global_kernel<C, DIMS, TIn, TOut>), dim3(static_cast<unsigned>((px + 255) / 256)),
+                               dim3(256), 0, s, xs, ys, ps, table, tap0, N, T, G0, G1, H, W, flag);
+            e = hipGetLastError();
+        }
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 template <int C, int DIMS>
 static hipError_t launch_py(int src_bf16, const void* src, int dst_bf16, void* dst, const float* pmap,
                             const float* table, int tap0, int N, int T, int G0, int G1, int H, int W, int halo,
-                            const int* flag, const float* raw, hipStream_t s) {
+                            const int* flag, const float* raw, hipStream_t s, Frames fr) {
     if (!src_bf16 && !dst_bf16)
-        return launch_typed<C, DIMS, float, float>(src, dst, pmap, table, tap0, N, T, G0, G1, H, W, halo, flag, raw, s);
+        return launch_typed<C, DIMS, float, float>(src, dst, pmap, table, tap0, N, T, G0, G1, H, W, halo, flag, raw, s, fr);
     if (src_bf16 && !dst_bf16)
-        return launch_typed<C, DIMS, uint16_t, float>(src, dst, pmap, table, tap0, N, T, G0, G1, H, W, halo, flag, raw, s);
+        return launch_typed<C, DIMS, uint16_t, float>(src, dst, pmap, table, tap0, N, T, G0, G1, H, W, halo, flag, raw, s, fr);
     if (!src_bf16 && dst_bf16)
-        return launch_typed<C, DIMS, float, uint16_t>(src, dst, pmap, table, tap0, N, T, G0, G1, H, W, halo, flag, raw, s);
-    return launch_typed<C, DIMS, uint16_t, uint16_t>(src, dst, pmap, table, tap0, N, T, G0, G1, H, W, halo, flag, raw, s);
+        return launch_typed<C, DIMS, float, uint16_t>(src, dst, pmap, table, tap0, N, T, G0, G1, H, W, halo, flag, raw, s, fr);
+    return launch_typed<C, DIMS, uint16_t, uint16_t>(src, dst, pmap, table, tap0, N, T, G0, G1, H, W, halo, flag, raw, s, fr);
 }
 
 template <int C>
 static hipError_t launch_dims(int dims, int src_bf16, const void* src, int dst_bf16, void* dst, const float* pmap,
                               const float* table, int tap0, int N, int T, int G0, int G1, int H, int W, int halo,
-                              const int* flag, const float* raw, hipStream_t s) {
-    if (dims == 1) return launch_py<C, 1>(src_bf16, src, dst_bf16, dst, pmap, table, tap0, N, T, G0, G1, H, W, halo, flag, raw, s);
-    return launch_py<C, 2>(src_bf16, src, dst_bf16, dst, pmap, table, tap0, N, T, G0, G1, H, W, halo, flag, raw, s);
+                              const int* flag, const float* raw, hipStream_t s, Frames fr) {
+    if (dims == 1) return launch_py<C, 1>(src_bf16, src, dst_bf16, dst, pmap, table, tap0, N, T, G0, G1, H, W, halo, flag, raw, s, fr);
+    return launch_py<C, 2>(src_bf16, src, dst_bf16, dst, pmap, table, tap0, N, T, G0, G1, H, W, halo, flag, raw, s, fr);
 }
 
 // One layer of a uniform chain on an image (CLAMP), as a pass of the staged
@@ -1580,12 +1602,13 @@ bool sv_pass_raw_ok(int C, int dims, int halo, int G0, int N) {
 
 hipError_t launch_sv_pass(int C, int dims, int src_bf16, const void* src, int dst_bf16, void* dst,
                           const float* pmap, const float* table, int tap0, int N, int T, int G0, int G1,
-                          int H, int W, int halo, const int* flag, const float* raw, hipStream_t s) {
+                          int H, int W, int halo, const int* flag, const float* raw, hipStream_t s, Frames fr) {
+    if (fr.F < 1) return hipErrorInvalidValue;
     switch (C) {
-        case 1: return launch_dims<1>(dims, src_bf16, src, dst_bf16, dst, pmap, table, tap0, N, T, G0, G1, H, W, halo, flag, raw, s);
-        case 2: return launch_dims<2>(dims, src_bf16, src, dst_bf16, dst, pmap, table, tap0, N, T, G0, G1, H, W, halo, flag, raw, s);
-        case 3: return launch_dims<3>(dims, src_bf16, src, dst_bf16, dst, pmap, table, tap0, N, T, G0, G1, H, W, halo, flag, raw, s);
-        default: return launch_dims<4>(dims, src_bf16, src, dst_bf16, dst, pmap, table, tap0, N, T, G0, G1, H, W, halo, flag, raw, s);
+        case 1: return launch_dims<1>(dims, src_bf16, src, dst_bf16, dst, pmap, table, tap0, N, T, G0, G1, H, W, halo, flag, raw, s, fr);
+        case 2: return launch_dims<2>(dims, src_bf16, src, dst_bf16, dst, pmap, table, tap0, N, T, G0, G1, H, W, halo, flag, raw, s, fr);
+        case 3: return launch_dims<3>(dims, src_bf16, src, dst_bf16, dst, pmap, table, tap0, N, T, G0, G1, H, W, halo, flag, raw, s, fr);
+        default: return launch_dims<4>(dims, src_bf16, src, dst_bf16, dst, pmap, table, tap0, N, T, G0, G1, H, W, halo, flag, raw, s, fr);
     }
 }
 

@@ -71,9 +71,17 @@ size_t sv_lds_bytes(int halo, int C, int py, bool pad = true);
 // table + flag from launch_sv_prep (raw == nullptr), or raw = the basis itself
 // (1-D, C >= 3 layers for which sv_pass_raw_ok holds): the pass derives its
 // layer's coefficient rows and checks its offsets against `halo` on its own.
+// F frames [F][C][H][W] in one pass (the pipelined kernel walks the tiles of
+// all frames in one launch); the parameter map is shared by the frames or one
+// [dims][H][W] per frame.
+struct Frames {
+    int F = 1;
+    int pmap_shared = 1;
+};
 hipError_t launch_sv_pass(int C, int dims, int src_bf16, const void* src, int dst_bf16, void* dst,
                           const float* pmap, const float* table, int tap0, int N, int T, int G0,
-                          int G1, int H, int W, int halo, const int* flag, const float* raw, hipStream_t s);
+                          int G1, int H, int W, int halo, const int* flag, const float* raw, hipStream_t s,
+                          Frames fr = Frames{});
 bool sv_pass_raw_ok(int C, int dims, int halo, int G0, int N);
 // One uniform-chain layer on a C = 3 or 4 image with the CLAMP boundary through
 // the staged pass kernel (halo derived on the device from the layer's taps).

@@ -5,7 +5,8 @@
 Training data: ``n`` synthetic targets (odd sides 15..127, the shape
 families of the batched-optimisation workload, 4 layers x 12 taps), each
 fitted by the batched optimiser from the radial initialisation (Adam, 1000
-steps or 40 dB, lr 1e-2 -> 1e-3, normalised MSE).  The network regresses the
+steps or 40 dB, lr 1e-2 -> 1e-3 with the offsets' rate in units of the
+target's half-width, normalised MSE).  The network regresses the
 fitted Theta in its own units (offsets / hw) from the area-resampled 64 x 64
 input.  Everything on the GPU runs through libdisk; this script only moves
 tensors around.  Chunk i of 4096 targets is drawn with seed 6000 + i.
@@ -21,7 +22,7 @@ from multiprocessing import Pool
 import numpy as np
 import torch
 
-from . import (OptParams, disk_init_radial, disk_net_param_count, disk_net_prepare_inputs, disk_net_train_step,
+from . import (OFFSETS_HALF_WIDTH, OptParams, disk_init_radial, disk_net_param_count, disk_net_prepare_inputs, disk_net_train_step,
                disk_optimize_batch, make_batch, net_workspace)
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -37,6 +38,11 @@ def _chunk(args):
     return pack_targets(b)
 
 
+# the optimiser settings of the batched workloads (and of the comparison the
+# network is judged by)
+FIT = dict(lr0=1e-2, lr1=1e-3, psnr_stop_db=40.0, offset_units=OFFSETS_HALF_WIDTH)
+
+
 def fitted_pairs(n, steps=1000, workers=8, log=print):
     """(inputs int16 [n][64][64] BF16 bits, half_width [n], theta [n][48][3],
     psnr [n]) on the GPU."""
@@ -44,7 +50,7 @@ def fitted_pairs(n, steps=1000, workers=8, log=print):
     with Pool(workers) as pool:
         packed = pool.map(_chunk, list(enumerate(sizes)))
     xs, hws, ths, pss = [], [], [], []
-    prm = OptParams(max_steps=steps, lr0=1e-2, lr1=1e-3, psnr_stop_db=40.0)
+    prm = OptParams(max_steps=steps, **FIT)
     for i, (desc, taps, tg) in enumerate(packed):
         t = time.perf_counter()
         bt = make_batch(desc, taps, tg)
@@ -125,7 +131,8 @@ def main():
     params, hist = train(x, hw, theta, epochs=a.epochs, log=lambda s: print(s, flush=True))
     t2 = time.perf_counter()
     params.cpu().numpy().astype("<f4").tofile(a.out)
-    meta = {"n": a.n, "epochs": a.epochs, "steps": a.steps, "data_seconds": round(t1 - t0, 1),
+    meta = {"n": a.n, "epochs": a.epochs, "steps": a.steps, "fit": {k: v for k, v in FIT.items()},
+            "data_seconds": round(t1 - t0, 1),
             "train_seconds": round(t2 - t1, 1), "final": hist[-1], "median_psnr_db": float(ps.median())}
     with open(a.out + ".json", "w") as f:
         json.dump(meta, f, indent=1)

@@ -249,3 +249,68 @@ def test_basis_rotate_and_angle_effect(dev):
     out, b = _run(to_np(got).astype(np.float32), taps, [4, 9], img, P)
     ref = SV.sv_chain(img.astype(np.float64), P.astype(np.float64), want, [4, 9], taps)
     assert rel_err(to_np(out), ref) <= TOL_F32
+
+
+@pytest.mark.parametrize("C,H,W,grid,taps,io,per_frame", [
+    (3, 150, 333, [16], [8, 8, 8, 8], torch.float32, False),   # pipelined kernel, frames in one launch
+    (3, 97, 130, [16], [8, 8, 8, 8], torch.bfloat16, True),
+    (4, 70, 100, [3, 3], [6, 5], torch.float32, True),          # 2-D basis, prepared table
+    (1, 64, 80, [5], [5, 4, 6], torch.float32, False),          # one-tile kernel, a launch per frame
+])
+def test_sv_frames_equal_single_frame_calls(dev, C, H, W, grid, taps, io, per_frame):
+    """F frames in one call (one launch per pass over all frames' tiles) equal
+    F single-frame calls bit for bit, with one shared map or a map per frame."""
+    F = 3
+    G = int(np.prod(grid))
+    b = disk.make_basis(to_dev(_basis(G, taps, seed=810 + C, r0=1.0, dr=0.8)), taps, grid)
+    x = torch.stack([to_dev(noise_image(H, W, C, seed=H + f, n_rects=10)) for f in range(F)]).to(io)
+    if per_frame:
+        p = torch.stack([to_dev(param_map(H, W, seed=W + f, period=64.0, dims=len(grid))) for f in range(F)])
+    else:
+        p = to_dev(param_map(H, W, seed=W, period=64.0, dims=len(grid)))
+    say("sv frames", C, H, W, grid, io, per_frame)
+    got = disk.disk_sv_filter_frames(b, x, p)
+    for f in range(F):
+        # a frame's own copy: the C ABI wants 16-byte aligned buffers
+        want = disk.disk_sv_filter(b, x[f].clone(), (p[f] if per_frame else p).clone())
+        assert torch.equal(got[f], want), f
+
+
+def test_sv_frames_bench_launch_and_graph_replay(dev):
+    """The benchmark's frame batch: 8 frames of 1920 x 1080 x 3 FP32 with the
+    16-entry basis of 4 x 8 taps in one call, captured into a HIP graph and
+    replayed (inputs changed between replays): every replay equals the eager
+    call bit for bit, and two frames equal the oracle on 96 x 96 crops with a
+    margin of the summed halos."""
+    taps = [8, 8, 8, 8]
+    basis = _basis(16, taps, seed=300, r0=1.0, dr=0.45)
+    b = disk.make_basis(to_dev(basis), taps, [16])
+    H, W, F = 1080, 1920, 8
+    imgs = [noise_image(H, W, 3, seed=20 + f, n_rects=50) for f in (0, 1)]
+    P = param_map(H, W, seed=3)
+    x = torch.stack([to_dev(imgs[f % 2]) for f in range(F)])
+    p = to_dev(P)
+    out = torch.empty_like(x)
+    ws = disk.sv_frames_workspace(b, F, 3, H, W)
+    say("sv frames 1080p x 8 eager")
+    want = disk.disk_sv_filter_frames(b, x, p, ws=ws).clone()
+    say("sv frames 1080p x 8 graph capture")
+    cap = disk.Captured(lambda: disk.disk_sv_filter_frames(b, x, p, out=out, ws=ws), warmup=False)
+    for r in range(3):
+        x[0].mul_(1.0)                       # eager work between replays
+        torch.cuda.synchronize()
+        say("sv frames graph replay", r)
+        cap.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(out, want), r
+    got = to_np(want)
+    m = int(sum(b.halo))
+    rng = np.random.default_rng(6)
+    for f in (0, 1):
+        y0, x0 = int(rng.integers(m, H - 96 - m)), int(rng.integers(m, W - 96 - m))
+        win = (slice(y0 - m, y0 + 96 + m), slice(x0 - m, x0 + 96 + m))
+        ref = SV.sv_chain(imgs[f][:, win[0], win[1]].astype(np.float64), P[:, win[0], win[1]].astype(np.float64),
+                          basis.astype(np.float64), [16], taps)[:, m:m + 96, m:m + 96]
+        e = rel_err(got[f][:, y0:y0 + 96, x0:x0 + 96], ref)
+        print(f"frame {f} crop ({y0},{x0}): {e:.2e}")
+        assert e <= TOL_F32
