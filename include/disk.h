@@ -324,6 +324,26 @@ disk_status disk_sv_filter_frames(const disk_basis* b, const float* basis_theta,
                                   int32_t C, int32_t H, int32_t W, disk_dtype io, void* ws,
                                   size_t ws_bytes, hipStream_t stream);
 
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * filter as disk_sv_filter, with identical results, but its scratch (the
+ * coefficient table and the two FP32 images between passes) lives in a fixed
+ * device array of the library, DISK_SV_NOALLOC_MAX_BYTES (64 MiB) per GPU,
+ * held from the first call on that GPU until the process ends.  The call
+ * allocates nothing; the caller still owns image, pmap and out.
+ * Errors: DISK_WORKSPACE_TOO_SMALL when disk_sv_filter_workspace_size(b, C, H,
+ * W, io) exceeds the array (e.g. above about 2.7 Mpixel of 3-channel FP32
+ * intermediates: 1920 x 1080 x 3 fits, 3840 x 2160 x 3 does not); otherwise
+ * as disk_sv_filter.  Every call on one GPU uses that GPU's one array: calls
+ * that overlap on the same GPU (different streams, threads or processes
+ * sharing it) race and must be serialised by the caller.
+ */
+#define DISK_SV_NOALLOC_MAX_BYTES (64u << 20)
+size_t disk_sv_noalloc_max_bytes(void);
+disk_status disk_sv_filter_noalloc(const disk_basis* b, const float* basis_theta, const void* image,
+                                   const float* pmap, void* out, int32_t C, int32_t H, int32_t W,
+                                   disk_dtype io, hipStream_t stream);
 
 /*
  * Angle axis for a 2-D basis (the angle-driven effects, rotational bokeh and

@@ -15,7 +15,8 @@ import torch
 
 __all__ = [
     "lib", "DiskError", "ZERO", "CLAMP", "F32", "BF16", "LOSS_NMSE", "LOSS_CHARBONNIER",
-    "disk_forward", "disk_backward", "disk_sv_filter", "disk_sv_filter_frames", "sv_frames_workspace", "disk_sv_prepare", "disk_sv_apply", "Basis", "make_basis",
+    "disk_forward", "disk_backward", "disk_sv_filter", "disk_sv_filter_frames", "sv_frames_workspace", "disk_sv_filter_noalloc",
+    "disk_sv_prepare", "disk_sv_apply", "Basis", "make_basis",
     "disk_optimize_batch", "Captured", "OptState", "opt_tune", "optimize_workspace_size", "OFFSETS_PIXELS",
     "OFFSETS_HALF_WIDTH", "disk_init_radial", "disk_init_random", "disk_fit_basis", "pack_targets", "fit_basis", "disk_init_shape", "OptParams", "Batch", "make_batch",
     "disk_init_predict", "disk_net_train_step", "disk_net_prepare_inputs", "disk_net_scatter_theta",
@@ -105,6 +106,8 @@ def lib():
                                                             c_int32]),
         "disk_sv_filter_frames": (c_int32, [POINTER(DiskBasis), P, P, P, c_int32, P, c_int32, c_int32, c_int32,
                                             c_int32, c_int32, P, c_size_t, P]),
+        "disk_sv_noalloc_max_bytes": (c_size_t, []),
+        "disk_sv_filter_noalloc": (c_int32, [POINTER(DiskBasis), P, P, P, P, c_int32, c_int32, c_int32, c_int32, P]),
         "disk_sv_table_bytes": (c_size_t, [POINTER(DiskBasis)]),
         "disk_sv_prepare": (c_int32, [POINTER(DiskBasis), P, P, c_size_t, P]),
         "disk_sv_apply_workspace_size": (c_size_t, [POINTER(DiskBasis), c_int32, c_int32, c_int32, c_int32]),
@@ -318,6 +321,22 @@ def disk_sv_filter_frames(basis: Basis, images, pmaps, out=None, ws=None):
 
 def sv_frames_workspace(basis: Basis, F, C, H, W, io=F32, device="cuda"):
     return _workspace(lib().disk_sv_filter_frames_workspace_size(ctypes.byref(basis.desc), F, C, H, W, io), device)
+
+
+def disk_sv_filter_noalloc(basis: Basis, image, pmap, out):
+    """disk_sv_filter without a workspace: the library's fixed device array
+    holds the scratch (calls on one GPU must not overlap).  ``out`` is
+    required, so the call allocates nothing."""
+    _dev(image, "image")
+    _dev(pmap, "pmap")
+    _dev(out, "out")
+    _f32(pmap, "pmap")
+    if out.dtype != image.dtype or tuple(out.shape) != tuple(image.shape):
+        raise DiskError("out must match the image's dtype and shape")
+    C, H, W = image.shape
+    _check(lib().disk_sv_filter_noalloc(ctypes.byref(basis.desc), _ptr(basis.theta), _ptr(image), _ptr(pmap),
+                                        _ptr(out), C, H, W, _io_dtype(image), _stream()))
+    return out
 
 
 def sv_filter_workspace(basis: Basis, C, H, W, io=F32, device="cuda"):

@@ -8,6 +8,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 
 #include "internal.hpp"
@@ -767,3 +768,55 @@ disk_status disk_net_scatter_theta(const disk_batch_meta* meta, const disk_targe
 
 }  // extern "C"
 
+// ---------------------------------------------------------------------------
+// disk_sv_filter_noalloc: disk_sv_filter with its scratch (the coefficient
+// table and the two FP32 ping-pong images between passes) in a file-scope
+// device array, for callers that cannot allocate device memory.  In host code
+// the array's name is only a stand-in: its device address is looked up once
+// per device with hipGetSymbolAddress (with that device current) and only that
+// address reaches the kernels.  All calls on one device share its array, so
+// calls that overlap on one device race.
+// ---------------------------------------------------------------------------
+namespace {
+constexpr size_t kNoallocBytes = size_t(DISK_SV_NOALLOC_MAX_BYTES);
+constexpr int kNoallocDevices = 64;
+__device__ __align__(256) unsigned char scratch[kNoallocBytes];
+std::mutex g_noalloc_mu;
+void* g_noalloc_ptr[kNoallocDevices] = {};
+
+disk_status noalloc_scratch(void** out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail(DISK_DEVICE, "hipGetDevice: %s", hipGetErrorString(e));
+    if (dev < 0 || dev >= kNoallocDevices)
+        return fail(DISK_UNSUPPORTED, "device %d beyond the %d supported", dev, kNoallocDevices);
+    std::lock_guard<std::mutex> lock(g_noalloc_mu);
+    if (!g_noalloc_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) return fail(DISK_DEVICE, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+        g_noalloc_ptr[dev] = p;
+    }
+    *out = g_noalloc_ptr[dev];
+    return DISK_OK;
+}
+}  // namespace
+
+size_t disk_sv_noalloc_max_bytes(void) { return kNoallocBytes; }
+
+disk_status disk_sv_filter_noalloc(const disk_basis* b, const float* basis_theta, const void* image,
+                                   const float* pmap, void* out, int32_t C, int32_t H, int32_t W, disk_dtype io,
+                                   hipStream_t stream) {
+    DISK_TRY(check_basis(b));
+    DISK_TRY(check_image(C, H, W));
+    const size_t need = disk_sv_filter_workspace_size(b, C, H, W, io);
+    if (need == 0) return fail(DISK_BAD_SHAPE, "invalid basis or image shape");
+    if (need > kNoallocBytes)
+        return fail(DISK_WORKSPACE_TOO_SMALL,
+                    "needs %zu bytes of scratch, more than the fixed %zu-byte device array of the allocation-free "
+                    "entry point (use disk_sv_filter with a workspace)",
+                    need, kNoallocBytes);
+    void* ws = nullptr;
+    DISK_TRY(noalloc_scratch(&ws));
+    return disk_sv_filter(b, basis_theta, image, pmap, out, C, H, W, io, ws, kNoallocBytes, stream);
+}
