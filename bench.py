@@ -47,6 +47,8 @@ def parse():
     ap.add_argument("--no-time-to-40db", action="store_true")
     ap.add_argument("--no-2d", action="store_true")
     ap.add_argument("--no-ablations", action="store_true")
+    ap.add_argument("--sv-only", action="store_true",
+                    help="only the headline filter measurement (for profiling its kernel)")
     ap.add_argument("--no-extras", action="store_true", help="skip the gradient-chain and network measurements")
     ap.add_argument("--extras-only", action="store_true",
                     help="only the gradient-chain and network measurements (for profiling them)")
@@ -400,6 +402,29 @@ def angle_effects(torch, disk, steps=20):
     return res
 
 
+def tilt_shift(torch, disk, basis, x, steps=20):
+    """Tilt-shift at 1920x1080x3 FP32 with the fitted disk basis: blur from
+    the distance of a pseudo-depth map (a ground plane receding upwards plus
+    smooth relief) to the focal depth."""
+    from synth import tilt_shift_map
+    p = torch.as_tensor(tilt_shift_map(H, W)).cuda()
+    out = torch.empty_like(x)
+    ws = disk.sv_filter_workspace(basis, C, H, W)
+    for _ in range(3):
+        disk.disk_sv_filter(basis, x, p, out=out, ws=ws)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        disk.disk_sv_filter(basis, x, p, out=out, ws=ws)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    return {"ms_per_frame": round(ms, 4), "mpix_s": round(H * W / ms / 1e3, 1),
+            "map": "focus 0.5, depth of field 0.08, falloff 0.35 on the pseudo-depth"}
+
+
 # Learned initialiser (64 x 64 input, conv3x3/s2 widths 32..256, FC 256-512-144):
 # multiply-adds per sample, layer by layer (output pixels x out channels x 9 x in channels)
 NET_MACS = [32 * 32 * 32 * 9 * 1, 16 * 16 * 64 * 9 * 32, 8 * 8 * 128 * 9 * 64, 4 * 4 * 128 * 9 * 128,
@@ -686,10 +711,14 @@ def main():
     }
     if fit_info:
         res["config"]["basis_fit"] = fit_info
+    if a.sv_only:
+        print(json.dumps(res), flush=True)
+        return
     res["dense_reference"] = dense_reference(torch, disk, x, p, out, single_ms)
     res["small_workloads"] = small_workloads(torch, disk)
     if not a.no_2d:
         res["angle_effects_1080p"] = angle_effects(torch, disk)
+        res["tilt_shift_1080p"] = tilt_shift(torch, disk, basis, x)
     if not a.no_ablations:
         res["ablations"] = ablations(torch, disk)
     if not a.no_2d:

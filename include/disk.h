@@ -196,9 +196,15 @@ typedef struct {
     int32_t max_T;
 } disk_batch_meta;
 /* Launch shape of the persistent optimiser, chosen per batch by the built-in
- * table (tune = NULL, written by the project's autotuner) or given here. */
+ * table (tune = NULL; rows keyed by batch size and largest side, written by the
+ * project's autotuner, paper_2512_04556_amd/autotune.py) or given here.  Each
+ * work-group owns one target at a time: 256 threads with 1..4 resident per
+ * compute unit, or 1024 threads (16 waves on one target) with 1 per unit, for
+ * batches too small to fill the chip.  Results do not depend on wgs_per_cu; the
+ * two work-group sizes sum in different orders (rounding-level differences). */
 typedef struct {
-    int32_t wgs_per_cu;        /* resident work-groups (one target each) per compute unit, 1..4 */
+    int32_t threads;           /* 256 or 1024 */
+    int32_t wgs_per_cu;        /* 1..4 for 256 threads, 1 for 1024 */
 } disk_opt_tune;
 size_t disk_optimize_workspace_size(const disk_batch_meta* meta, const disk_opt_tune* tune);
 disk_status disk_optimize_batch(const disk_batch_meta* meta, const disk_target* desc,

@@ -57,7 +57,7 @@ class DiskOptState(ctypes.Structure):
 
 
 class DiskOptTune(ctypes.Structure):
-    _fields_ = [("wgs_per_cu", c_int32)]
+    _fields_ = [("threads", c_int32), ("wgs_per_cu", c_int32)]
 
 
 class DiskDenseParams(ctypes.Structure):
@@ -402,9 +402,10 @@ class OptState:
         self.c = DiskOptState(*[None if t is None else _ptr(t) for t in self.tensors], int(max_updates))
 
 
-def opt_tune(wgs_per_cu):
-    """A launch shape for disk_optimize_batch (None selects the built-in table)."""
-    return DiskOptTune(int(wgs_per_cu))
+def opt_tune(wgs_per_cu, threads=256):
+    """A launch shape for disk_optimize_batch (None selects the built-in table):
+    256 threads with 1..4 work-groups per CU, or 1024 threads with 1."""
+    return DiskOptTune(int(threads), int(wgs_per_cu))
 
 
 class Batch:

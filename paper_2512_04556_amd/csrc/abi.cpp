@@ -507,19 +507,26 @@ static disk_status check_opt_params(const disk_opt_params* params) {
     return DISK_OK;
 }
 
+static bool tune_ok(const disk_opt_tune* t) {
+    return !t || (t->threads == 256 && t->wgs_per_cu >= 1 && t->wgs_per_cu <= 4) ||
+           (t->threads == 1024 && t->wgs_per_cu == 1);
+}
+
 static disk_status check_tune(const disk_opt_tune* t) {
-    if (t && (t->wgs_per_cu < 1 || t->wgs_per_cu > 4))
-        return fail(DISK_INVALID_ARG, "tune->wgs_per_cu=%d must be in 1..4", t->wgs_per_cu);
+    if (!tune_ok(t))
+        return fail(DISK_INVALID_ARG, "tune: threads=%d wgs_per_cu=%d (256 x 1..4, or 1024 x 1)", t->threads,
+                    t->wgs_per_cu);
     return DISK_OK;
 }
 
-static int wgs_per_cu(const disk_batch_meta* m, const disk_opt_tune* t) {
-    return t ? t->wgs_per_cu : opt_default_wgs_per_cu(*m);
+static disk_opt_tune launch_shape(const disk_batch_meta* m, const disk_opt_tune* t) {
+    return t ? *t : opt_default_tune(*m);
 }
 
 static size_t optimize_ws(const disk_batch_meta* m, const disk_opt_tune* t, Carve& cv, int** order, int** queue,
                           float** scratch, size_t* slot, int* nwg) {
-    *nwg = opt_workgroups(m->B, wgs_per_cu(m, t));
+    const disk_opt_tune sh = launch_shape(m, t);
+    *nwg = opt_workgroups(m->B, sh.wgs_per_cu, sh.threads);
     *slot = opt_slot_floats(m->max_side, std::min(m->max_T, DISK_MAX_LAYERS));
     *order = cv.take<int>(m->B);
     *queue = cv.take<int>(64);
@@ -529,7 +536,7 @@ static size_t optimize_ws(const disk_batch_meta* m, const disk_opt_tune* t, Carv
 
 size_t disk_optimize_workspace_size(const disk_batch_meta* meta, const disk_opt_tune* tune) {
     if (!meta || meta->B < 1 || meta->max_side < 1 || meta->max_T < 1) return 0;
-    if (tune && (tune->wgs_per_cu < 1 || tune->wgs_per_cu > 4)) return 0;
+    if (!tune_ok(tune)) return 0;
     Carve cv(nullptr, 0);
     int *o, *q, nwg;
     float* sc;
@@ -577,7 +584,7 @@ disk_status disk_optimize_batch(const disk_batch_meta* meta, const disk_target* 
         x.max_updates = state->max_updates;
     }
     DISK_HIP(launch_optimize(meta->B, desc, taps, targets, theta, psnr_db, steps, status, p, order, queue, scratch,
-                             slot, nwg, meta->max_side, meta->max_T, x, stream),
+                             slot, nwg, meta->max_side, meta->max_T, x, launch_shape(meta, tune).threads, stream),
              "optimize");
     return ok();
 }
@@ -610,7 +617,8 @@ disk_status disk_fit_basis(const disk_batch_meta* meta, const disk_target* desc,
     for (int k = 0; k < meta->B; ++k) {
         if (k > 0) DISK_HIP(launch_continue(desc, taps, theta, k, scale[k], stream), "continuation start");
         DISK_HIP(launch_optimize(1, desc + k, taps, targets, theta, psnr_db + k, steps + k, status + k, *params,
-                                 order, queue, scratch, slot, nwg, meta->max_side, meta->max_T, OptExtra{}, stream),
+                                 order, queue, scratch, slot, nwg, meta->max_side, meta->max_T, OptExtra{},
+                                 launch_shape(&one, nullptr).threads, stream),
                  "optimize");
     }
     return ok();

@@ -120,13 +120,14 @@ struct OptExtra {
     float* loss = nullptr;
     int max_updates = 0;
 };
-int opt_workgroups(int B, int per_cu);
-int opt_default_wgs_per_cu(const disk_batch_meta& m);
+int opt_workgroups(int B, int per_cu, int threads);
+// the built-in launch table (opt_tune.cpp)
+disk_opt_tune opt_default_tune(const disk_batch_meta& m);
 size_t opt_slot_floats(int max_side, int max_L);
 hipError_t launch_optimize(int B, const disk_target* desc, const int* taps, const float* targets, float* theta,
                            float* psnr, int* steps, int* status, const disk_opt_params& p, int* order, int* queue,
                            float* scratch, size_t slot_floats, int nwg, int max_side, int max_T,
-                           const OptExtra& x, hipStream_t s);
+                           const OptExtra& x, int threads, hipStream_t s);
 hipError_t launch_continue(const disk_target* desc, const int* taps, float* theta, int k, float scale,
                            hipStream_t s);
 hipError_t launch_init_radial(int B, const disk_target* desc, const int* taps, const float* targets, float* theta,

@@ -1,24 +1,26 @@
-// Built-in launch table of the persistent optimiser: resident work-groups per
-// compute unit for a batch, by the batch's maximum side and size.  The rows
-// are written by the project's autotuner (paper_2512_04556_amd/autotune.py),
-// which times each candidate on seeded batches of the side bucket and keeps
-// the fastest.
+// Built-in launch table of the persistent optimiser: the work-group size and
+// the resident work-groups per compute unit for a batch, by its size and its
+// largest side.  The rows are written by the project's autotuner
+// (paper_2512_04556_amd/autotune.py), which times every candidate shape on
+// seeded batches of each bucket and keeps the fastest.
 #include "internal.hpp"
 
 namespace disk {
 
 namespace {
 struct TuneRow {
-    int max_side_upto;   // the row applies to batches whose largest side is at most this
+    int max_B;          // the row applies to batches of at most this many targets
+    int max_side_upto;  // ... whose largest side is at most this
+    int threads;
     int wgs_per_cu;
 };
 #include "opt_tune_table.inc"
 }  // namespace
 
-int opt_default_wgs_per_cu(const disk_batch_meta& m) {
+disk_opt_tune opt_default_tune(const disk_batch_meta& m) {
     for (const TuneRow& r : kTuneRows)
-        if (m.max_side <= r.max_side_upto) return r.wgs_per_cu;
-    return 4;
+        if (m.B <= r.max_B && m.max_side <= r.max_side_upto) return disk_opt_tune{r.threads, r.wgs_per_cu};
+    return disk_opt_tune{256, 4};
 }
 
 }  // namespace disk

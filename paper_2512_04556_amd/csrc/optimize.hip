@@ -29,8 +29,11 @@
 
 namespace disk {
 
+// Work-group sizes: 256 threads (four resident per CU, one target each) for
+// large batches; 1024 threads (one per CU, sixteen waves on one target) for
+// batches too small to fill the chip.
 constexpr int kOptThreads = 256;
-constexpr int kOptWaves = kOptThreads / 64;
+constexpr int kOptThreadsWide = 1024;
 constexpr int kMaxT = DISK_MAX_LAYERS * DISK_MAX_TAPS;  // 256
 constexpr int kChunk = 8;                               // taps per gradient chunk
 
@@ -75,7 +78,8 @@ __device__ __forceinline__ const float* at(const float* base, int idx) {
 
 __device__ __forceinline__ int opt_pad(int M) { return (M + 1) / 2 + 1; }
 
-// Reduce v over the work-group in a fixed order; every thread gets the sum.
+// Reduce v over the work-group (NW waves) in a fixed order; every thread gets the sum.
+template <int NW>
 __device__ __forceinline__ float wg_sum(float v, float* red) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     v = wave_sum(v);
@@ -84,10 +88,11 @@ __device__ __forceinline__ float wg_sum(float v, float* red) {
     __syncthreads();
     float s = 0.0f;
 #pragma unroll
-    for (int w = 0; w < kOptWaves; ++w) s += red[w];
+    for (int w = 0; w < NW; ++w) s += red[w];
     return s;
 }
 
+template <int NW>
 __device__ __forceinline__ float wg_max(float v, float* red) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     v = wave_max(v);
@@ -96,7 +101,7 @@ __device__ __forceinline__ float wg_max(float v, float* red) {
     __syncthreads();
     float s = red[0];
 #pragma unroll
-    for (int w = 1; w < kOptWaves; ++w) s = fmaxf(s, red[w]);
+    for (int w = 1; w < NW; ++w) s = fmaxf(s, red[w]);
     return s;
 }
 
@@ -211,12 +216,12 @@ struct LossOut {
 // Blocks that miss `box` (where the sum is zero, or not needed) take 0 without
 // reading; of those, the ones that also miss `zbox` are skipped unless Out
 // needs every pixel.
-template <int SGN, class Out>
+template <int NW, int SGN, class Out>
 __device__ void gather_layer(const float* __restrict__ src, const TapO* tp, int N, const Walk& wk, Out& out,
                              const Box& box, const Box& zbox) {
     const int wave = threadIdx.x >> 6;
     const int S = wk.S;
-    for (int blk = wave; blk < wk.nblk; blk += kOptWaves) {
+    for (int blk = wave; blk < wk.nblk; blk += NW) {
         const bool hit = block_meets(wk, blk, box);
         if (!hit && !Out::kEvery && !block_meets(wk, blk, zbox)) continue;
         int x, y;
@@ -267,7 +272,7 @@ __device__ void gather_layer(const float* __restrict__ src, const TapO* tp, int 
 // reads).  The sums go through the fixed-order wave + LDS reduction into sS.
 constexpr int kFuseS = 8;      // taps whose sums the fused pass accumulates
 constexpr int kFuseMax = 12;   // taps per layer up to which the fused pass runs
-template <int NS, int NT>
+template <int NW, int NS, int NT>
 __device__ __forceinline__ void fused_backward(const float* __restrict__ G, float* X, const TapO* tp, int N,
                                                const Walk& wk, float (*sS)[4], float* red, const Box& box) {
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
@@ -287,7 +292,7 @@ __device__ __forceinline__ void fused_backward(const float* __restrict__ G, floa
             all_in = all_in && tp[k].inside;
         }
     }
-    for (int blk = wave; blk < wk.nblk; blk += kOptWaves) {
+    for (int blk = wave; blk < wk.nblk; blk += NW) {
         // outside the box of X: X = 0 (no sums) and G' is not needed
         if (!block_meets(wk, blk, box)) continue;
         int x, y;
@@ -370,12 +375,15 @@ __device__ __forceinline__ void fused_backward(const float* __restrict__ G, floa
     if (tid < 4 * ns) {
         const int k = tid >> 2, ab = tid & 3;
         float v = 0.0f;
-        for (int w = 0; w < kOptWaves; ++w) v += red[(w * NS + k) * 4 + ab];
+        for (int w = 0; w < NW; ++w) v += red[(w * NS + k) * 4 + ab];
         sS[k][ab] = v;
     }
 }
 
-__global__ __launch_bounds__(kOptThreads, 4) void opt_kernel(OptArgs a) {
+template <int NTH>
+__global__ __launch_bounds__(NTH, NTH == kOptThreads ? 4 : 1) void opt_kernel(OptArgs a) {
+    constexpr int kOptWaves = NTH / 64;
+    constexpr int kOptThreads = NTH;
     __shared__ float th[kMaxT * 3], am[kMaxT * 3], av[kMaxT * 3], gr[kMaxT * 3];
     __shared__ TapO tap[kMaxT];
     __shared__ float sS[kMaxT][4];
@@ -433,20 +441,22 @@ __global__ __launch_bounds__(kOptThreads, 4) void opt_kernel(OptArgs a) {
         const float n = static_cast<float>(M) * M;
 
         // ---- target setup: parameters, moments, zeroed canvases, peak -------
-        float* am_g = a.adam_m ? a.adam_m + 3 * static_cast<size_t>(d.theta_off) : nullptr;
-        float* av_g = a.adam_v ? a.adam_v + 3 * static_cast<size_t>(d.theta_off) : nullptr;
-        for (int i = tid; i < 3 * T; i += kOptThreads) {
-            th[i] = theta_g[i];
-            am[i] = am_g ? am_g[i] : 0.0f;
-            av[i] = av_g ? av_g[i] : 0.0f;
+        {
+            const float* am_g = a.adam_m ? a.adam_m + 3 * static_cast<size_t>(d.theta_off) : nullptr;
+            const float* av_g = a.adam_v ? a.adam_v + 3 * static_cast<size_t>(d.theta_off) : nullptr;
+            for (int i = tid; i < 3 * T; i += kOptThreads) {
+                th[i] = theta_g[i];
+                am[i] = am_g ? am_g[i] : 0.0f;
+                av[i] = av_g ? av_g[i] : 0.0f;
+            }
         }
-        // learning-rate unit of the offsets: pixels, or the target's half-width
-        const float ounit = a.p.offset_units == DISK_OFFSETS_HALF_WIDTH ? 0.5f * static_cast<float>(M - 1) : 1.0f;
+        // the last schedule position this call may reach
+        const int step_end = a.max_updates > 0 ? min(a.p.max_steps, s0 + a.max_updates) : a.p.max_steps;
         for (size_t i = tid; i < SS * L; i += kOptThreads) slot[i] = 0.0f;
         if (tid < 4 * (DISK_MAX_LAYERS + 1)) s_box[tid >> 2][tid & 3] = (tid & 1) ? -1 : M;   // empty: the canvases are zero
         float pk = -INFINITY;
         for (int i = tid; i < M * M; i += kOptThreads) pk = fmaxf(pk, tgt[i]);
-        pk = wg_max(pk, red);
+        pk = wg_max<kOptWaves>(pk, red);
         const float inv_pk2 = 1.0f / (pk * pk);
         // beta^t after the s0 updates already applied (the same products an
         // uninterrupted run forms one step at a time)
@@ -541,10 +551,10 @@ __global__ __launch_bounds__(kOptThreads, 4) void opt_kernel(OptArgs a) {
                 const Box bo = load_box(s_box[l + 1]);
                 if (l < L - 1) {
                     StoreOut o{slot + (l + 1) * SS};
-                    gather_layer<1>(src, tap + t0[l], ntap[l], wk, o, bo, load_box(s_pbox[l + 1]));
+                    gather_layer<kOptWaves, 1>(src, tap + t0[l], ntap[l], wk, o, bo, load_box(s_pbox[l + 1]));
                 } else {
                     LossOut o{slot, tgt, M, a.p.loss == DISK_LOSS_CHARBONNIER, pk, inv_pk2, n, ce, 0.0f, 0.0f};
-                    gather_layer<1>(src, tap + t0[l], ntap[l], wk, o, bo, bo);
+                    gather_layer<kOptWaves, 1>(src, tap + t0[l], ntap[l], wk, o, bo, bo);
                     se = o.se;
                     ch = o.ch;
                 }
@@ -561,8 +571,8 @@ __global__ __launch_bounds__(kOptThreads, 4) void opt_kernel(OptArgs a) {
                 se = o.se;
                 ch = o.ch;
             }
-            se = wg_sum(se, red);
-            if (a.p.loss == DISK_LOSS_CHARBONNIER) ch = wg_sum(ch, red);
+            se = wg_sum<kOptWaves>(se, red);
+            if (a.p.loss == DISK_LOSS_CHARBONNIER) ch = wg_sum<kOptWaves>(ch, red);
             const float nmse = se * inv_pk2 / n;
             loss = a.p.loss == DISK_LOSS_CHARBONNIER ? ch / n : nmse;
             psnr = nmse > 0.0f ? -10.0f * log10f(nmse) : INFINITY;
@@ -574,7 +584,7 @@ __global__ __launch_bounds__(kOptThreads, 4) void opt_kernel(OptArgs a) {
                 status = 1;
                 break;
             }
-            if (step >= a.p.max_steps || (a.max_updates > 0 && step - s0 >= a.max_updates)) break;
+            if (step >= step_end) break;
 
             // ---- backward ----------------------------------------------------
             for (int l = L - 1; l >= 0; --l) {
@@ -696,7 +706,7 @@ __global__ __launch_bounds__(kOptThreads, 4) void opt_kernel(OptArgs a) {
                         __syncthreads();
                     }
                     // correlations of the first taps and G_l (1-based) in one pass; G_l replaces X_l
-                    if (fuse) fused_backward<kFuseS, kFuseMax>(G, slot + l * SS, tp, N, wk, sS, red, load_box(s_box[l]));
+                    if (fuse) fused_backward<kOptWaves, kFuseS, kFuseMax>(G, slot + l * SS, tp, N, wk, sS, red, load_box(s_box[l]));
                 }
                 __syncthreads();
                 // dTheta of this layer's taps
@@ -715,7 +725,7 @@ __global__ __launch_bounds__(kOptThreads, 4) void opt_kernel(OptArgs a) {
                     StoreOut o{slot + l * SS};
                     // needed (and written) only in X_l's box: the canvas keeps its zeros elsewhere
                     const Box none{M, -1, M, -1};
-                    gather_layer<-1>(G, tp, N, wk, o, load_box(s_box[l]), none);
+                    gather_layer<kOptWaves, -1>(G, tp, N, wk, o, load_box(s_box[l]), none);
                 }
                 __syncthreads();
             }
@@ -728,7 +738,9 @@ __global__ __launch_bounds__(kOptThreads, 4) void opt_kernel(OptArgs a) {
             b1t *= a.p.beta1;
             b2t *= a.p.beta2;
             const float bc1 = 1.0f - b1t, bc2 = 1.0f - b2t;
-            const float lr_o = lr * ounit;
+            // learning-rate unit of the offsets: pixels, or the target's half-width
+            const float lr_o =
+                a.p.offset_units == DISK_OFFSETS_HALF_WIDTH ? lr * (0.5f * static_cast<float>(M - 1)) : lr;
             for (int i = tid; i < 3 * T; i += kOptThreads) {
                 const float g = gr[i];
                 const float m = fmaf(a.p.beta1, am[i], (1.0f - a.p.beta1) * g);
@@ -740,10 +752,14 @@ __global__ __launch_bounds__(kOptThreads, 4) void opt_kernel(OptArgs a) {
             __syncthreads();
         }
 
-        for (int i = tid; i < 3 * T; i += kOptThreads) {
-            theta_g[i] = th[i];
-            if (am_g) am_g[i] = am[i];
-            if (av_g) av_g[i] = av[i];
+        {
+            float* am_g = a.adam_m ? a.adam_m + 3 * static_cast<size_t>(d.theta_off) : nullptr;
+            float* av_g = a.adam_v ? a.adam_v + 3 * static_cast<size_t>(d.theta_off) : nullptr;
+            for (int i = tid; i < 3 * T; i += kOptThreads) {
+                theta_g[i] = th[i];
+                if (am_g) am_g[i] = am[i];
+                if (av_g) av_g[i] = av[i];
+            }
         }
         if (tid == 0) {
             a.psnr[b] = psnr;
@@ -818,13 +834,13 @@ hipError_t launch_continue(const disk_target* desc, const int* taps, float* thet
 }
 
 // Resident work-groups: `per_cu` per compute unit (each owns one target at a
-// time), at most one per target.
-int opt_workgroups(int B, int per_cu) {
+// time; at most 4 of 256 threads, or 1 of 1024), at most one per target.
+int opt_workgroups(int B, int per_cu, int threads) {
     int dev = 0, n = 0;
     if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
         n <= 0)
         n = 256;
-    per_cu = std::max(1, std::min(per_cu, 4));
+    per_cu = std::max(1, std::min(per_cu, threads == kOptThreadsWide ? 1 : 4));
     return std::max(1, std::min(B, per_cu * n));
 }
 
@@ -836,12 +852,15 @@ size_t opt_slot_floats(int max_side, int max_L) {
 hipError_t launch_optimize(int B, const disk_target* desc, const int* taps, const float* targets, float* theta,
                            float* psnr, int* steps, int* status, const disk_opt_params& p, int* order, int* queue,
                            float* scratch, size_t slot_floats, int nwg, int max_side, int max_T,
-                           const OptExtra& x, hipStream_t s) {
+                           const OptExtra& x, int threads, hipStream_t s) {
     hipLaunchKernelGGL(opt_order_kernel, dim3(1), dim3(1024), 0, s, B, desc, taps, order, queue, x.ticks);
     OptArgs a{B,     desc,  taps,    targets,     theta,    psnr,     steps,   status, p,
               order, queue, scratch, slot_floats, max_side, max_T,    x.ticks, x.adam_m, x.adam_v,
               x.start, x.loss, x.max_updates};
-    hipLaunchKernelGGL(opt_kernel, dim3(nwg), dim3(kOptThreads), 0, s, a);
+    if (threads == kOptThreadsWide)
+        hipLaunchKernelGGL(opt_kernel<kOptThreadsWide>, dim3(nwg), dim3(kOptThreadsWide), 0, s, a);
+    else
+        hipLaunchKernelGGL(opt_kernel<kOptThreads>, dim3(nwg), dim3(kOptThreads), 0, s, a);
     return hipGetLastError();
 }
 

@@ -29,6 +29,7 @@ __all__ = [
     "gaussian_kernel", "aniso_gaussian_kernel", "disk_kernel", "ellipse_kernel",
     "polygon_kernel", "ring_kernel", "star_kernel", "shape_kernel",
     "random_theta", "TargetBatch", "shape_batch", "mixed_batch", "pack_targets",
+    "line_kernel", "direction_map", "pseudo_depth", "tilt_shift_map",
 ]
 
 
@@ -201,6 +202,26 @@ def direction_map(H: int, W: int, kind: str = "radial") -> np.ndarray:
     r = np.hypot(dx, dy)
     a = np.arctan2(dy, dx) + (0.0 if kind == "radial" else math.pi / 2.0)
     return np.stack([r / r.max(), np.mod(a, math.pi) / math.pi]).astype(np.float32)
+
+
+def pseudo_depth(H: int, W: int, seed: int = 12, relief: float = 0.15, period: float = 256.0) -> np.ndarray:
+    """Float64 [H][W] pseudo-depth in [0, 1]: a ground plane receding from
+    the bottom row (depth 0) to the top row (depth 1), plus smooth relief
+    (one octave of gradient noise, amplitude ``relief``), clipped to [0, 1]."""
+    g = rng(seed)
+    ramp = 1.0 - np.arange(H, dtype=np.float64)[:, None] / max(H - 1, 1)
+    d = ramp + relief * gradient_noise(H, W, period, g) / 0.7
+    return np.clip(d, 0.0, 1.0)
+
+
+def tilt_shift_map(H: int, W: int, focus: float = 0.5, depth_of_field: float = 0.08, falloff: float = 0.35,
+                   seed: int = 12) -> np.ndarray:
+    """Parameter map [1][H][W] of a tilt-shift effect: zero blur within
+    ``depth_of_field`` of the focal depth, growing linearly with the
+    pseudo-depth distance beyond it and saturating at ``falloff``."""
+    d = pseudo_depth(H, W, seed)
+    b = np.clip((np.abs(d - focus) - depth_of_field) / falloff, 0.0, 1.0)
+    return b[None].astype(np.float32)
 
 
 def _polygon_sdf(x, y, n: int, R: float, rot: float):

@@ -140,8 +140,8 @@ def test_optimiser_and_basis_fit_validation():
     # misaligned finish_ticks
     assert L.disk_optimize_batch(*args, P(0x1008), ctypes.byref(prm), None, None, fake, ws, None) == -1
     # launch shape out of range; Adam moments given without the other
-    for w in (0, 5):
-        tune = disk.DiskOptTune(w)
+    for th, w in ((256, 0), (256, 5), (1024, 2), (512, 1)):
+        tune = disk.DiskOptTune(th, w)
         assert L.disk_optimize_batch(*args, None, ctypes.byref(prm), None, ctypes.byref(tune), fake, ws, None) == -1
         assert L.disk_optimize_workspace_size(ctypes.byref(meta), ctypes.byref(tune)) == 0
     st = disk.DiskOptState(fake, None, None, None, 0)
@@ -149,7 +149,7 @@ def test_optimiser_and_basis_fit_validation():
     st = disk.DiskOptState(fake, fake, None, None, -1)
     assert L.disk_optimize_batch(*args, None, ctypes.byref(prm), ctypes.byref(st), None, fake, ws, None) == -1
     # more resident work-groups need more workspace
-    t1, t4 = disk.DiskOptTune(1), disk.DiskOptTune(4)
+    t1, t4 = disk.DiskOptTune(256, 1), disk.DiskOptTune(256, 4)
     assert (L.disk_optimize_workspace_size(ctypes.byref(meta), ctypes.byref(t1)) <=
             L.disk_optimize_workspace_size(ctypes.byref(meta), ctypes.byref(t4)))
     # workspace too small

@@ -212,15 +212,19 @@ def _jittered(batch, seed, sd=0.3):
     return th0 + j
 
 
-@pytest.mark.parametrize("loss", [Lo.NMSE, Lo.CHARBONNIER])
-def test_loss_and_theta_trajectory_vs_oracle(dev, loss):
+@pytest.mark.parametrize("loss,shape", [(Lo.NMSE, None), (Lo.CHARBONNIER, None), (Lo.NMSE, (1024, 1)),
+                                        (Lo.CHARBONNIER, (256, 2))])
+def test_loss_and_theta_trajectory_vs_oracle(dev, loss, shape):
     """Three targets (sides 21..45, 4 x 12 and 3 x 8 taps) from a jittered
     radial start (no symmetric zero gradients): after 5, 10 and 20 steps the
     reported loss agrees with the oracle's to 2e-5 relative, the PSNR to
     0.01 dB, and Theta element by element (offsets 1e-3 px, weights 2e-6).
     Bars: FP32 gradients perturbed by 1e-6 relative move the FP64 iterate by
     <= 2e-4 px and 3e-7 in the weights over 20 steps; a Charbonnier epsilon
-    10 % off moves the weights by 5e-6 and the loss by 1e-5 relative."""
+    10 % off moves the weights by 5e-6 and the loss by 1e-5 relative.  Launch
+    shapes: the built-in table's, 1024-thread work-groups (16 waves on one
+    target), and 256-thread ones at two per CU."""
+    tune = None if shape is None else disk.opt_tune(shape[1], shape[0])
     for seed, L, N in ((61, 4, 12), (62, 3, 8)):
         batch = mixed_batch(3, seed=seed, side=(21, 45), fixed_L=L, fixed_N=N)
         th0 = _jittered(batch, seed)
@@ -232,7 +236,7 @@ def test_loss_and_theta_trajectory_vs_oracle(dev, loss):
             lo = torch.empty(batch.B, device="cuda")
             ps, st, stat = disk.disk_optimize_batch(bt, th, disk.OptParams(max_steps=n, lr0=1e-2, lr1=1e-3,
                                                                            loss=loss),
-                                                    state=disk.OptState(loss=lo))
+                                                    state=disk.OptState(loss=lo), tune=tune)
             th, ps, lo = th.cpu().numpy().astype(np.float64), ps.cpu().numpy(), lo.cpu().numpy()
             p = Ad.OptParams(max_steps=n, lr0=1e-2, lr1=1e-3, loss=loss)
             for b in range(batch.B):

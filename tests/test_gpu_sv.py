@@ -172,9 +172,9 @@ def test_sv_bench_configuration_full_frame(dev):
 def test_sv_2d_4k_bf16_sampled(dev):
     """The 2-D workload at full size: 3840x2160x3 BF16 I/O, 8 x 8 basis of
     4 x 12 taps with halos above the pipelined kernels' range, 2-D map.  Two
-    seeded 32 x 32 output crops against the oracle run on the crop plus a
-    margin of the summed halos (the margin's own clamping cannot reach the
-    crop)."""
+    seeded interior 32 x 32 output crops, a top-border, a left-border and the
+    bottom-right corner crop against the oracle run on the crop plus a margin
+    of the summed halos (the margin's own clamping cannot reach the crop)."""
     taps = [12, 12, 12, 12]
     basis = _basis(64, taps, seed=400, r0=4.0, dr=0.4)
     H, W = 2160, 3840
@@ -187,11 +187,15 @@ def test_sv_2d_4k_bf16_sampled(dev):
     m = int(sum(b.halo))
     xb = bf16_round(img)
     rng = np.random.default_rng(4)
-    for _ in range(2):
-        y0, x0 = int(rng.integers(m, H - 32 - m)), int(rng.integers(m, W - 32 - m))
-        win = (slice(y0 - m, y0 + 32 + m), slice(x0 - m, x0 + 32 + m))
-        want = SV.sv_chain(xb[:, win[0], win[1]], P[:, win[0], win[1]].astype(np.float64),
-                           basis.astype(np.float64), [8, 8], taps)[:, m:m + 32, m:m + 32]
+    crops = [(int(rng.integers(m, H - 32 - m)), int(rng.integers(m, W - 32 - m))) for _ in range(2)]
+    # the top border, the bottom-right corner and the left border: the CLAMP
+    # edge and the ends of the tile runs (the crop's margin is clipped at the
+    # image's edge, where the oracle's own CLAMP border is the image's)
+    crops += [(0, 1900), (H - 32, W - 32), (1000, 0)]
+    for y0, x0 in crops:
+        ya, yb, xa, xb_ = max(0, y0 - m), min(H, y0 + 32 + m), max(0, x0 - m), min(W, x0 + 32 + m)
+        want = SV.sv_chain(xb[:, ya:yb, xa:xb_], P[:, ya:yb, xa:xb_].astype(np.float64),
+                           basis.astype(np.float64), [8, 8], taps)[:, y0 - ya:y0 - ya + 32, x0 - xa:x0 - xa + 32]
         e = rel_err(got[:, y0:y0 + 32, x0:x0 + 32], want)
         print(f"sv 2d 4k bf16 crop ({y0},{x0}) halo={b.halo}: {e:.2e}")
         assert e <= TOL_BF16
@@ -230,10 +234,12 @@ def test_sv_halo_just_beyond_padded_tile(dev):
     assert rel_err(to_np(out), want) <= TOL_F32
 
 
-def test_basis_rotate_and_angle_effect(dev):
+@pytest.mark.parametrize("kind", ["rotational", "radial"])
+def test_basis_rotate_and_angle_effect(dev, kind):
     """Angle axis built on the device (offsets rotated per angle, FP32)
-    against the FP64 oracle's rotation, then a rotational-blur filter with
-    that 2-D basis (blur length x direction) against the oracle."""
+    against the FP64 oracle's rotation, then a rotational-blur or radial
+    motion-blur filter with that 2-D basis (blur length x direction) against
+    the oracle."""
     from oracle import interp as IP
     from synth import direction_map
     taps = [6, 6, 6]
@@ -245,7 +251,7 @@ def test_basis_rotate_and_angle_effect(dev):
     assert np.abs(to_np(got) - want).max() <= 2e-6 * np.abs(want).max()
     H, W = 70, 120
     img = noise_image(H, W, 3, seed=9, n_rects=10)
-    P = direction_map(H, W, "rotational")
+    P = direction_map(H, W, kind)
     out, b = _run(to_np(got).astype(np.float32), taps, [4, 9], img, P)
     ref = SV.sv_chain(img.astype(np.float64), P.astype(np.float64), want, [4, 9], taps)
     assert rel_err(to_np(out), ref) <= TOL_F32
@@ -313,4 +319,38 @@ def test_sv_frames_bench_launch_and_graph_replay(dev):
                           basis.astype(np.float64), [16], taps)[:, m:m + 96, m:m + 96]
         e = rel_err(got[f][:, y0:y0 + 96, x0:x0 + 96], ref)
         print(f"frame {f} crop ({y0},{x0}): {e:.2e}")
+        assert e <= TOL_F32
+
+
+def test_tilt_shift_from_pseudo_depth(dev):
+    """Tilt-shift (the depth-driven effect of the paper's spatially varying
+    examples): blur from the distance of a pseudo-depth map to the focal
+    depth, with a disk-like 1-D basis of 16 entries (4 x 8 taps).  A 96 x 160
+    image against the oracle in full, and the 1920 x 1080 frame on a
+    top-border crop, a bottom-corner crop and an interior crop, each with a
+    margin of the summed halos (clipped at the image's edges, which the
+    oracle treats as the same CLAMP border)."""
+    from synth import tilt_shift_map
+    taps = [8, 8, 8, 8]
+    basis = _basis(16, taps, seed=320, r0=0.8, dr=0.5)
+    H, W = 96, 160
+    img = noise_image(H, W, 3, seed=31, n_rects=12)
+    P = tilt_shift_map(H, W, seed=5)
+    say("tilt-shift small")
+    out, b = _run(basis, taps, [16], img, P)
+    want = SV.sv_chain(img.astype(np.float64), P.astype(np.float64), basis.astype(np.float64), [16], taps)
+    assert rel_err(to_np(out), want) <= TOL_F32
+    H, W = 1080, 1920
+    img = noise_image(H, W, 3, seed=32, n_rects=60)
+    P = tilt_shift_map(H, W)
+    say("tilt-shift 1080p")
+    out, b = _run(basis, taps, [16], img, P)
+    got = to_np(out)
+    m = int(sum(b.halo))
+    for y0, x0 in ((0, 700), (H - 64, W - 64), (500, 900)):
+        ya, yb, xa, xb = max(0, y0 - m), min(H, y0 + 64 + m), max(0, x0 - m), min(W, x0 + 64 + m)
+        ref = SV.sv_chain(img[:, ya:yb, xa:xb].astype(np.float64), P[:, ya:yb, xa:xb].astype(np.float64),
+                          basis.astype(np.float64), [16], taps)[:, y0 - ya:y0 - ya + 64, x0 - xa:x0 - xa + 64]
+        e = rel_err(got[:, y0:y0 + 64, x0:x0 + 64], ref)
+        print(f"tilt-shift 1080p crop ({y0},{x0}): {e:.2e}")
         assert e <= TOL_F32
