@@ -563,16 +563,41 @@ __global__ __launch_bounds__(256) void loss_final_kernel(const float* __restrict
     if (threadIdx.x == 0) loss_out[0] = buf[0] / static_cast<float>(n);
 }
 
-// Column sums of g [M][N] (FP32): stage 1 writes part[blk][N] for 256-row
-// slabs, stage 2 adds the slabs in order.
+// Column sums of g [M][N] (FP32, N a multiple of 4, at most 1024): stage 1
+// writes part[blk][N] for 256-row slabs, stage 2 adds the slabs in order.
+// Stage 1 reads whole rows as float4: thread t owns column quad q = t % (N/4)
+// of rows r0 + j * rpi (r0 = t / (N/4), rpi = 256 / (N/4) rows per sweep), and
+// the rpi partial sums of each quad are then added in order of r0.
 constexpr int kColRows = 256;
 __global__ __launch_bounds__(256) void colsum_part_kernel(const float* __restrict__ g, int M, int N,
                                                           float* __restrict__ part) {
-    const int r0 = blockIdx.x * kColRows, r1 = min(M, r0 + kColRows);
-    for (int n = threadIdx.x; n < N; n += 256) {
-        float s = 0.0f;
-        for (int r = r0; r < r1; ++r) s += g[static_cast<size_t>(r) * N + n];
-        part[static_cast<size_t>(blockIdx.x) * N + n] = s;
+    __shared__ float4 red[256];
+    const int nq = N >> 2, rpi = 256 / nq;
+    const int t = threadIdx.x, q = t % nq, r0 = t / nq;
+    const int s0 = blockIdx.x * kColRows, s1 = min(M, s0 + kColRows);
+    float4 acc = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    if (r0 < rpi) {
+        const float4* g4 = reinterpret_cast<const float4*>(g);
+        for (int r = s0 + r0; r < s1; r += rpi) {
+            const float4 v = g4[static_cast<size_t>(r) * nq + q];
+            acc.x += v.x;
+            acc.y += v.y;
+            acc.z += v.z;
+            acc.w += v.w;
+        }
+    }
+    red[t] = acc;
+    __syncthreads();
+    if (t < nq) {
+        float4 s = red[t];
+        for (int k = 1; k < rpi; ++k) {
+            const float4 v = red[k * nq + t];
+            s.x += v.x;
+            s.y += v.y;
+            s.z += v.z;
+            s.w += v.w;
+        }
+        reinterpret_cast<float4*>(part + static_cast<size_t>(blockIdx.x) * N)[t] = s;
     }
 }
 // One work-group per column: strided partial sums, then a fixed tree.
@@ -823,6 +848,7 @@ hipError_t net_backward(const float* params, const uint16_t* x0, const float* re
         const int M = B * L.hout * L.hout;
         const uint16_t* xin = act_ptr(ws, w, B, L, x0);
         // bias gradient: column sums of g (FP32)
+        if ((L.cout & 3) != 0 || L.cout > 1024) return hipErrorInvalidValue;   // the column-sum layout
         const int nblk = (M + kColRows - 1) / kColRows;
         hipLaunchKernelGGL(colsum_part_kernel, dim3(nblk), dim3(256), 0, s, g32[cur], M, L.cout, cpart);
         hipLaunchKernelGGL(colsum_final_kernel, dim3(L.cout), dim3(256), 0, s, cpart, nblk, L.cout,
