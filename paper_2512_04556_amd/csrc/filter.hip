@@ -1003,7 +1003,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4, 4)))
         for (int j = 0; j < PY; ++j)
             for (int c = 0; c < C; ++c) nan[j][c] = __builtin_nanf("");
         for (; tile < tend; tile += nwg) {
-            const int f = tile / ntf, tt = tile - f * ntf;
+            const int f = MODE == 0 ? tile / ntf : 0, tt = tile - f * ntf;
             sv_store<C, TOut, PY>(Y + static_cast<size_t>(f) * C * plane, plane, W, H, (tt % tiles_x) * kTW + lx,
                                   (tt / tiles_x) * TH + lyb, nan);
         }
@@ -1022,8 +1022,27 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4, 4)))
     float stg[kPipeRPW][kPipeNQ][C];
     float pv[PY][DIMS];
     float gv[PY][C];   // corr: the tile's output gradient at the lane's pixels
-    auto issue = [&](int t) {
-        const int f = t / ntf, tt = t - f * ntf;
+    // (frame, tile within the frame) of the current and the prefetched tile,
+    // advanced by nwg without a division (nwg <= tiles per frame is not
+    // assumed); chain layers (MODE != 0) always cover one frame
+    int cur_f = 0, cur_t = tile;
+    if constexpr (MODE == 0) {
+        while (cur_t >= ntf) {
+            cur_t -= ntf;
+            ++cur_f;
+        }
+    }
+    int nxt_f = cur_f, nxt_t = cur_t;
+    auto advance = [&](int& f, int& t) {
+        t += nwg;
+        if constexpr (MODE == 0) {
+            while (t >= ntf) {
+                t -= ntf;
+                ++f;
+            }
+        }
+    };
+    auto issue = [&](int f, int tt) {
         const size_t xfo = static_cast<size_t>(f) * C * plane, pfo = static_cast<size_t>(f) * pfs * plane;
         const int tx0 = (tt % tiles_x) * kTW, ty0 = (tt / tiles_x) * TH;
         uint32_t gx[kPipeNQ];
@@ -1083,7 +1102,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4, 4)))
         }
     };
 
-    issue(tile);
+    issue(cur_f, cur_t);
     for (;;) {
         // the staged registers of `tile` -> LDS
 #pragma unroll
@@ -1104,7 +1123,8 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4, 4)))
 #pragma unroll
         for (int j = 0; j < PY; ++j) asm volatile("" ::"v"(ta[j]), "v"(tb[j]), "v"(kk[j]));
         __syncthreads();
-        const int fr = tile / ntf, tr = tile - fr * ntf;
+        const int fr = cur_f, tr = cur_t;
+        advance(nxt_f, nxt_t);
         TOut* const Yf = Y + static_cast<size_t>(fr) * C * plane;
         const int x = (tr % tiles_x) * kTW + lx, y0 = (tr / tiles_x) * TH + lyb;
         const int next = tile + nwg;
@@ -1117,7 +1137,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4, 4)))
                     xq[j][c] = gv[j][c];
                     asm volatile("" ::"v"(xq[j][c]));   // this tile's X ahead of the prefetch
                 }
-            if (next < tend) issue(next);
+            if (next < tend) issue(nxt_f, nxt_t);
             float acc[PY][C];
             fused_tile_taps<C, PY, ROWB>(s, acc, xq, base0, tabL, N, min(N, kCorrTaps));
             sv_store<C, TOut, PY>(Yf, plane, W, H, x, y0, acc);
@@ -1130,16 +1150,18 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4, 4)))
                     gc[j][c] = gv[j][c];
                     asm volatile("" ::"v"(gc[j][c]));   // this tile's G ahead of the prefetch
                 }
-            if (next < tend) issue(next);
+            if (next < tend) issue(nxt_f, nxt_t);
             corr_tile_taps<C, PY, ROWB>(s, gc, base0, tabL, N);
         } else {
-            if (next < tend) issue(next);
+            if (next < tend) issue(nxt_f, nxt_t);
             float acc[PY][C];
             sv_tile_taps<C, DIMS, PY, ROWB, TL>(acc, ta, tb, kk, base0, rowB, table, tap0, N, T, tabL);
             sv_store<C, TOut, PY>(Yf, plane, W, H, x, y0, acc);
         }
         if (next >= tend) break;
         tile = next;
+        cur_f = nxt_f;
+        cur_t = nxt_t;
         __syncthreads();  // every wave is done reading this tile before the next is written
     }
     corr_finish();
