@@ -1196,8 +1196,11 @@ __global__ __launch_bounds__(256) void sv_pass_global_kernel(const TIn* __restri
     sv_decode<DIMS, 1>(pv, G0, G1, ta, tb, kk);
 #pragma unroll
     for (int c = 0; c < C; ++c) acc[c] = 0.0f;
-    for (int i = 0; i < N; ++i) {
-        const float* r = table + (static_cast<size_t>(kk[0]) * T + tap0 + i) * RW;
+    // one base per plane, 32-bit element offsets inside it (H W <= 2^30)
+    const TIn* Xc[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) Xc[c] = X + c * plane;
+    auto tap = [&](const float* __restrict__ r) {
         float nx, ny, w;
         if (DIMS == 1) {
             nx = fmaf(ta[0], r[1], r[0]);
@@ -1215,19 +1218,29 @@ __global__ __launch_bounds__(256) void sv_pass_global_kernel(const TIn* __restri
         const float c01 = wy0 * fx, c00 = wy0 - c01;
         const float c11 = wy1 * fx, c10 = wy1 - c11;
         const int x0 = x + static_cast<int>(flx), y0 = y + static_cast<int>(fly);
-        const int xa = min(max(x0, 0), W - 1), xb = min(max(x0 + 1, 0), W - 1);
-        const size_t ra = static_cast<size_t>(min(max(y0, 0), H - 1)) * W;
-        const size_t rb = static_cast<size_t>(min(max(y0 + 1, 0), H - 1)) * W;
+        const uint32_t xa = static_cast<uint32_t>(min(max(x0, 0), W - 1));
+        const uint32_t xb = static_cast<uint32_t>(min(max(x0 + 1, 0), W - 1));
+        const uint32_t ra = static_cast<uint32_t>(min(max(y0, 0), H - 1)) * static_cast<uint32_t>(W);
+        const uint32_t rb = static_cast<uint32_t>(min(max(y0 + 1, 0), H - 1)) * static_cast<uint32_t>(W);
 #pragma unroll
         for (int c = 0; c < C; ++c) {
-            const size_t o = c * plane;
+            constexpr uint32_t E = sizeof(TIn);
             float a = acc[c];
-            a = fmaf(c00, IO<TIn>::load(X, o + ra + xa), a);
-            a = fmaf(c01, IO<TIn>::load(X, o + ra + xb), a);
-            a = fmaf(c10, IO<TIn>::load(X, o + rb + xa), a);
-            a = fmaf(c11, IO<TIn>::load(X, o + rb + xb), a);
+            a = fmaf(c00, IO<TIn>::load(byte_at(Xc[c], (ra + xa) * E), 0), a);
+            a = fmaf(c01, IO<TIn>::load(byte_at(Xc[c], (ra + xb) * E), 0), a);
+            a = fmaf(c10, IO<TIn>::load(byte_at(Xc[c], (rb + xa) * E), 0), a);
+            a = fmaf(c11, IO<TIn>::load(byte_at(Xc[c], (rb + xb) * E), 0), a);
             acc[c] = a;
         }
+    };
+    // a wave whose pixels share one interval reads its coefficient rows at a
+    // wave-uniform address (scalar loads); same arithmetic either way
+    const int k0 = uniform(kk[0]);
+    if (__all(kk[0] == k0)) {
+        const float* e = table + (static_cast<size_t>(k0) * T + tap0) * RW;
+        for (int i = 0; i < N; ++i) tap(e + i * RW);
+    } else {
+        for (int i = 0; i < N; ++i) tap(table + (static_cast<size_t>(kk[0]) * T + tap0 + i) * RW);
     }
 #pragma unroll
     for (int c = 0; c < C; ++c) IO<TOut>::store(Y, c * plane + idx, acc[c]);
