@@ -220,33 +220,50 @@ struct EpStore {  // plain FP32 store; split z writes its own M x N slab
         out[z * slab + static_cast<size_t>(m) * ld + n] = acc;
     }
 };
-struct EpMaskGrad {  // FC input gradient: g = acc * [x > 0], kept in FP32 and BF16
-    float* g32;
+// Input-gradient epilogues (kColSum): g = acc * [x > 0] in FP32 is the
+// gradient of the lower layer's pre-activation; its BF16 rounding is stored
+// for that layer's contractions, and the GEMM sums g over each tile's rows in
+// a fixed order into colpart[(cls nM + m-tile)][n], the partial column sums
+// from which that layer's bias gradient is formed (the FP32 g itself is not
+// stored).
+struct EpMaskGrad {  // FC input gradient
     uint16_t* gq;
     const uint16_t* x;
     int ld;
-    static constexpr bool kStaged = false;
-    __device__ void put(int m, int n, float acc, int) const {
+    float* colpart;
+    static constexpr bool kStaged = false, kColSum = true;
+    static constexpr int cls = 0;
+    __device__ float put(int m, int n, float acc, int) const {
         const size_t i = static_cast<size_t>(m) * ld + n;
         const float g = (x[i] & 0x7fffu) != 0 && !(x[i] & 0x8000u) ? acc : 0.0f;
-        g32[i] = g;
         gq[i] = f32_to_bf16(g);
+        return g;
     }
 };
 
-struct EpSubpix {   // conv input gradient of one parity class: g = acc * [x > 0] at (b, 2j+py, 2i+px, ci)
-    float* g32;
+struct EpSubpix {   // conv input gradient of one parity class at (b, 2j+py, 2i+px, ci)
     uint16_t* gq;
     const uint16_t* x;   // the layer input, NHWC [B][Hin][Hin][Cin]
     int py, px, lgHo, Ho, Cin;
-    static constexpr bool kStaged = false;
-    __device__ void put(int m, int ci, float acc, int) const {
+    float* colpart;
+    int cls;             // the parity class, 2 py + px
+    static constexpr bool kStaged = false, kColSum = true;
+    __device__ float put(int m, int ci, float acc, int) const {
         const int b = m >> (2 * lgHo), j = (m >> lgHo) & (Ho - 1), i = m & (Ho - 1);
         const size_t idx = ((static_cast<size_t>(b) * 2 * Ho + 2 * j + py) * 2 * Ho + 2 * i + px) * Cin + ci;
         const float g = (x[idx] & 0x7fffu) != 0 && !(x[idx] & 0x8000u) ? acc : 0.0f;
-        g32[idx] = g;
         gq[idx] = f32_to_bf16(g);
+        return g;
     }
+};
+
+template <class EP, class = void>
+struct ColSumOf {
+    static constexpr bool value = false;
+};
+template <class EP>
+struct ColSumOf<EP, decltype(void(EP::kColSum))> {
+    static constexpr bool value = EP::kColSum;
 };
 
 // C[M][N] = sum_k A(m, k) B(k, n), B given as Op(n, k).  Block: 64 x 64 tile,
@@ -342,6 +359,34 @@ __global__ __launch_bounds__(256) void gemm_kernel(LA la, LB lb, EP ep, int M, i
             if (row0 + rr < M && col0 + c8 < N)
                 ep.put8(row0 + rr, col0 + c8, *reinterpret_cast<const uint4*>(smem + rr * kCs + c8));
         }
+    } else if constexpr (ColSumOf<EP>::value) {
+        // column sums of the stored values over the tile's rows: this lane's
+        // eight rows in order, then the four lane groups of a column (fixed
+        // butterfly), then the two waves along M through LDS
+        float cs[2];
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            cs[j] = 0.0f;
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int m = row0 + wm * 32 + i * 16 + 4 * (lane >> 4) + r;
+                    const int n = col0 + wn * 32 + j * 16 + (lane & 15);
+                    if (m < M && n < N) cs[j] += ep.put(m, n, acc[i][j][r], blockIdx.z);
+                }
+            cs[j] += __shfl_xor(cs[j], 16, 64);
+            cs[j] += __shfl_xor(cs[j], 32, 64);
+        }
+        float* red = reinterpret_cast<float*>(smem);   // 2 x 64 floats over the operand tiles
+        __syncthreads();
+        if (lane < 16) {
+#pragma unroll
+            for (int j = 0; j < 2; ++j) red[wm * kBN + wn * 32 + j * 16 + lane] = cs[j];
+        }
+        __syncthreads();
+        if (t < kBN && col0 + t < N)
+            ep.colpart[(static_cast<size_t>(ep.cls) * nM + mt) * N + col0 + t] = red[t] + red[kBN + t];
     } else {
 #pragma unroll
         for (int i = 0; i < 2; ++i)
@@ -729,6 +774,16 @@ int grid_for(long n) { return static_cast<int>(std::min<long>((n + 255) / 256, 8
 long net_param_count() { return table().params; }
 
 // Workspace layout (offsets in bytes, 256-aligned), for batch B.
+// Rows of partial column sums from which layer i's bias gradient is formed
+// (i < 7): the tiles of the GEMMs that produce its output gradient, i.e. the
+// input gradient of layer i + 1 (four parity classes for a convolution).
+static size_t bias_part_rows(int B, int i) {
+    const Layer& P = table().l[i + 1];
+    const size_t M = static_cast<size_t>(B) * P.hout * P.hout;
+    const size_t nM = (M + kBM - 1) / kBM;
+    return P.conv ? 4 * nM : nM;
+}
+
 NetWs net_ws_layout(int B, bool train) {
     const Table& T = table();
     NetWs w{};
@@ -746,8 +801,9 @@ NetWs net_ws_layout(int B, bool train) {
         w.total = take(0);
         return w;
     }
-    // gradient buffers: the largest layer output (layer 1: 32 x 32 x 32 per sample)
-    size_t gmax = 0, part = 0, cpart = 0;
+    // gradient buffers: BF16 copies of the largest layer output (layer 1: 32 x
+    // 32 x 32 per sample); FP32 only for the output layer's (the loss gradient)
+    size_t gmax = 0, part = 0, cpart = ((static_cast<size_t>(B) + kColRows - 1) / kColRows) * kOut;
     for (int i = 0; i < 8; ++i) {
         const Layer& L = T.l[i];
         const size_t M = static_cast<size_t>(B) * L.hout * L.hout;
@@ -755,10 +811,10 @@ NetWs net_ws_layout(int B, bool train) {
         int S, kc;
         net_wgrad_splits(L.cout, L.Kp, static_cast<int>(M), &S, &kc);
         part = std::max(part, static_cast<size_t>(S) * L.cout * L.Kp);
-        cpart = std::max(cpart, ((M + kColRows - 1) / kColRows) * L.cout);
+        if (i < 7) cpart = std::max(cpart, bias_part_rows(B, i) * L.cout);
     }
-    w.g32[0] = take(gmax * 4);
-    w.g32[1] = take(gmax * 4);
+    w.g32[0] = take(static_cast<size_t>(B) * kOut * 4);
+    w.g32[1] = w.g32[0];
     w.gq[0] = take(gmax * 2);
     w.gq[1] = take(gmax * 2);
     w.part = take(part * 4);
@@ -829,7 +885,7 @@ hipError_t net_backward(const float* params, const uint16_t* x0, const float* re
     const Table& T = table();
     const uint16_t* wp = reinterpret_cast<const uint16_t*>(ws + w.wp);
     const float* yhat = reinterpret_cast<const float*>(ws + w.yhat);
-    float* g32[2] = {reinterpret_cast<float*>(ws + w.g32[0]), reinterpret_cast<float*>(ws + w.g32[1])};
+    float* g32 = reinterpret_cast<float*>(ws + w.g32[0]);
     uint16_t* gq[2] = {reinterpret_cast<uint16_t*>(ws + w.gq[0]), reinterpret_cast<uint16_t*>(ws + w.gq[1])};
     float* part = reinterpret_cast<float*>(ws + w.part);
     float* cpart = reinterpret_cast<float*>(ws + w.cpart);
@@ -837,7 +893,7 @@ hipError_t net_backward(const float* params, const uint16_t* x0, const float* re
         // the loss partials use the column-sum scratch (>= 128 B floats: layer 1's slab count x 32)
         const long n = static_cast<long>(B) * kOut;
         const int nb = static_cast<int>(std::min<long>(kLossBlocks, (n + 1023) / 1024));
-        hipLaunchKernelGGL(loss_grad_kernel, dim3(nb), dim3(256), 0, s, B, yhat, ref, hw, g32[0], gq[0], cpart);
+        hipLaunchKernelGGL(loss_grad_kernel, dim3(nb), dim3(256), 0, s, B, yhat, ref, hw, g32, gq[0], cpart);
         hipLaunchKernelGGL(loss_final_kernel, dim3(1), dim3(256), 0, s, cpart, nb, n, loss_out);
     }
     hipError_t e = hipGetLastError();
@@ -847,12 +903,20 @@ hipError_t net_backward(const float* params, const uint16_t* x0, const float* re
         const Layer& L = T.l[i];
         const int M = B * L.hout * L.hout;
         const uint16_t* xin = act_ptr(ws, w, B, L, x0);
-        // bias gradient: column sums of g (FP32)
-        if ((L.cout & 3) != 0 || L.cout > 1024) return hipErrorInvalidValue;   // the column-sum layout
-        const int nblk = (M + kColRows - 1) / kColRows;
-        hipLaunchKernelGGL(colsum_part_kernel, dim3(nblk), dim3(256), 0, s, g32[cur], M, L.cout, cpart);
-        hipLaunchKernelGGL(colsum_final_kernel, dim3(L.cout), dim3(256), 0, s, cpart, nblk, L.cout,
-                           grad + L.b_off);
+        // bias gradient: column sums of g (FP32).  The output layer's g is the
+        // loss gradient in FP32; every other layer's comes as the partial
+        // column sums that the epilogues of the input-gradient GEMMs of layer
+        // i + 1 left in cpart (one row per tile, parity classes in order)
+        if (i == 7) {
+            if ((L.cout & 3) != 0 || L.cout > 1024) return hipErrorInvalidValue;   // the column-sum layout
+            const int nblk = (M + kColRows - 1) / kColRows;
+            hipLaunchKernelGGL(colsum_part_kernel, dim3(nblk), dim3(256), 0, s, g32, M, L.cout, cpart);
+            hipLaunchKernelGGL(colsum_final_kernel, dim3(L.cout), dim3(256), 0, s, cpart, nblk, L.cout,
+                               grad + L.b_off);
+        } else {
+            hipLaunchKernelGGL(colsum_final_kernel, dim3(L.cout), dim3(256), 0, s, cpart,
+                               static_cast<int>(bias_part_rows(B, i)), L.cout, grad + L.b_off);
+        }
         // weight gradient: dW(co, j) = sum_m g(m, co) x_col(m, j), split over m
         int S, kc;
         net_wgrad_splits(L.cout, L.Kp, M, &S, &kc);
@@ -888,12 +952,12 @@ hipError_t net_backward(const float* params, const uint16_t* x0, const float* re
                     LdSubpixW wb;
                     static_cast<SubpixTap&>(wb) = st;
                     wb.wp = wp + L.wp_off; wb.Kp = L.Kp; wb.Cin = L.cin; wb.K = Kc;
-                    EpSubpix ep{g32[nxt], gq[nxt], xin, py, px, lgHo, L.hout, L.cin};
+                    EpSubpix ep{gq[nxt], xin, py, px, lgHo, L.hout, L.cin, cpart, 2 * py + px};
                     e = gemm(a, wb, ep, M, L.cin, Kc, 1, Kc, s);
                     if (e != hipSuccess) return e;
                 }
         } else {
-            EpMaskGrad ep{g32[nxt], gq[nxt], xin, L.K};
+            EpMaskGrad ep{gq[nxt], xin, L.K, cpart};
             e = gemm(gr, wc, ep, M, L.K, L.cout, 1, L.cout, s);
         }
         e = hipGetLastError();

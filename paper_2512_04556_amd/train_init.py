@@ -1,6 +1,6 @@
 """Train the learned initialiser and write its parameters.
 
-    python -m paper_2512_04556_amd.train_init [--n 50000] [--epochs 40] [--out PATH]
+    python -m paper_2512_04556_amd.train_init [--n 150000] [--epochs 60] [--out PATH]
 
 Training data: ``n`` synthetic targets (odd sides 15..127, the shape
 families of the batched-optimisation workload, 4 layers x 12 taps), each
@@ -120,8 +120,8 @@ def train(x, hw, theta, epochs=40, batch=256, lr=1e-3, val=2048, seed=0, log=pri
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--n", type=int, default=50000)
-    ap.add_argument("--epochs", type=int, default=40)
+    ap.add_argument("--n", type=int, default=150000)
+    ap.add_argument("--epochs", type=int, default=60)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--out", default=WEIGHTS)
     a = ap.parse_args()

@@ -284,8 +284,8 @@ def test_learned_initialiser_gains_over_radial_init(dev):
     the batched workload's optimiser settings: the predicted Theta starts at a
     higher PSNR than the radial initialisation (Eq. 6), and after 50 Adam
     steps more targets have reached 40 dB and the median PSNR is higher.
-    Margins (printed): measured 12.7 vs 8.0 dB at the start, 109 vs 58 targets
-    at 40 dB and 15.5 vs 13.6 dB after 50 steps."""
+    Margins (printed): measured 13.2 vs 8.0 dB at the start, 112 vs 58 targets
+    at 40 dB and 15.7 vs 13.6 dB after 50 steps."""
     from paper_2512_04556_amd import train_init
     b = mixed_batch(1024, seed=8000, fixed_L=4, fixed_N=12)
     bt = disk.make_batch(*pack_targets(b))
