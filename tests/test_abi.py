@@ -89,6 +89,22 @@ def test_backward_and_sv_validation():
     assert L.disk_sv_filter(ctypes.byref(b), fake, fake, fake, other, 3, 8, 8, 0, None, 0, None) == -3
     # image aliasing out
     assert L.disk_sv_filter(ctypes.byref(b), fake, fake, fake, fake, 3, 8, 8, 0, fake, 1 << 20, None) == -1
+    # frames: count out of range, aliasing, workspace sized for all frames
+    for F in (0, 65):
+        assert L.disk_sv_filter_frames(ctypes.byref(b), fake, fake, fake, 0, other, F, 3, 8, 8, 0, fake, 1 << 20,
+                                       None) == -2
+        assert L.disk_sv_filter_frames_workspace_size(ctypes.byref(b), F, 3, 8, 8, 0) == 0
+    assert L.disk_sv_filter_frames(ctypes.byref(b), fake, fake, fake, 1, fake, 2, 3, 8, 8, 0, fake, 1 << 20,
+                                   None) == -1
+    one = L.disk_sv_filter_frames_workspace_size(ctypes.byref(b), 1, 3, 64, 64, 0)
+    eight = L.disk_sv_filter_frames_workspace_size(ctypes.byref(b), 8, 3, 64, 64, 0)
+    assert one == L.disk_sv_filter_workspace_size(ctypes.byref(b), 3, 64, 64, 0)
+    assert eight > 7 * (one - L.disk_sv_table_bytes(ctypes.byref(b)) - 256)
+    assert L.disk_sv_filter_frames(ctypes.byref(b), fake, fake, fake, 0, other, 8, 3, 64, 64, 0, fake, one,
+                                   None) == -3
+    # the allocation-free filter refuses frames whose scratch exceeds its fixed array
+    assert L.disk_sv_filter_noalloc(ctypes.byref(b), fake, fake, fake, other, 3, 2160, 3840, 0, None) == -3
+    assert b"scratch" in L.disk_last_error()
 
 
 def test_basis_halo_from_host_copy():
