@@ -1102,6 +1102,14 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4, 4)))
         }
     };
 
+    // A tile's output is stored after the next tile has been staged, ahead of
+    // that tile's prefetch: the loop-top wait for the prefetched loads then
+    // never waits for stores (vmcnt retires in order, and exec-masked stores
+    // are not counted by the compiler's wait), and the stores have a whole
+    // tile of gathers to drain.
+    float pacc[PY][C];
+    TOut* pY = nullptr;
+    int px = 0, py0 = 0;
     issue(cur_f, cur_t);
     for (;;) {
         // the staged registers of `tile` -> LDS
@@ -1128,6 +1136,10 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4, 4)))
         TOut* const Yf = Y + static_cast<size_t>(fr) * C * plane;
         const int x = (tr % tiles_x) * kTW + lx, y0 = (tr / tiles_x) * TH + lyb;
         const int next = tile + nwg;
+        if constexpr (!corr || fused) {
+            if (pY) sv_store<C, TOut, PY>(pY, plane, W, H, px, py0, pacc);
+            asm volatile("" ::: "memory");   // the stores stay ahead of the prefetch
+        }
         if constexpr (fused) {
             float xq[PY][C];
 #pragma unroll
@@ -1138,9 +1150,10 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4, 4)))
                     asm volatile("" ::"v"(xq[j][c]));   // this tile's X ahead of the prefetch
                 }
             if (next < tend) issue(nxt_f, nxt_t);
-            float acc[PY][C];
-            fused_tile_taps<C, PY, ROWB>(s, acc, xq, base0, tabL, N, min(N, kCorrTaps));
-            sv_store<C, TOut, PY>(Yf, plane, W, H, x, y0, acc);
+            fused_tile_taps<C, PY, ROWB>(s, pacc, xq, base0, tabL, N, min(N, kCorrTaps));
+            pY = Yf;
+            px = x;
+            py0 = y0;
         } else if constexpr (corr) {
             float gc[PY][C];
 #pragma unroll
@@ -1154,15 +1167,19 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4, 4)))
             corr_tile_taps<C, PY, ROWB>(s, gc, base0, tabL, N);
         } else {
             if (next < tend) issue(nxt_f, nxt_t);
-            float acc[PY][C];
-            sv_tile_taps<C, DIMS, PY, ROWB, TL>(acc, ta, tb, kk, base0, rowB, table, tap0, N, T, tabL);
-            sv_store<C, TOut, PY>(Yf, plane, W, H, x, y0, acc);
+            sv_tile_taps<C, DIMS, PY, ROWB, TL>(pacc, ta, tb, kk, base0, rowB, table, tap0, N, T, tabL);
+            pY = Yf;
+            px = x;
+            py0 = y0;
         }
         if (next >= tend) break;
         tile = next;
         cur_f = nxt_f;
         cur_t = nxt_t;
         __syncthreads();  // every wave is done reading this tile before the next is written
+    }
+    if constexpr (!corr || fused) {
+        if (pY) sv_store<C, TOut, PY>(pY, plane, W, H, px, py0, pacc);
     }
     corr_finish();
 }
