@@ -260,16 +260,10 @@ disk_status disk_backward(const disk_complex* cx, const float* theta, const floa
         if (grad_theta && (l > 0 || grad_in) && !impulse && chain_pass_ok(C, DISK_CLAMP)) {
             // the input adjoint and the tap correlations in one staged pass
             float* Gn = l == 0 ? grad_in : (G == g0 ? g1 : g0);
-            int rows = 0;
             DISK_HIP(launch_chain_fused(C, boundary, G, static_cast<const float*>(X), Gn, theta, sp.tap0[l],
-                                        sp.taps[l], sp.T, H, W, partial, &rows, stream),
+                                        sp.taps[l], sp.T, H, W, partial, tapu + sp.tap0[l],
+                                        grad_theta + 3 * sp.tap0[l], stream),
                      "adjoint fused");
-            DISK_HIP(launch_adjoint_finish(partial, rows, theta + 3 * sp.tap0[l], sp.taps[l],
-                                           grad_theta + 3 * sp.tap0[l], stream),
-                     "adjoint finish");
-            if (boundary == DISK_CLAMP)
-                DISK_HIP(launch_adjoint_input_border(C, G, tapu + sp.tap0[l], sp.taps[l], H, W, Gn, stream),
-                         "adjoint input border");
             G = Gn;
             continue;
         }

@@ -324,6 +324,140 @@ hipError_t launch_adjoint_input_border(int C, const float* G, const TapU* taps, 
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// CLAMP border work of one fused backward layer, in one launch
+// ---------------------------------------------------------------------------
+struct BorderArgs {
+    const float* G;         // the layer's output gradient
+    const float* X;         // its input
+    const float* theta;     // its N taps
+    const TapU* taps;
+    int N, NS, H, W, hmax, parts, nA, nrows;
+    float* partial;         // nrows rows of N * 4 correlation partials; the last `parts` are written here
+    float* Gprev;           // the input adjoint, whose border pixels are written here
+};
+
+// Work-groups [0, nA): the CLAMP samples the fused pass leaves out, for tap i
+// < NS and corner ab: over the pixels p whose sample p + d + ab (d =
+// floor(-o_i)) leaves the image, G(p) X(clamp(p + d + ab)) summed over the
+// channels (zero for i >= NS, and for every tap when the layer's halo exceeds
+// hmax: the fused kernel's fallback then reads those samples itself).  The
+// pixels (the rows whose sample row leaves the image, whole, then the sample
+// columns that leave it in the other rows) are split into `parts`; (tap,
+// corner, part) writes entry 4 i + ab of border row `part` (rows nrows - parts
+// .. nrows - 1).  Work-groups [nA, ...): the input adjoint's border pixels, one
+// wave each (adjoint_input_border_kernel's arithmetic).  Fixed-order sums.
+// (dTheta then needs every row: adjoint_finish_kernel, launched after this.
+// Reducing it in the last correlation work-group instead needs a device-scope
+// release per work-group, an L2 write-back each on this GPU: far slower.)
+template <int C>
+__global__ __launch_bounds__(256) void adjoint_border_kernel(BorderArgs a) {
+    __shared__ float red[4];
+    const int t = threadIdx.x;
+    if (static_cast<int>(blockIdx.x) < a.nA) {
+        const int part = blockIdx.x % a.parts, ia = blockIdx.x / a.parts, i = ia >> 2, ab = ia & 3;
+        const int N = a.N, H = a.H, W = a.W;
+        float m = 0.0f;
+        for (int k = 0; k < N; ++k) {
+            float mk = fmaxf(fabsf(a.theta[3 * k]), fabsf(a.theta[3 * k + 1]));
+            if (!(mk <= 1.0e6f)) mk = 1.0e6f;   // non-finite or huge
+            m = fmaxf(m, mk);
+        }
+        const int halo = static_cast<int>(ceilf(m)) + 1;
+        float v = 0.0f;
+        if (i < a.NS && halo <= a.hmax) {
+            const int dx = static_cast<int>(floorf(-a.theta[3 * i])) + (ab & 1);
+            const int dy = static_cast<int>(floorf(-a.theta[3 * i + 1])) + (ab >> 1);
+            const int rlo = dy < 0 ? min(-dy, H) : 0, rhi = dy > 0 ? min(dy, H - rlo) : 0;
+            const int clo = dx < 0 ? min(-dx, W) : 0, chi = dx > 0 ? min(dx, W - clo) : 0;
+            const int ncol = clo + chi, nin = H - rlo - rhi;
+            const long n1 = static_cast<long>(rlo + rhi) * W, n = n1 + static_cast<long>(nin) * ncol;
+            const size_t plane = static_cast<size_t>(H) * W;
+            const long u0 = n * part / a.parts, u1 = n * (part + 1) / a.parts;
+            for (long u = u0 + t; u < u1; u += 256) {
+                int x, y;
+                if (u < n1) {
+                    const int r = static_cast<int>(u / W);
+                    x = static_cast<int>(u - static_cast<long>(r) * W);
+                    y = r < rlo ? r : H - rhi + (r - rlo);
+                } else {
+                    const long w = u - n1;
+                    const int r = static_cast<int>(w / ncol), k = static_cast<int>(w - static_cast<long>(r) * ncol);
+                    y = rlo + r;
+                    x = k < clo ? k : W - chi + (k - clo);
+                }
+                const int sx = min(max(x + dx, 0), W - 1), sy = min(max(y + dy, 0), H - 1);
+                const size_t pg = static_cast<size_t>(y) * W + x, px = static_cast<size_t>(sy) * W + sx;
+#pragma unroll
+                for (int c = 0; c < C; ++c) v = fmaf(a.G[c * plane + pg], a.X[c * plane + px], v);
+            }
+        }
+        // fixed-order block sum: wave butterflies, then the four waves in order
+        v = wave_sum(v);
+        if ((t & 63) == 0) red[t >> 6] = v;
+        __syncthreads();
+        if (t == 0) {
+            float* row = a.partial + static_cast<size_t>(a.nrows - a.parts + part) * N * 4;
+            row[4 * i + ab] = (red[0] + red[1]) + (red[2] + red[3]);
+        }
+        return;
+    }
+    const long i = (static_cast<long>(blockIdx.x) - a.nA) * 4 + (t >> 6);   // wave-uniform
+    const int lane = t & 63, H = a.H, W = a.W;
+    if (i >= border_count(H, W)) return;
+    int x, y;
+    if (H <= 2 || W <= 2) {
+        y = static_cast<int>(i / W);
+        x = static_cast<int>(i - static_cast<long>(y) * W);
+    } else if (i < 2L * W) {
+        y = i < W ? 0 : H - 1;
+        x = static_cast<int>(i < W ? i : i - W);
+    } else {
+        const int j = static_cast<int>(i - 2L * W);
+        x = j < H - 2 ? 0 : W - 1;
+        y = 1 + (j < H - 2 ? j : j - (H - 2));
+    }
+    const size_t plane = static_cast<size_t>(H) * W;
+    float acc[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) acc[c] = 0.0f;
+    for (int pr = lane; pr < 4 * a.N; pr += 64) {
+        const TapU tp = a.taps[pr >> 2];
+        const int k = pr & 3;
+        const float cw = k == 0 ? tp.c00 : k == 1 ? tp.c01 : k == 2 ? tp.c10 : tp.c11;
+        int xl, xh, yl, yh;
+        preimage<DISK_CLAMP>(x, tp.ix + (k & 1), W, xl, xh);
+        preimage<DISK_CLAMP>(y, tp.iy + (k >> 1), H, yl, yh);
+        for (int py = yl; py <= yh; ++py)
+            for (int px = xl; px <= xh; ++px) {
+                const size_t pi = static_cast<size_t>(py) * W + px;
+#pragma unroll
+                for (int c = 0; c < C; ++c) acc[c] = fmaf(cw, a.G[c * plane + pi], acc[c]);
+            }
+    }
+#pragma unroll
+    for (int c = 0; c < C; ++c) acc[c] = wave_sum(acc[c]);
+    if (lane == 0)
+#pragma unroll
+        for (int c = 0; c < C; ++c) a.Gprev[c * plane + static_cast<size_t>(y) * W + x] = acc[c];
+}
+
+hipError_t launch_adjoint_border(int C, const float* G, const float* X, const float* theta_layer, const TapU* taps,
+                                 int N, int NS, int H, int W, int hmax, float* partial, int nrows, int parts,
+                                 float* Gprev, hipStream_t s) {
+    if (N < 1 || N > 32 || parts < 1 || nrows < parts) return hipErrorInvalidValue;
+    BorderArgs a{G, X, theta_layer, taps, N, NS, H, W, hmax, parts, 4 * N * parts, nrows, partial, Gprev};
+    const long nb = (H <= 2 || W <= 2) ? static_cast<long>(H) * W : 2L * W + 2L * (H - 2);
+    const dim3 grid(static_cast<unsigned>(a.nA + (nb + 3) / 4)), block(256);
+    if (C == 3)
+        hipLaunchKernelGGL(adjoint_border_kernel<3>, grid, block, 0, s, a);
+    else if (C == 4)
+        hipLaunchKernelGGL(adjoint_border_kernel<4>, grid, block, 0, s, a);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
 template <int C>
 static hipError_t input_bound(int boundary, const float* G, const TapU* taps, int N, int H, int W, float* Gprev,
                               hipStream_t s) {

@@ -1536,70 +1536,9 @@ hipError_t launch_adjoint_corr(int C, int boundary, const float* X, const float*
     return hipErrorInvalidValue;
 }
 
-// The CLAMP samples the fused pass leaves out: for tap i < NS and corner ab,
-// sum over the pixels p whose sample p + d + ab (d = floor(-o_i)) leaves the
-// image of G(p) X(clamp(p + d + ab)), over the channels.  The pixels (the
-// rows whose sample row leaves the image, whole, then the sample columns that
-// leave it in the other rows) are split into gridDim.y parts; work-group
-// (tap, corner) x part writes rows[part][4 i + ab] (rows of N * 4 floats):
-// zero for i >= NS, and for every tap when the layer's halo (computed as the
-// fused kernel does) exceeds hmax, since that kernel's fallback then reads
-// those samples itself.  Fixed-order sums.
-template <int C>
-__global__ __launch_bounds__(256) void corr_border_kernel(const float* __restrict__ G, const float* __restrict__ X,
-                                                          const float* __restrict__ theta, int N, int NS, int H,
-                                                          int W, int hmax, float* __restrict__ rows) {
-    __shared__ float red[256];
-    const int i = blockIdx.x >> 2, ab = blockIdx.x & 3, t = threadIdx.x;
-    const int part = blockIdx.y, nparts = gridDim.y;
-    float* row = rows + static_cast<size_t>(part) * N * 4;
-    float m = 0.0f;
-    for (int k = 0; k < N; ++k) {
-        float mk = fmaxf(fabsf(theta[3 * k]), fabsf(theta[3 * k + 1]));
-        if (!(mk <= 1.0e6f)) mk = 1.0e6f;   // non-finite or huge
-        m = fmaxf(m, mk);
-    }
-    const int halo = static_cast<int>(ceilf(m)) + 1;
-    float v = 0.0f;
-    if (i < NS && halo <= hmax) {
-        const int dx = static_cast<int>(floorf(-theta[3 * i])) + (ab & 1);
-        const int dy = static_cast<int>(floorf(-theta[3 * i + 1])) + (ab >> 1);
-        const int rlo = dy < 0 ? min(-dy, H) : 0, rhi = dy > 0 ? min(dy, H - rlo) : 0;
-        const int clo = dx < 0 ? min(-dx, W) : 0, chi = dx > 0 ? min(dx, W - clo) : 0;
-        const int ncol = clo + chi, nin = H - rlo - rhi;
-        const long n1 = static_cast<long>(rlo + rhi) * W, n = n1 + static_cast<long>(nin) * ncol;
-        const size_t plane = static_cast<size_t>(H) * W;
-        const long u0 = n * part / nparts, u1 = n * (part + 1) / nparts;
-        for (long u = u0 + t; u < u1; u += 256) {
-            int x, y;
-            if (u < n1) {
-                const int r = static_cast<int>(u / W);
-                x = static_cast<int>(u - static_cast<long>(r) * W);
-                y = r < rlo ? r : H - rhi + (r - rlo);
-            } else {
-                const long w = u - n1;
-                const int r = static_cast<int>(w / ncol), k = static_cast<int>(w - static_cast<long>(r) * ncol);
-                y = rlo + r;
-                x = k < clo ? k : W - chi + (k - clo);
-            }
-            const int sx = min(max(x + dx, 0), W - 1), sy = min(max(y + dy, 0), H - 1);
-            const size_t pg = static_cast<size_t>(y) * W + x, px = static_cast<size_t>(sy) * W + sx;
-#pragma unroll
-            for (int c = 0; c < C; ++c) v = fmaf(G[c * plane + pg], X[c * plane + px], v);
-        }
-    }
-    red[t] = v;
-    __syncthreads();
-    for (int h = 128; h >= 1; h >>= 1) {
-        if (t < h) red[t] += red[t + h];
-        __syncthreads();
-    }
-    if (t == 0) row[4 * i + ab] = red[0];
-}
-
 template <int C>
 static hipError_t fused_c(int zero, const float* G, const float* X, float* Gn, const float* theta, int tap0, int N,
-                          int T, int H, int W, float* partial, int* nrows, hipStream_t s) {
+                          int T, int H, int W, float* partial, const TapU* taps, float* dtheta, hipStream_t s) {
     int nb = 0;
     hipError_t e = zero ? launch_pipe<C, 1, float, float, 16, kPipeHalo, kPipeRowB, true, 6>(
                               G, Gn, X, nullptr, tap0, N, T, 1, 1, H, W, 0, nullptr, theta, s, N, 0, &nb, partial)
@@ -1611,22 +1550,25 @@ static hipError_t fused_c(int zero, const float* G, const float* X, float* Gn, c
         e = corr_c<C>(zero, X, G, theta, tap0, N, T, H, W, partial, &nb2, s, kCorrTaps, nb);
         if (e != hipSuccess) return e;
     }
-    *nrows = nb;
+    int nrows = nb;
     if (!zero) {
-        // up to 16 rows after the grid's (the partial buffer holds at least
-        // adjoint_tap_blocks(H, W) + 1 rows of the layer's widest N)
+        // CLAMP: the border samples into up to 16 rows after the grid's (the
+        // partial buffer holds at least adjoint_tap_blocks(H, W) + 1 rows of
+        // the layer's widest N) and the border pixels of Gn, in one launch
         const int parts = std::max(1, std::min(16, adjoint_tap_blocks(H, W) + 1 - nb));
-        hipLaunchKernelGGL(corr_border_kernel<C>, dim3(4 * N, parts), dim3(256), 0, s, G, X, theta + 3 * tap0, N,
-                           std::min(N, kCorrTaps), H, W, kPipeHalo, partial + static_cast<size_t>(nb) * N * 4);
-        *nrows = nb + parts;
+        nrows = nb + parts;
+        e = launch_adjoint_border(C, G, X, theta + 3 * tap0, taps, N, std::min(N, kCorrTaps), H, W, kPipeHalo,
+                                  partial, nrows, parts, Gn, s);
+        if (e != hipSuccess) return e;
     }
-    return hipGetLastError();
+    return launch_adjoint_finish(partial, nrows, theta + 3 * tap0, N, dtheta, s);
 }
 hipError_t launch_chain_fused(int C, int boundary, const float* G, const float* X, float* Gn, const float* theta,
-                              int tap0, int N, int T, int H, int W, float* partial, int* nrows, hipStream_t s) {
+                              int tap0, int N, int T, int H, int W, float* partial, const TapU* taps,
+                              float* dtheta, hipStream_t s) {
     const int zero = boundary == DISK_ZERO;
-    if (C == 3) return fused_c<3>(zero, G, X, Gn, theta, tap0, N, T, H, W, partial, nrows, s);
-    if (C == 4) return fused_c<4>(zero, G, X, Gn, theta, tap0, N, T, H, W, partial, nrows, s);
+    if (C == 3) return fused_c<3>(zero, G, X, Gn, theta, tap0, N, T, H, W, partial, taps, dtheta, s);
+    if (C == 4) return fused_c<4>(zero, G, X, Gn, theta, tap0, N, T, H, W, partial, taps, dtheta, s);
     return hipErrorInvalidValue;
 }
 

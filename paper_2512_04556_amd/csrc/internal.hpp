@@ -99,14 +99,22 @@ hipError_t launch_adjoint_input_border(int C, const float* G, const TapU* taps, 
 // gradient (both FP32).
 hipError_t launch_adjoint_corr(int C, int boundary, const float* X, const float* G, const float* theta, int tap0,
                                int N, int T, int H, int W, float* partial, int* nblk, hipStream_t s);
-// The transpose of a chain layer (C = 3, 4; ZERO or CLAMP forward) fused with
-// its tap correlations: G' into Gn and the correlation partials into
-// partial[*nrows][N][4] (the in-image part of the first taps from the fused
-// pass, the other taps from correlation passes on the same grid, and for
-// CLAMP one last row with the samples that leave the image).  CLAMP border
-// pixels of Gn still need launch_adjoint_input_border.
+// The backward of a chain layer (C = 3, 4; ZERO or CLAMP forward): its
+// transpose G' into Gn fused with its tap correlations (the in-image part of
+// the first taps from the fused pass, the other taps from correlation passes
+// on the same grid, as rows of partial[][N][4]), then dTheta into dtheta (the
+// layer's 3 N values).  For CLAMP one launch in between adds the samples that
+// leave the image and recomputes the border pixels of Gn exactly
+// (launch_adjoint_border).  taps: the layer's prepared taps.
 hipError_t launch_chain_fused(int C, int boundary, const float* G, const float* X, float* Gn, const float* theta,
-                              int tap0, int N, int T, int H, int W, float* partial, int* nrows, hipStream_t s);
+                              int tap0, int N, int T, int H, int W, float* partial, const TapU* taps, float* dtheta,
+                              hipStream_t s);
+// The CLAMP border work of one fused backward layer in one launch: the
+// correlation samples that leave the image into rows nrows - parts .. nrows -
+// 1 of partial, and the input adjoint on the border pixels of Gprev.
+hipError_t launch_adjoint_border(int C, const float* G, const float* X, const float* theta_layer, const TapU* taps,
+                                 int N, int NS, int H, int W, int hmax, float* partial, int nrows, int parts,
+                                 float* Gprev, hipStream_t s);
 hipError_t launch_chain_pass(int C, int src_bf16, const void* src, int dst_bf16, void* dst, const float* theta,
                              int tap0, int N, int T, int H, int W, hipStream_t s);
 
