@@ -205,6 +205,57 @@ def test_bench_batch_one_step_all_targets(dev):
     print(f"4096 targets, one step: worst |dTheta| on well-determined components {worst:.2e}")
 
 
+def test_uneven_batch_default_shape_vs_oracle(dev):
+    """The uneven batching workload (4096 targets: odd sides 15..127, the five
+    shape families, 2..6 layers of 6..16 taps, seed 13, radial init) with the
+    built-in launch shape (1024-thread work-groups for this batch) and the
+    batched settings' half-width offset units.  One Adam step: every target
+    against the oracle, as in the 4 x 12 test.  Twenty steps: the largest and
+    the smallest target of each layer count against the oracle's trajectory
+    at the trajectory tests' bars (PSNR 0.01 dB, offsets 1e-3 px, weights
+    2e-6; measured at most 1e-4 dB, 2.2e-4 px at 96 taps on side 127, 1.3e-7)."""
+    from tests import oracle_pool
+    batch = mixed_batch(4096, seed=13)
+    th0 = _theta0(batch)
+    desc, _, _ = pack_targets(batch)
+    rows = [(int(desc[b, 3]), int(np.sum(batch.taps[b]))) for b in range(batch.B)]
+    say("opt uneven batch 4096 x 1 step")
+    th, ps, st, stat = _run(batch, th0, max_steps=1, lr0=1e-2, lr1=1e-3, offset_units=disk.OFFSETS_HALF_WIDTH)
+    assert np.all(st == 1) and np.all(stat == 0)
+    sides = np.array([k.shape[0] for k in batch.kernels])
+    lrs = [1e-2 * Ad.rate_units(int(s), 1) for s in sides]     # per coordinate: half-width units for offsets
+    res = oracle_pool.one_step_all([k for k in batch.kernels], [th0[o:o + T] for o, T in rows], batch.taps, lrs)
+    worst = 0.0
+    for b, ((o, T), (want, g)) in enumerate(zip(rows, res)):
+        got = th[o:o + T]
+        lr = np.broadcast_to(lrs[b], got.shape)
+        big = np.abs(g) > 1e-3 * np.abs(g).max()
+        e = float((np.abs(got - want) / lr)[big].max())
+        worst = max(worst, e)
+        assert e <= 1e-4, (b, e)
+        assert np.all(np.abs(got - want) <= lr + 1e-6), b
+    print(f"uneven 4096 targets, one step: worst |dTheta| / lr on well-determined components {worst:.2e}")
+    say("opt uneven batch 4096 x 20 steps")
+    th, ps, st, stat = _run(batch, th0, max_steps=20, lr0=1e-2, lr1=1e-3, offset_units=disk.OFFSETS_HALF_WIDTH)
+    assert np.all(st == 20) and np.all(stat == 0)
+    Ls = np.asarray(batch.L)
+    picks = []
+    for L in sorted(set(Ls.tolist())):
+        idx = np.flatnonzero(Ls == L)
+        cost = sides[idx] ** 2 * np.array([rows[i][1] for i in idx])
+        picks += [int(idx[np.argmax(cost)]), int(idx[np.argmin(cost)])]
+    want = oracle_pool.trajectories([batch.kernels[b] for b in picks], [th0[rows[b][0]:rows[b][0] + rows[b][1]] for b in picks],
+                                    [batch.taps[b] for b in picks], max_steps=20, lr0=1e-2, lr1=1e-3, offset_units=1)
+    for b, (th_o, ps_o, st_o) in zip(picks, want):
+        o, T = rows[b]
+        got = th[o:o + T]
+        eo = float(np.abs(got[:, :2] - th_o[:, :2]).max())
+        ew = float(np.abs(got[:, 2] - th_o[:, 2]).max())
+        print(f"target {b} side {sides[b]} L {Ls[b]} T {T}: GPU {ps[b]:.4f} dB oracle {ps_o:.4f} dB, "
+              f"offsets {eo:.2e} px, weights {ew:.2e}")
+        assert abs(ps[b] - ps_o) <= 0.01 and eo <= 1e-3 and ew <= 2e-6, (b, ps[b], ps_o, eo, ew)
+
+
 def _jittered(batch, seed, sd=0.3):
     th0 = _theta0(batch)
     j = np.random.default_rng(seed).normal(0.0, sd, th0.shape).astype(np.float32)
