@@ -261,19 +261,18 @@ __global__ __launch_bounds__(256) void adjoint_input_kernel(const float* __restr
 }
 
 // The CLAMP border pixels only (rows 0 and H-1, columns 0 and W-1): run after
-// the interior was produced by the zero-padded transposed gather.  One wave per
-// border pixel: lane l takes the (tap, corner) pairs l, l + 64, ... and sums
-// their preimage runs; a fixed butterfly adds the lanes.
+// the interior was produced by the zero-padded transposed gather, one wave
+// per border pixel.
 __device__ __forceinline__ long border_count(int H, int W) {
     return (H <= 2 || W <= 2) ? static_cast<long>(H) * W : 2L * W + 2L * (H - 2);
 }
+// Border pixel i (wave-uniform) of the input adjoint: lane l takes the (tap,
+// corner) pairs l, l + 64, ... and sums their preimage runs; a fixed
+// butterfly adds the lanes.
 template <int C>
-__global__ __launch_bounds__(256) void adjoint_input_border_kernel(const float* __restrict__ G,
-                                                                   const TapU* __restrict__ taps, int N, int H,
-                                                                   int W, float* __restrict__ Gprev) {
-    const long i = (static_cast<long>(blockIdx.x) * 256 + threadIdx.x) >> 6;   // wave-uniform
+__device__ __forceinline__ void input_border_pixel(const float* __restrict__ G, const TapU* __restrict__ taps, int N,
+                                                   int H, int W, long i, float* __restrict__ Gprev) {
     const int lane = threadIdx.x & 63;
-    if (i >= border_count(H, W)) return;
     int x, y;
     if (H <= 2 || W <= 2) {
         y = static_cast<int>(i / W);
@@ -311,6 +310,14 @@ __global__ __launch_bounds__(256) void adjoint_input_border_kernel(const float* 
         for (int c = 0; c < C; ++c) Gprev[c * plane + static_cast<size_t>(y) * W + x] = acc[c];
 }
 
+template <int C>
+__global__ __launch_bounds__(256) void adjoint_input_border_kernel(const float* __restrict__ G,
+                                                                   const TapU* __restrict__ taps, int N, int H,
+                                                                   int W, float* __restrict__ Gprev) {
+    const long i = (static_cast<long>(blockIdx.x) * 256 + threadIdx.x) >> 6;   // one wave per border pixel
+    if (i < border_count(H, W)) input_border_pixel<C>(G, taps, N, H, W, i, Gprev);
+}
+
 hipError_t launch_adjoint_input_border(int C, const float* G, const TapU* taps, int N, int H, int W, float* Gprev,
                                        hipStream_t s) {
     const long nb = (H <= 2 || W <= 2) ? static_cast<long>(H) * W : 2L * W + 2L * (H - 2);
@@ -346,7 +353,7 @@ struct BorderArgs {
 // columns that leave it in the other rows) are split into `parts`; (tap,
 // corner, part) writes entry 4 i + ab of border row `part` (rows nrows - parts
 // .. nrows - 1).  Work-groups [nA, ...): the input adjoint's border pixels, one
-// wave each (adjoint_input_border_kernel's arithmetic).  Fixed-order sums.
+// wave each (input_border_pixel).  Fixed-order sums.
 // (dTheta then needs every row: adjoint_finish_kernel, launched after this.
 // Reducing it in the last correlation work-group instead needs a device-scope
 // release per work-group, an L2 write-back each on this GPU: far slower.)
@@ -403,43 +410,7 @@ __global__ __launch_bounds__(256) void adjoint_border_kernel(BorderArgs a) {
         return;
     }
     const long i = (static_cast<long>(blockIdx.x) - a.nA) * 4 + (t >> 6);   // wave-uniform
-    const int lane = t & 63, H = a.H, W = a.W;
-    if (i >= border_count(H, W)) return;
-    int x, y;
-    if (H <= 2 || W <= 2) {
-        y = static_cast<int>(i / W);
-        x = static_cast<int>(i - static_cast<long>(y) * W);
-    } else if (i < 2L * W) {
-        y = i < W ? 0 : H - 1;
-        x = static_cast<int>(i < W ? i : i - W);
-    } else {
-        const int j = static_cast<int>(i - 2L * W);
-        x = j < H - 2 ? 0 : W - 1;
-        y = 1 + (j < H - 2 ? j : j - (H - 2));
-    }
-    const size_t plane = static_cast<size_t>(H) * W;
-    float acc[C];
-#pragma unroll
-    for (int c = 0; c < C; ++c) acc[c] = 0.0f;
-    for (int pr = lane; pr < 4 * a.N; pr += 64) {
-        const TapU tp = a.taps[pr >> 2];
-        const int k = pr & 3;
-        const float cw = k == 0 ? tp.c00 : k == 1 ? tp.c01 : k == 2 ? tp.c10 : tp.c11;
-        int xl, xh, yl, yh;
-        preimage<DISK_CLAMP>(x, tp.ix + (k & 1), W, xl, xh);
-        preimage<DISK_CLAMP>(y, tp.iy + (k >> 1), H, yl, yh);
-        for (int py = yl; py <= yh; ++py)
-            for (int px = xl; px <= xh; ++px) {
-                const size_t pi = static_cast<size_t>(py) * W + px;
-#pragma unroll
-                for (int c = 0; c < C; ++c) acc[c] = fmaf(cw, a.G[c * plane + pi], acc[c]);
-            }
-    }
-#pragma unroll
-    for (int c = 0; c < C; ++c) acc[c] = wave_sum(acc[c]);
-    if (lane == 0)
-#pragma unroll
-        for (int c = 0; c < C; ++c) a.Gprev[c * plane + static_cast<size_t>(y) * W + x] = acc[c];
+    if (i < border_count(a.H, a.W)) input_border_pixel<C>(a.G, a.taps, a.N, a.H, a.W, i, a.Gprev);
 }
 
 hipError_t launch_adjoint_border(int C, const float* G, const float* X, const float* theta_layer, const TapU* taps,
