@@ -150,7 +150,7 @@ hipError_t launch_dense_sv(int kind, float r0, float r1, float a0, float a1, int
 
 // ---- learned initialiser (net.hip) ----
 struct NetWs {   // byte offsets into the caller's workspace
-    size_t wp, act, yhat, g32[2], gq[2], part, cpart, grad, total;
+    size_t wp, act, yhat, g32[2], gq[2], part, cpart, cslab, grad, total;
 };
 long net_param_count();
 NetWs net_ws_layout(int B, bool train);

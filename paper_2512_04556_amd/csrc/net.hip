@@ -803,7 +803,7 @@ NetWs net_ws_layout(int B, bool train) {
     }
     // gradient buffers: BF16 copies of the largest layer output (layer 1: 32 x
     // 32 x 32 per sample); FP32 only for the output layer's (the loss gradient)
-    size_t gmax = 0, part = 0, cpart = ((static_cast<size_t>(B) + kColRows - 1) / kColRows) * kOut;
+    size_t gmax = 0, part = 0, cpart = ((static_cast<size_t>(B) + kColRows - 1) / kColRows) * kOut, cslab = 0;
     for (int i = 0; i < 8; ++i) {
         const Layer& L = T.l[i];
         const size_t M = static_cast<size_t>(B) * L.hout * L.hout;
@@ -811,7 +811,10 @@ NetWs net_ws_layout(int B, bool train) {
         int S, kc;
         net_wgrad_splits(L.cout, L.Kp, static_cast<int>(M), &S, &kc);
         part = std::max(part, static_cast<size_t>(S) * L.cout * L.Kp);
-        if (i < 7) cpart = std::max(cpart, bias_part_rows(B, i) * L.cout);
+        if (i < 7) {
+            cpart = std::max(cpart, bias_part_rows(B, i) * L.cout);
+            cslab = std::max(cslab, (bias_part_rows(B, i) + kColRows - 1) / kColRows * L.cout);
+        }
     }
     w.g32[0] = take(static_cast<size_t>(B) * kOut * 4);
     w.g32[1] = w.g32[0];
@@ -819,6 +822,7 @@ NetWs net_ws_layout(int B, bool train) {
     w.gq[1] = take(gmax * 2);
     w.part = take(part * 4);
     w.cpart = take(cpart * 4);
+    w.cslab = take(cslab * 4);
     w.grad = take(T.params * 4);
     w.total = take(0);
     return w;
@@ -914,8 +918,22 @@ hipError_t net_backward(const float* params, const uint16_t* x0, const float* re
             hipLaunchKernelGGL(colsum_final_kernel, dim3(L.cout), dim3(256), 0, s, cpart, nblk, L.cout,
                                grad + L.b_off);
         } else {
-            hipLaunchKernelGGL(colsum_final_kernel, dim3(L.cout), dim3(256), 0, s, cpart,
-                               static_cast<int>(bias_part_rows(B, i)), L.cout, grad + L.b_off);
+            // the tile partials, [rows][cout]; many rows: 256-row slabs read as
+            // whole rows, then the slabs in order (reading 64K rows a column at
+            // a time took 23 us per layer at batch 4096; for a few thousand
+            // rows the extra launch costs more than it saves)
+            const int rows = static_cast<int>(bias_part_rows(B, i));
+            if (rows > 8192) {
+                if ((L.cout & 3) != 0 || L.cout > 1024) return hipErrorInvalidValue;
+                const int nslab = (rows + kColRows - 1) / kColRows;
+                float* cslab = reinterpret_cast<float*>(ws + w.cslab);
+                hipLaunchKernelGGL(colsum_part_kernel, dim3(nslab), dim3(256), 0, s, cpart, rows, L.cout, cslab);
+                hipLaunchKernelGGL(colsum_final_kernel, dim3(L.cout), dim3(256), 0, s, cslab, nslab, L.cout,
+                                   grad + L.b_off);
+            } else {
+                hipLaunchKernelGGL(colsum_final_kernel, dim3(L.cout), dim3(256), 0, s, cpart, rows, L.cout,
+                                   grad + L.b_off);
+            }
         }
         // weight gradient: dW(co, j) = sum_m g(m, co) x_col(m, j), split over m
         int S, kc;
