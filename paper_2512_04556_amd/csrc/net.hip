@@ -667,20 +667,20 @@ __global__ __launch_bounds__(256) void wgrad_reduce_kernel(Layer L, const float*
                                                            float* __restrict__ grad) {
     const long n = static_cast<long>(L.cout) * L.K;
     const size_t slab = static_cast<size_t>(L.cout) * L.Kp;
+    // i walks the packed columns (co, k), so the S slab reads of consecutive
+    // threads are consecutive floats; each sum goes to its blob position
+    // (for a convolution, packed column k = tap * cin + ci is blob entry
+    // (co, ci, tap))
     for (long i = blockIdx.x * 256L + threadIdx.x; i < n; i += static_cast<long>(gridDim.x) * 256) {
-        int co, k;
-        if (L.conv) {   // i = (co, ci, tap) in the blob; packed column k = tap * cin + ci
-            co = static_cast<int>(i / L.K);
-            const int rem = static_cast<int>(i - static_cast<long>(co) * L.K);
-            const int ci = rem / 9, tap = rem - 9 * ci;
-            k = tap * L.cin + ci;
-        } else {
-            co = static_cast<int>(i / L.K);
-            k = static_cast<int>(i - static_cast<long>(co) * L.K);
-        }
+        const int co = static_cast<int>(i / L.K), k = static_cast<int>(i - static_cast<long>(co) * L.K);
         float s = 0.0f;
         for (int z = 0; z < S; ++z) s += part[z * slab + static_cast<size_t>(co) * L.Kp + k];
-        grad[L.w_off + i] = s;
+        long dst = i;
+        if (L.conv) {
+            const int tap = k / L.cin, ci = k - tap * L.cin;
+            dst = static_cast<long>(co) * L.K + 9 * ci + tap;
+        }
+        grad[L.w_off + dst] = s;
     }
 }
 
