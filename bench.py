@@ -52,6 +52,8 @@ def parse():
     ap.add_argument("--no-extras", action="store_true", help="skip the gradient-chain and network measurements")
     ap.add_argument("--extras-only", action="store_true",
                     help="only the gradient-chain and network measurements (for profiling them)")
+    ap.add_argument("--sv2d-only", action="store_true",
+                    help="only the 2-D 3840x2160 BF16 filter measurement (for profiling its kernels)")
     ap.add_argument("--time-to-40db-only", action="store_true",
                     help="only run the batched-optimisation comparison (for profiling it)")
     ap.add_argument("--copy-reference", type=int, default=0, metavar="MIB",
@@ -648,6 +650,9 @@ def main():
         print(json.dumps({"time_to_40db": time_to_40db(torch, disk),
                           "time_to_40db_gaussians": time_to_40db(torch, disk, kinds=("gaussian",)),
                           "batched_uneven_4096": batched_uneven(torch, disk)}), flush=True)
+        return
+    if a.sv2d_only:
+        print(json.dumps({"sv2d_4k_bf16": sv2d_4k(torch, disk)}), flush=True)
         return
     if a.extras_only:
         print(json.dumps({"gradient_chain_1080p": gradient_chain(torch, disk),

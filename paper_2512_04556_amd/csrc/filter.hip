@@ -619,11 +619,17 @@ constexpr int kPipeHalo = 24;
 #endif
 constexpr int kPipeHalo8 = DISK_SV_HALO8;   // 8-wave variant
 constexpr int kPipePY = 2;
+// Halos 25..30 (2-D bases with a wide layer): 8-wave 64 x 16 tiles, one per
+// CU, two waves per SIMD (the 74-76 staged rows take 60 staging registers),
+// row stride 124 pixels (no bank padding: it would not fit the LDS).
+constexpr int kPipeHaloWide = 30;
+constexpr int kPipeRowBWide = (kTW + 2 * kPipeHaloWide) * 16;
 template <int NW, int HMAX>
 struct PipeShape {
     static constexpr int TH = 4 * kPipePY * (NW / 4);                     // tile rows
     static constexpr int RPW = (TH + 2 * HMAX + NW - 1) / NW;              // staged rows per wave
     static constexpr int NQ = (kTW + 2 * HMAX + 63) / 64;                  // 64-column chunks
+    static constexpr int WPE = HMAX > kPipeHalo ? 2 : 4;                   // waves per SIMD
 };
 
 // Uniform chain layer whose offsets exceed the staged halo (or are not
@@ -858,7 +864,9 @@ __device__ __forceinline__ void fused_tile_taps(float (&s)[kCorrTaps][4], float 
 // MODE 0: a spatially varying pass.  MODE 1 (TL, raw = Theta, G0 = 1, P ==
 // nullptr): one layer of a uniform chain.  MODE 2: that layer's transpose.
 template <int C, int DIMS, typename TIn, typename TOut, int NW, int HMAX, int ROWB, bool TL, int MODE = 0>
-__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4, 4))) void sv_pass_pipe_kernel(
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(PipeShape<NW, HMAX>::WPE,
+                                                                           PipeShape<NW, HMAX>::WPE))) void
+sv_pass_pipe_kernel(
     const TIn* __restrict__ X, TOut* __restrict__ Y, const float* __restrict__ P,
     const float* __restrict__ table, int tap0, int N, int T, int G0, int G1, int H, int W, int halo,
     int tiles_x, int per, int ntiles, const int* __restrict__ flag, int rowW, const float* __restrict__ raw,
@@ -1429,6 +1437,7 @@ static hipError_t launch_typed(const void* src, void* dst, const float* pmap, co
     if constexpr (C >= 3) {
         SV_TRY_PIPE(8, kPipeHalo8, kPipeRowB, false, 80 * 1024)
         SV_TRY_PIPE(16, kPipeHalo, kPipeRowB, false, 160 * 1024)
+        SV_TRY_PIPE(8, kPipeHaloWide, kPipeRowBWide, false, 160 * 1024)
     } else {
         SV_TRY_PIPE(8, kPipeHalo8, 0, false, 80 * 1024)
         SV_TRY_PIPE(16, kPipeHalo, 0, false, 160 * 1024)

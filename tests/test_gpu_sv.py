@@ -171,7 +171,7 @@ def test_sv_bench_configuration_full_frame(dev):
 
 def test_sv_2d_4k_bf16_sampled(dev):
     """The 2-D workload at full size: 3840x2160x3 BF16 I/O, 8 x 8 basis of
-    4 x 12 taps with halos above the pipelined kernels' range, 2-D map.  Two
+    4 x 12 taps with halos 27..30 (the wide-halo staged kernel), 2-D map.  Two
     seeded interior 32 x 32 output crops, a top-border, a left-border and the
     bottom-right corner crop against the oracle run on the crop plus a margin
     of the summed halos (the margin's own clamping cannot reach the crop)."""
@@ -217,6 +217,33 @@ def test_sv_large_halo_global_path(dev, C, dims):
     assert max(b.halo) > 33
     want = SV.sv_chain(img.astype(np.float64), P.astype(np.float64), basis.astype(np.float64), grid, taps)
     assert rel_err(to_np(out), want) <= TOL_F32
+
+
+@pytest.mark.parametrize("C,dims,io,seed,r0,dr,want_halo", [
+    (3, 1, torch.float32, 700, 24.0, 0.5, [25, 25, 27]),
+    (4, 1, torch.float32, 720, 26.5, 0.5, [27, 30, 29]),
+    (3, 2, torch.float32, 720, 26.5, 0.3, [28, 29, 30]),
+    (3, 2, torch.bfloat16, 700, 26.0, 0.3, [28, 26, 28]),
+])
+def test_sv_wide_halo_staged(dev, C, dims, io, seed, r0, dr, want_halo):
+    """Halos 25..30 (C >= 3): the 8-wave kernel with 64 x 16 tiles and 124-pixel
+    staged rows, over several tiles with ragged right and bottom tails, the
+    CLAMP border on every side, against the oracle on the whole image."""
+    taps = [6, 6, 5]
+    G = 6 if dims == 1 else 9
+    grid = [G] if dims == 1 else [3, 3]
+    basis = _basis(G, taps, seed=seed, r0=r0, dr=dr)
+    H, W = 70, 150
+    img = noise_image(H, W, C, seed=seed, n_rects=10)
+    P = param_map(H, W, seed=seed + 1, period=48.0, dims=dims)
+    say("sv wide halo", C, dims, io, want_halo)
+    out, b = _run(basis, taps, grid, img, P, io=io)
+    assert list(b.halo) == want_halo
+    x = img if io == torch.float32 else bf16_round(img)
+    want = SV.sv_chain(x.astype(np.float64), P.astype(np.float64), basis.astype(np.float64), grid, taps)
+    e = rel_err(to_np(out), want)
+    print(f"sv wide halo C={C} dims={dims} {io} halo={b.halo}: {e:.2e}")
+    assert e <= (TOL_F32 if io == torch.float32 else TOL_BF16)
 
 
 def test_sv_halo_just_beyond_padded_tile(dev):
