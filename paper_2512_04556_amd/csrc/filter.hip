@@ -624,12 +624,16 @@ constexpr int kPipePY = 2;
 // row stride 124 pixels (no bank padding: it would not fit the LDS).
 constexpr int kPipeHaloWide = 30;
 constexpr int kPipeRowBWide = (kTW + 2 * kPipeHaloWide) * 16;
+// C <= 2 (and the plane groups of a C >= 3 image whose halo is beyond the
+// staged C >= 3 kernels): 16-wave 64 x 32 tiles up to halo 42 (at C = 2 the
+// 116 staged rows of 8-byte pixels take 160 KB of LDS).
+constexpr int kPipeHaloBig = 42;
 template <int NW, int HMAX>
 struct PipeShape {
     static constexpr int TH = 4 * kPipePY * (NW / 4);                     // tile rows
     static constexpr int RPW = (TH + 2 * HMAX + NW - 1) / NW;              // staged rows per wave
     static constexpr int NQ = (kTW + 2 * HMAX + 63) / 64;                  // 64-column chunks
-    static constexpr int WPE = HMAX > kPipeHalo ? 2 : 4;                   // waves per SIMD
+    static constexpr int WPE = NW < 16 && HMAX > kPipeHalo ? 2 : 4;       // waves per SIMD
 };
 
 // Uniform chain layer whose offsets exceed the staged halo (or are not
@@ -1441,6 +1445,7 @@ static hipError_t launch_typed(const void* src, void* dst, const float* pmap, co
     } else {
         SV_TRY_PIPE(8, kPipeHalo8, 0, false, 80 * 1024)
         SV_TRY_PIPE(16, kPipeHalo, 0, false, 160 * 1024)
+        SV_TRY_PIPE(16, kPipeHaloBig, 0, false, 160 * 1024)
     }
 #undef SV_TRY_PIPE
     // A staged tile pays for its halo only when it is tall: 64 x 32 tiles while
@@ -1456,6 +1461,18 @@ static hipError_t launch_typed(const void* src, void* dst, const float* pmap, co
         hipError_t e;
         if (sv_rows_per_wave(halo, C) == 4) {
             e = launch_tiles<C, DIMS, TIn, TOut, 4, 8>(xs, ys, ps, table, tap0, N, T, G0, G1, H, W, halo, flag, s);
+        } else if (C >= 3 && sv_rows_per_wave(halo, 2) == 4) {
+            // Every plane is filtered with the same per-pixel coefficients and
+            // independently of the others: groups of two planes stage 8-byte
+            // pixels, whose 64 x 32 tiles still fit the LDS at this halo.
+            if constexpr (C >= 3) {
+                const size_t plane = static_cast<size_t>(H) * W;
+                e = launch_typed<2, DIMS, TIn, TOut>(xs, ys, ps, table, tap0, N, T, G0, G1, H, W, halo, flag, nullptr,
+                                                     s, Frames{});
+                if (e == hipSuccess)
+                    e = launch_typed<C - 2, DIMS, TIn, TOut>(xs + 2 * plane, ys + 2 * plane, ps, table, tap0, N, T,
+                                                             G0, G1, H, W, halo, flag, nullptr, s, Frames{});
+            }
         } else {
             const long px = static_cast<long>(H) * W;
             hipLaunchKernelGGL((sv_pass_global_kernel<C, DIMS, TIn, TOut>), dim3(static_cast<unsigned>((px + 255) / 256)),

@@ -201,22 +201,31 @@ def test_sv_2d_4k_bf16_sampled(dev):
         assert e <= TOL_BF16
 
 
-@pytest.mark.parametrize("C,dims", [(3, 1), (4, 2), (1, 1)])
-def test_sv_large_halo_global_path(dev, C, dims):
-    """Halos whose staged tile exceeds the LDS (offsets up to ~45 px for C = 3, 4)
-    take the one-pixel-per-thread kernel; same results."""
+@pytest.mark.parametrize("C,dims,r0,dr,want_halo", [
+    (3, 1, 30.0, 3.0, [41, 41]),
+    (4, 2, 30.0, 3.0, [52, 52]),
+    (1, 1, 30.0, 3.0, [42, 39]),
+    (3, 2, 38.0, 1.5, [43, 49]),
+])
+def test_sv_large_halo_global_path(dev, C, dims, r0, dr, want_halo):
+    """Large halos: C = 3 at halo 41 (plane groups on the staged C <= 2
+    kernel), C = 4 at halo 52 and C = 3 at 43 and 49, beyond every staged
+    tile (the one-pixel-per-thread kernel), C = 1 at halos 42 and 39
+    (staged)."""
     taps = [5, 6]
     G = 6 if dims == 1 else 9
-    basis = _basis(G, taps, seed=500 + C, r0=30.0, dr=3.0)
+    basis = _basis(G, taps, seed=500 + C, r0=r0, dr=dr)
     H, W = 96, 150
     img = noise_image(H, W, C, seed=C, n_rects=8)
     P = param_map(H, W, seed=7, period=64.0, dims=dims)
     grid = [G] if dims == 1 else [3, 3]
-    say("sv large halo", C, dims)
+    say("sv large halo", C, dims, want_halo)
     out, b = _run(basis, taps, grid, img, P)
-    assert max(b.halo) > 33
+    assert list(b.halo) == want_halo
     want = SV.sv_chain(img.astype(np.float64), P.astype(np.float64), basis.astype(np.float64), grid, taps)
-    assert rel_err(to_np(out), want) <= TOL_F32
+    e = rel_err(to_np(out), want)
+    print(f"sv large halo C={C} dims={dims} halo={b.halo}: {e:.2e}")
+    assert e <= TOL_F32
 
 
 @pytest.mark.parametrize("C,dims,io,seed,r0,dr,want_halo", [
@@ -224,11 +233,20 @@ def test_sv_large_halo_global_path(dev, C, dims):
     (4, 1, torch.float32, 720, 26.5, 0.5, [27, 30, 29]),
     (3, 2, torch.float32, 720, 26.5, 0.3, [28, 29, 30]),
     (3, 2, torch.bfloat16, 700, 26.0, 0.3, [28, 26, 28]),
+    (3, 2, torch.float32, 800, 28.0, 0.3, [31, 29, 31]),
+    (3, 2, torch.bfloat16, 820, 39.0, 0.3, [39, 40, 41]),
+    (4, 2, torch.float32, 800, 39.0, 0.3, [41, 40, 42]),
+    (2, 1, torch.float32, 820, 32.0, 0.5, [32, 34, 35]),
+    (2, 2, torch.bfloat16, 800, 39.0, 0.3, [41, 40, 42]),
+    (1, 2, torch.float32, 820, 39.0, 0.3, [39, 40, 41]),
 ])
-def test_sv_wide_halo_staged(dev, C, dims, io, seed, r0, dr, want_halo):
-    """Halos 25..30 (C >= 3): the 8-wave kernel with 64 x 16 tiles and 124-pixel
-    staged rows, over several tiles with ragged right and bottom tails, the
-    CLAMP border on every side, against the oracle on the whole image."""
+def test_sv_staged_large_halo(dev, C, dims, io, seed, r0, dr, want_halo):
+    """Halos 25..42 on staged tiles: C >= 3 up to halo 30 on the 8-wave kernel
+    with 64 x 16 tiles and 124-pixel rows; beyond that the image's planes in
+    groups of two (and one) on the 16-wave C <= 2 kernel, whose 64 x 32 tiles
+    of 8-byte pixels fit up to halo 42; C <= 2 images on that kernel directly.
+    Several tiles with ragged right and bottom tails, the CLAMP border on
+    every side, against the oracle on the whole image."""
     taps = [6, 6, 5]
     G = 6 if dims == 1 else 9
     grid = [G] if dims == 1 else [3, 3]
@@ -236,19 +254,19 @@ def test_sv_wide_halo_staged(dev, C, dims, io, seed, r0, dr, want_halo):
     H, W = 70, 150
     img = noise_image(H, W, C, seed=seed, n_rects=10)
     P = param_map(H, W, seed=seed + 1, period=48.0, dims=dims)
-    say("sv wide halo", C, dims, io, want_halo)
+    say("sv staged large halo", C, dims, io, want_halo)
     out, b = _run(basis, taps, grid, img, P, io=io)
     assert list(b.halo) == want_halo
     x = img if io == torch.float32 else bf16_round(img)
     want = SV.sv_chain(x.astype(np.float64), P.astype(np.float64), basis.astype(np.float64), grid, taps)
     e = rel_err(to_np(out), want)
-    print(f"sv wide halo C={C} dims={dims} {io} halo={b.halo}: {e:.2e}")
+    print(f"sv staged large halo C={C} dims={dims} {io} halo={b.halo}: {e:.2e}")
     assert e <= (TOL_F32 if io == torch.float32 else TOL_BF16)
 
 
 def test_sv_halo_just_beyond_padded_tile(dev):
-    """C = 3 with halos 31..33, just beyond the staged kernels (the
-    one-pixel-per-thread kernel)."""
+    """C = 3 with halos 31..33, just beyond the staged C >= 3 kernels (plane
+    groups on the C <= 2 kernel)."""
     taps = [6, 6]
     basis = _basis(6, taps, seed=610, r0=29.6, dr=0.38)
     H, W = 80, 170
