@@ -204,6 +204,8 @@ disk_status disk_forward(const disk_complex* cx, const float* theta, const void*
 // ---------------------------------------------------------------------------
 // backward
 // ---------------------------------------------------------------------------
+static size_t partial_slot(int nblk, int maxN) { return static_cast<size_t>(nblk) * maxN * 4 + maxN * 4; }
+
 static size_t backward_ws(const disk_complex* cx, int C, int H, int W, Carve& cv, TapU** tapu, float** partial,
                           float** g0, float** g1) {
     const LayerSpec sp = make_spec(*cx);
@@ -211,7 +213,8 @@ static size_t backward_ws(const disk_complex* cx, int C, int H, int W, Carve& cv
     for (int l = 0; l < sp.L; ++l) maxN = std::max(maxN, sp.taps[l]);
     const int nblk = adjoint_tap_blocks(H, W);
     *tapu = cv.take<TapU>(sp.T);
-    *partial = cv.take<float>(static_cast<size_t>(nblk) * maxN * 4 + maxN * 4);
+    // one slot of partial rows per layer (their finish runs after the last layer)
+    *partial = cv.take<float>(static_cast<size_t>(sp.L) * partial_slot(nblk, maxN));
     *g0 = cv.take<float>(image_floats(C, H, W));
     *g1 = cv.take<float>(image_floats(C, H, W));
     return cv.used;
@@ -252,18 +255,29 @@ disk_status disk_backward(const disk_complex* cx, const float* theta, const floa
     const LayerSpec sp = make_spec(*cx);
     const size_t n = image_floats(C, H, W);
     const int nblk = adjoint_tap_blocks(H, W);
+    int maxN = 0;
+    for (int l = 0; l < sp.L; ++l) maxN = std::max(maxN, sp.taps[l]);
+    const size_t slot = partial_slot(nblk, maxN);
     DISK_HIP(launch_prep_uniform(theta, sp.T, tapu, stream), "prep");
     const float* G = grad_out;
+    FinishLayers fin;   // the fused layers' dTheta, reduced in one launch after the last layer
     for (int l = sp.L - 1; l >= 0; --l) {
         const void* X = l == 0 ? static_cast<const void*>(in) : static_cast<const void*>(saved + (l - 1) * n);
         const int src_kind = (l == 0 && impulse) ? 2 : 0;
+        float* partial_l = partial + l * slot;
         if (grad_theta && (l > 0 || grad_in) && !impulse && chain_pass_ok(C, DISK_CLAMP)) {
             // the input adjoint and the tap correlations in one staged pass
             float* Gn = l == 0 ? grad_in : (G == g0 ? g1 : g0);
+            int nrows = 0;
             DISK_HIP(launch_chain_fused(C, boundary, G, static_cast<const float*>(X), Gn, theta, sp.tap0[l],
-                                        sp.taps[l], sp.T, H, W, partial, tapu + sp.tap0[l],
-                                        grad_theta + 3 * sp.tap0[l], stream),
+                                        sp.taps[l], sp.T, H, W, partial_l, tapu + sp.tap0[l], &nrows, stream),
                      "adjoint fused");
+            const int k = fin.n++;
+            fin.first[k] = k == 0 ? 0 : fin.first[k - 1] + fin.N[k - 1];
+            fin.N[k] = sp.taps[l];
+            fin.nblk[k] = nrows;
+            fin.tap0[k] = sp.tap0[l];
+            fin.pofs[k] = static_cast<long long>(l) * static_cast<long long>(slot);
             G = Gn;
             continue;
         }
@@ -271,14 +285,14 @@ disk_status disk_backward(const disk_complex* cx, const float* theta, const floa
             int nb = nblk;
             if (!impulse && chain_pass_ok(C, DISK_CLAMP)) {
                 DISK_HIP(launch_adjoint_corr(C, boundary, static_cast<const float*>(X), G, theta, sp.tap0[l], sp.taps[l],
-                                             sp.T, H, W, partial, &nb, stream),
+                                             sp.T, H, W, partial_l, &nb, stream),
                          "adjoint taps");
             } else {
-                DISK_HIP(launch_adjoint_taps(C, boundary, src_kind, X, G, tapu + sp.tap0[l], sp.taps[l], H, W, partial,
-                                             stream),
+                DISK_HIP(launch_adjoint_taps(C, boundary, src_kind, X, G, tapu + sp.tap0[l], sp.taps[l], H, W,
+                                             partial_l, stream),
                          "adjoint taps");
             }
-            DISK_HIP(launch_adjoint_finish(partial, nb, theta + 3 * sp.tap0[l], sp.taps[l],
+            DISK_HIP(launch_adjoint_finish(partial_l, nb, theta + 3 * sp.tap0[l], sp.taps[l],
                                            grad_theta + 3 * sp.tap0[l], stream),
                      "adjoint finish");
         }
@@ -298,6 +312,7 @@ disk_status disk_backward(const disk_complex* cx, const float* theta, const floa
             G = Gn;
         }
     }
+    if (fin.n > 0) DISK_HIP(launch_adjoint_finish_layers(fin, partial, theta, grad_theta, stream), "adjoint finish");
     return ok();
 }
 

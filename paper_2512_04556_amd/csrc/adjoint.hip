@@ -107,15 +107,13 @@ __global__ __launch_bounds__(256) void adjoint_taps_kernel(Src src, const float*
     }
 }
 
-// One block per (tap, corner): fixed-order strided sums then a fixed tree.
 // One work-group per tap: the four corner sums S_ab over the nblk block
 // partials (thread t adds blocks t, t + 256, ... in order, then a fixed tree),
 // and from them the tap's gradient (the bilinear weights' derivatives).
-__global__ __launch_bounds__(256) void adjoint_finish_kernel(const float* __restrict__ partial, int nblk, int N,
-                                                             const float* __restrict__ theta,
-                                                             float* __restrict__ dtheta) {
+__device__ __forceinline__ void finish_tap(const float* __restrict__ partial, int nblk, int N, int i,
+                                           const float* __restrict__ theta, float* __restrict__ dtheta) {
     __shared__ float buf[4][256];
-    const int i = blockIdx.x, t = threadIdx.x;
+    const int t = threadIdx.x;
     float v[4] = {0.0f, 0.0f, 0.0f, 0.0f};
     for (int b = t; b < nblk; b += 256) {
         const float* q = partial + (static_cast<size_t>(b) * N + i) * 4;
@@ -144,6 +142,23 @@ __global__ __launch_bounds__(256) void adjoint_finish_kernel(const float* __rest
     dtheta[3 * i + 0] = gx;
     dtheta[3 * i + 1] = gy;
     dtheta[3 * i + 2] = gw;
+}
+
+__global__ __launch_bounds__(256) void adjoint_finish_kernel(const float* __restrict__ partial, int nblk, int N,
+                                                             const float* __restrict__ theta,
+                                                             float* __restrict__ dtheta) {
+    finish_tap(partial, nblk, N, blockIdx.x, theta, dtheta);
+}
+
+// The finish of several layers in one launch: work-group b takes tap
+// b - first[l] of entry l (first[] ascending).
+__global__ __launch_bounds__(256) void adjoint_finish_layers_kernel(FinishLayers a, const float* __restrict__ partial,
+                                                                    const float* __restrict__ theta,
+                                                                    float* __restrict__ dtheta) {
+    int l = 0;
+    while (l + 1 < a.n && static_cast<int>(blockIdx.x) >= a.first[l + 1]) ++l;
+    finish_tap(partial + a.pofs[l], a.nblk[l], a.N[l], blockIdx.x - a.first[l], theta + 3 * a.tap0[l],
+               dtheta + 3 * a.tap0[l]);
 }
 
 template <int C, int BOUND, class Src>
@@ -185,6 +200,14 @@ hipError_t launch_adjoint_taps(int C, int boundary, int src_kind, const void* X,
 
 // `partial` holds nblk * N * 4 block partials (the workspace carving also
 // reserves N * 4 floats after them).
+hipError_t launch_adjoint_finish_layers(const FinishLayers& a, const float* partial, const float* theta, float* dtheta,
+                                        hipStream_t s) {
+    if (a.n < 1 || a.n > DISK_MAX_LAYERS) return hipErrorInvalidValue;
+    const int nwg = a.first[a.n - 1] + a.N[a.n - 1];
+    hipLaunchKernelGGL(adjoint_finish_layers_kernel, dim3(nwg), dim3(256), 0, s, a, partial, theta, dtheta);
+    return hipGetLastError();
+}
+
 hipError_t launch_adjoint_finish(float* partial, int nblk, const float* theta_layer, int N, float* dtheta_layer,
                                  hipStream_t s) {
     hipLaunchKernelGGL(adjoint_finish_kernel, dim3(N), dim3(256), 0, s, partial, nblk, N, theta_layer,

@@ -1564,7 +1564,7 @@ hipError_t launch_adjoint_corr(int C, int boundary, const float* X, const float*
 
 template <int C>
 static hipError_t fused_c(int zero, const float* G, const float* X, float* Gn, const float* theta, int tap0, int N,
-                          int T, int H, int W, float* partial, const TapU* taps, float* dtheta, hipStream_t s) {
+                          int T, int H, int W, float* partial, const TapU* taps, int* nrows_out, hipStream_t s) {
     int nb = 0;
     hipError_t e = zero ? launch_pipe<C, 1, float, float, 16, kPipeHalo, kPipeRowB, true, 6>(
                               G, Gn, X, nullptr, tap0, N, T, 1, 1, H, W, 0, nullptr, theta, s, N, 0, &nb, partial)
@@ -1587,14 +1587,15 @@ static hipError_t fused_c(int zero, const float* G, const float* X, float* Gn, c
                                   partial, nrows, parts, Gn, s);
         if (e != hipSuccess) return e;
     }
-    return launch_adjoint_finish(partial, nrows, theta + 3 * tap0, N, dtheta, s);
+    *nrows_out = nrows;
+    return hipSuccess;
 }
 hipError_t launch_chain_fused(int C, int boundary, const float* G, const float* X, float* Gn, const float* theta,
                               int tap0, int N, int T, int H, int W, float* partial, const TapU* taps,
-                              float* dtheta, hipStream_t s) {
+                              int* nrows, hipStream_t s) {
     const int zero = boundary == DISK_ZERO;
-    if (C == 3) return fused_c<3>(zero, G, X, Gn, theta, tap0, N, T, H, W, partial, taps, dtheta, s);
-    if (C == 4) return fused_c<4>(zero, G, X, Gn, theta, tap0, N, T, H, W, partial, taps, dtheta, s);
+    if (C == 3) return fused_c<3>(zero, G, X, Gn, theta, tap0, N, T, H, W, partial, taps, nrows, s);
+    if (C == 4) return fused_c<4>(zero, G, X, Gn, theta, tap0, N, T, H, W, partial, taps, nrows, s);
     return hipErrorInvalidValue;
 }
 

@@ -56,6 +56,16 @@ hipError_t launch_adjoint_taps(int C, int boundary, int src_kind, const void* X,
 // Reduces partials (fixed order) and writes dtheta rows [N][3] of this layer.
 hipError_t launch_adjoint_finish(float* partial, int nblk, const float* theta_layer, int N, float* dtheta_layer,
                                  hipStream_t s);
+// The same for n layers in one launch: entry l has N[l] taps from tap0[l] of
+// the complex, nblk[l] partial rows at partial + pofs[l] (floats), and
+// first[l] = the sum of N over the entries before it.
+struct FinishLayers {
+    int n = 0;
+    int first[DISK_MAX_LAYERS], N[DISK_MAX_LAYERS], nblk[DISK_MAX_LAYERS], tap0[DISK_MAX_LAYERS];
+    long long pofs[DISK_MAX_LAYERS];
+};
+hipError_t launch_adjoint_finish_layers(const FinishLayers& a, const float* partial, const float* theta, float* dtheta,
+                                        hipStream_t s);
 // Input adjoint: Gprev = A^T G (exact transpose incl. CLAMP border folding).
 // pad: scratch of (H+2R)*(W+2R)*C floats for CLAMP (R = halo); may be null for ZERO.
 hipError_t launch_adjoint_input(int C, int boundary, const float* G, const TapU* taps, int N, int H, int W,
@@ -102,12 +112,13 @@ hipError_t launch_adjoint_corr(int C, int boundary, const float* X, const float*
 // The backward of a chain layer (C = 3, 4; ZERO or CLAMP forward): its
 // transpose G' into Gn fused with its tap correlations (the in-image part of
 // the first taps from the fused pass, the other taps from correlation passes
-// on the same grid, as rows of partial[][N][4]), then dTheta into dtheta (the
-// layer's 3 N values).  For CLAMP one launch in between adds the samples that
-// leave the image and recomputes the border pixels of Gn exactly
-// (launch_adjoint_border).  taps: the layer's prepared taps.
+// on the same grid, as rows of partial[][N][4]; *nrows is set to their
+// count, for launch_adjoint_finish or launch_adjoint_finish_layers).  For
+// CLAMP one launch after the pass adds the samples that leave the image and
+// recomputes the border pixels of Gn exactly (launch_adjoint_border).  taps:
+// the layer's prepared taps.
 hipError_t launch_chain_fused(int C, int boundary, const float* G, const float* X, float* Gn, const float* theta,
-                              int tap0, int N, int T, int H, int W, float* partial, const TapU* taps, float* dtheta,
+                              int tap0, int N, int T, int H, int W, float* partial, const TapU* taps, int* nrows,
                               hipStream_t s);
 // The CLAMP border work of one fused backward layer in one launch: the
 // correlation samples that leave the image into rows nrows - parts .. nrows -
