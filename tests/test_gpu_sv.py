@@ -302,18 +302,23 @@ def test_basis_rotate_and_angle_effect(dev, kind):
     assert rel_err(to_np(out), ref) <= TOL_F32
 
 
-@pytest.mark.parametrize("C,H,W,grid,taps,io,per_frame", [
-    (3, 150, 333, [16], [8, 8, 8, 8], torch.float32, False),   # pipelined kernel, frames in one launch
-    (3, 97, 130, [16], [8, 8, 8, 8], torch.bfloat16, True),
-    (4, 70, 100, [3, 3], [6, 5], torch.float32, True),          # 2-D basis, prepared table
-    (1, 64, 80, [5], [5, 4, 6], torch.float32, False),          # one-tile kernel, a launch per frame
+@pytest.mark.parametrize("C,H,W,grid,taps,io,per_frame,r0,dr", [
+    (3, 150, 333, [16], [8, 8, 8, 8], torch.float32, False, 1.0, 0.8),   # pipelined kernel, frames in one launch
+    (3, 97, 130, [16], [8, 8, 8, 8], torch.bfloat16, True, 1.0, 0.8),
+    (4, 70, 100, [3, 3], [6, 5], torch.float32, True, 1.0, 0.8),          # 2-D basis, prepared table
+    (1, 64, 80, [5], [5, 4, 6], torch.float32, False, 1.0, 0.8),          # pipelined C = 1 kernel
+    (3, 70, 150, [6], [6, 6], torch.float32, True, 24.0, 0.5),            # halos 26: the wide staged kernel
+    (3, 70, 150, [6], [6, 6], torch.bfloat16, False, 33.0, 0.5),          # halos 34: plane groups, per frame
+    (4, 70, 150, [3, 3], [6, 5], torch.float32, True, 33.0, 0.3),         # halos 35, 36: plane groups, 2-D
 ])
-def test_sv_frames_equal_single_frame_calls(dev, C, H, W, grid, taps, io, per_frame):
-    """F frames in one call (one launch per pass over all frames' tiles) equal
-    F single-frame calls bit for bit, with one shared map or a map per frame."""
+def test_sv_frames_equal_single_frame_calls(dev, C, H, W, grid, taps, io, per_frame, r0, dr):
+    """F frames in one call (one launch per pass over all frames' tiles, or a
+    launch per frame and plane group for halos beyond the staged C >= 3
+    kernels) equal F single-frame calls bit for bit, with one shared map or a
+    map per frame."""
     F = 3
     G = int(np.prod(grid))
-    b = disk.make_basis(to_dev(_basis(G, taps, seed=810 + C, r0=1.0, dr=0.8)), taps, grid)
+    b = disk.make_basis(to_dev(_basis(G, taps, seed=810 + C, r0=r0, dr=dr)), taps, grid)
     x = torch.stack([to_dev(noise_image(H, W, C, seed=H + f, n_rects=10)) for f in range(F)]).to(io)
     if per_frame:
         p = torch.stack([to_dev(param_map(H, W, seed=W + f, period=64.0, dims=len(grid))) for f in range(F)])
