@@ -29,6 +29,9 @@ PASS_BYTES_PER_PX = 4 * C + 4 + 4 * C
 # fractions, 6 for the four corner weights, 3 for the LDS corner address (2 FMAs
 # and a conversion), 12 accumulating FMAs (3 channels x 4 corners)
 OPS_PER_PX_TAP = 3 + 4 + 6 + 3 + 12
+# the same with a 2-D basis: the bilinear coefficient interpolation takes the
+# product of the two fractions and 3 FMAs per parameter (ox, oy, w) instead of 3
+OPS_PER_PX_TAP_2D = 1 + 9 + 4 + 6 + 3 + 12
 # FP32 vector peak in operations: 256 CUs x 4 SIMDs x 32 lanes x 2.4 GHz.  On
 # gfx950 a plain (non-packed) wave64 FP32 add, multiply or FMA issues in two
 # cycles (measured), which is the published 157.3 TFLOP/s with an FMA counted
@@ -271,8 +274,12 @@ def sv2d_4k(torch, disk, steps=20):
     ms = e0.elapsed_time(e1) / steps
     # algorithmic bytes: first pass reads 6 B, middle 12 B, last writes 6 B, plus 8 B of map per pass
     frame_bytes = h * w * (6 + 12 + 8 + (12 + 12 + 8) * 2 + 12 + 6 + 8)
+    ops = OPS_PER_PX_TAP_2D * sum(taps) * h * w / (ms * 1e-3) / 1e12
     return {"workload": "sv_filter_2160p_bf16_2d", "ms_per_frame": round(ms, 4), "mpix_s": round(h * w / ms / 1e3, 1),
-            "hbm_frac": round(frame_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4), "halo": basis.halo,
+            "hbm_frac": round(frame_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "alu": {"achieved": round(ops, 3), "peak": round(VALU_PEAK_TOPS, 2),
+                    "unit": "Tops/s (FP32 vector, FMA = 1)", "frac": round(ops / VALU_PEAK_TOPS, 4)},
+            "halo": basis.halo,
             "basis_build_s": round(build_s, 3), "basis_psnr_db_mean": round(float(ps.mean()), 2)}
 
 
