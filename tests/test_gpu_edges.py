@@ -14,7 +14,7 @@ from oracle import init as I
 from oracle import sparse as S
 from oracle import svfilter as SV
 from synth import TargetBatch, disk_kernel, noise_image, random_theta
-from tests.gpu_util import say, to_dev, to_np, rel_err, TOL_F32
+from tests.gpu_util import say, to_dev, to_np, rel_err, bf16_round, TOL_F32, TOL_BF16
 
 pytestmark = pytest.mark.gpu
 
@@ -53,6 +53,29 @@ def test_max_structure_image_chain(dev, C, H, W):
     e = (rel_err(to_np(out), want), rel_err(to_np(gt), wt), rel_err(to_np(gi), wi))
     print(f"8 x 32 taps, {C} x {H} x {W}: forward {e[0]:.2e} dTheta {e[1]:.2e} dX {e[2]:.2e}")
     assert max(e) <= TOL_F32
+
+
+@pytest.mark.parametrize("C,grid,io", [(3, [16], torch.float32), (4, [4, 4], torch.float32),
+                                      (3, [16], torch.bfloat16)])
+def test_sv_filter_max_structure(dev, C, grid, io):
+    """The spatially varying filter with the largest layer structure (8 layers
+    x 32 taps, T = 256: the layer tables no longer fit the LDS beside the
+    tile) on a ragged multi-tile image, 1-D and 2-D bases, against the
+    oracle on the whole image."""
+    G = int(np.prod(grid))
+    basis = np.stack([random_theta(TAPS_MAX, 1.0 + 0.25 * k, seed=70 + k) for k in range(G)]).astype(np.float32)
+    H, W = 45, 140
+    img = noise_image(H, W, C, seed=C + 50, n_rects=6)
+    rng = np.random.default_rng(C + 60)
+    P = rng.random((len(grid), H, W)).astype(np.float32)
+    b = disk.make_basis(to_dev(basis), TAPS_MAX, grid)
+    say("sv filter max structure", C, grid, io, b.halo)
+    out = disk.disk_sv_filter(b, to_dev(img).to(io), to_dev(P))
+    x = img.astype(np.float64) if io == torch.float32 else bf16_round(img)
+    want = SV.sv_chain(x, P.astype(np.float64), basis.astype(np.float64), grid, TAPS_MAX)
+    e = rel_err(to_np(out), want)
+    print(f"sv 8 x 32 taps C={C} grid={grid} {io} halo={b.halo}: {e:.2e}")
+    assert e <= (TOL_F32 if io == torch.float32 else TOL_BF16)
 
 
 def test_sv_filter_one_pixel_image(dev):
