@@ -372,6 +372,35 @@ def test_sv_frames_bench_launch_and_graph_replay(dev):
         assert e <= TOL_F32
 
 
+@pytest.mark.parametrize("seed,r0,io,want_halo", [(720, 26.5, torch.float32, [28, 29, 30]),
+                                                 (820, 39.0, torch.bfloat16, [39, 40, 41])])
+def test_sv_large_halo_frames_graph_replay(dev, seed, r0, io, want_halo):
+    """Large-halo passes (the wide staged C = 3 kernel; plane groups, a launch
+    per frame and group) captured in a HIP graph with 2 frames of a 2-D basis:
+    three replays with eager work between them equal the eager call bit for
+    bit."""
+    taps = [6, 6, 5]
+    basis = _basis(9, taps, seed=seed, r0=r0, dr=0.3)
+    b = disk.make_basis(to_dev(basis), taps, [3, 3])
+    assert list(b.halo) == want_halo
+    H, W, F = 70, 150, 2
+    x = torch.stack([to_dev(noise_image(H, W, 3, seed=seed + f, n_rects=10)) for f in range(F)]).to(io)
+    p = to_dev(param_map(H, W, seed=seed + 5, period=48.0, dims=2))
+    out = torch.empty_like(x)
+    ws = disk.sv_frames_workspace(b, F, 3, H, W, disk.BF16 if io == torch.bfloat16 else disk.F32)
+    say("sv large halo frames eager", want_halo, io)
+    want = disk.disk_sv_filter_frames(b, x, p, ws=ws).clone()
+    say("sv large halo frames graph capture")
+    cap = disk.Captured(lambda: disk.disk_sv_filter_frames(b, x, p, out=out, ws=ws), warmup=False)
+    for r in range(3):
+        x[0].mul_(1.0)                       # eager work between replays
+        torch.cuda.synchronize()
+        say("sv large halo graph replay", r)
+        cap.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(out, want), r
+
+
 def test_tilt_shift_from_pseudo_depth(dev):
     """Tilt-shift (the depth-driven effect of the paper's spatially varying
     examples): blur from the distance of a pseudo-depth map to the focal
