@@ -636,6 +636,23 @@ struct PipeShape {
     static constexpr int WPE = NW < 16 && HMAX > kPipeHalo ? 2 : 4;       // waves per SIMD
 };
 
+// Staging registers of the pipelined kernel hold what each load returned,
+// untouched until the LDS store: arithmetic on a loaded value (the BF16
+// widening, the zero select outside the image) would make the compiler wait
+// for that load inside the prefetch, before the gathers it should overlap.
+template <typename T>
+struct Staged {
+    using type = float;
+    __device__ __forceinline__ static float load(const float* p) { return *p; }
+    __device__ __forceinline__ static float widen(float v) { return v; }
+};
+template <>
+struct Staged<uint16_t> {
+    using type = uint32_t;
+    __device__ __forceinline__ static uint32_t load(const uint16_t* p) { return *p; }
+    __device__ __forceinline__ static float widen(uint32_t v) { return __uint_as_float(v << 16); }
+};
+
 // Uniform chain layer whose offsets exceed the staged halo (or are not
 // finite): the work-group's tiles with corners read straight from the clamped
 // source planes, in the staged path's arithmetic and order.
@@ -1031,7 +1048,9 @@ sv_pass_pipe_kernel(
 #pragma unroll
     for (int d = 0; d < DIMS; ++d) Pd[d] = chain ? nullptr : P + d * plane;
 
-    float stg[kPipeRPW][kPipeNQ][C];
+    static_assert(kPipeRPW * kPipeNQ <= 32, "one outside-the-image bit per staged (row, chunk)");
+    typename Staged<TIn>::type stg[kPipeRPW][kPipeNQ][C];
+    uint32_t zmask = 0;   // zstage: bit rr * kPipeNQ + q set when that staged value lies outside the image
     float pv[PY][DIMS];
     float gv[PY][C];   // corr: the tile's output gradient at the lane's pixels
     // (frame, tile within the frame) of the current and the prefetched tile,
@@ -1065,6 +1084,7 @@ sv_pass_pipe_kernel(
             gx[q] = static_cast<uint32_t>(min(max(cx, 0), W - 1));
             vx[q] = zstage ? static_cast<unsigned>(cx) < static_cast<unsigned>(W) : true;
         }
+        if constexpr (zstage) zmask = 0;
 #pragma unroll
         for (int rr = 0; rr < kPipeRPW; ++rr) {
             if (rr < nr) {
@@ -1076,13 +1096,9 @@ sv_pass_pipe_kernel(
                     if (q < nq) {
                         const uint32_t off = (grow + gx[q]) * static_cast<uint32_t>(sizeof(TIn));   // bytes
 #pragma unroll
-                        for (int c = 0; c < C; ++c) {
-                            const float v = IO<TIn>::load(byte_at(Xc[c] + xfo, off), 0);
-                            if constexpr (zstage)
-                                stg[rr][q][c] = (vy && vx[q]) ? v : 0.0f;
-                            else
-                                stg[rr][q][c] = v;
-                        }
+                        for (int c = 0; c < C; ++c) stg[rr][q][c] = Staged<TIn>::load(byte_at(Xc[c] + xfo, off));
+                        if constexpr (zstage)
+                            if (!(vy && vx[q])) zmask |= 1u << (rr * kPipeNQ + q);
                     }
                 }
             }
@@ -1131,7 +1147,16 @@ sv_pass_pipe_kernel(
 #pragma unroll
             for (int q = 0; q < kPipeNQ; ++q) {
                 const int cx = lane + 64 * q;
-                if (rr < nr && q < nq && cx < SX) sv_put<C>(lds, rowW, ly, cx, stg[rr][q]);
+                if (rr < nr && q < nq && cx < SX) {
+                    float v[C];
+#pragma unroll
+                    for (int c = 0; c < C; ++c) v[c] = Staged<TIn>::widen(stg[rr][q][c]);
+                    if constexpr (zstage)
+                        if ((zmask >> (rr * kPipeNQ + q)) & 1u)
+#pragma unroll
+                            for (int c = 0; c < C; ++c) v[c] = 0.0f;
+                    sv_put<C>(lds, rowW, ly, cx, v);
+                }
             }
         }
         float ta[PY], tb[PY];
