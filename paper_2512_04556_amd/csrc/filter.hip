@@ -1052,7 +1052,8 @@ sv_pass_pipe_kernel(
     typename Staged<TIn>::type stg[kPipeRPW][kPipeNQ][C];
     uint32_t zmask = 0;   // zstage: bit rr * kPipeNQ + q set when that staged value lies outside the image
     float pv[PY][DIMS];
-    float gv[PY][C];   // corr: the tile's output gradient at the lane's pixels
+    float gv[PY][C];   // corr: the tile's output gradient at the lane's pixels (as loaded)
+    uint32_t gmask = 0;   // corr: bit j set when the lane's pixel j lies outside the image
     // (frame, tile within the frame) of the current and the prefetched tile,
     // advanced by nwg without a division (nwg <= tiles per frame is not
     // assumed); chain layers (MODE != 0) always cover one frame
@@ -1105,16 +1106,15 @@ sv_pass_pipe_kernel(
         }
         const uint32_t xc = static_cast<uint32_t>(min(tx0 + lx, W - 1));
         if constexpr (corr) {
+            gmask = 0;
 #pragma unroll
             for (int j = 0; j < PY; ++j) {
                 const int y = ty0 + 4 * j + lyb;
                 const bool in = tx0 + lx < W && y < H;
                 const uint32_t pi = (static_cast<uint32_t>(min(y, H - 1)) * static_cast<uint32_t>(W) + xc) * 4u;
 #pragma unroll
-                for (int c = 0; c < C; ++c) {
-                    const float v = *byte_at(P + c * plane, pi);
-                    gv[j][c] = in ? v : 0.0f;
-                }
+                for (int c = 0; c < C; ++c) gv[j][c] = *byte_at(P + c * plane, pi);
+                if (!in) gmask |= 1u << j;
             }
         }
 #pragma unroll
@@ -1183,7 +1183,7 @@ sv_pass_pipe_kernel(
             for (int j = 0; j < PY; ++j)
 #pragma unroll
                 for (int c = 0; c < C; ++c) {
-                    xq[j][c] = gv[j][c];
+                    xq[j][c] = ((gmask >> j) & 1u) ? 0.0f : gv[j][c];
                     asm volatile("" ::"v"(xq[j][c]));   // this tile's X ahead of the prefetch
                 }
             if (next < tend) issue(nxt_f, nxt_t);
@@ -1197,7 +1197,7 @@ sv_pass_pipe_kernel(
             for (int j = 0; j < PY; ++j)
 #pragma unroll
                 for (int c = 0; c < C; ++c) {
-                    gc[j][c] = gv[j][c];
+                    gc[j][c] = ((gmask >> j) & 1u) ? 0.0f : gv[j][c];
                     asm volatile("" ::"v"(gc[j][c]));   // this tile's G ahead of the prefetch
                 }
             if (next < tend) issue(nxt_f, nxt_t);
