@@ -4,8 +4,9 @@
 
     python bench.py [--steps K] [--warmup W] [--gpus 1]
 
-One step = one disk_sv_filter call on a frame already resident in HBM
-(basis preparation + the 4 gather passes).  Prints one JSON line.
+One step = one disk_sv_filter_frames call on 32 frames already resident in
+HBM (the 4 gather passes, each over the tiles of all frames), captured once
+in a HIP graph and replayed.  Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -44,7 +45,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--frames", type=int, default=8, help="frames per step (one captured call over all of them)")
+    ap.add_argument("--frames", type=int, default=32, help="frames per step (one captured call over all of them)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--basis", choices=["fitted", "random"], default="fitted")
     ap.add_argument("--no-time-to-40db", action="store_true")
