@@ -1474,10 +1474,10 @@ static hipError_t launch_typed(const void* src, void* dst, const float* pmap, co
     }
 #undef SV_TRY_PIPE
     // A staged tile pays for its halo only when it is tall: 64 x 32 tiles while
-    // they fit; below that the halo rows dominate (measured: an 8-row tile at
-    // halo 33 is slower than reading the corners through L1), so larger halos
-    // take the one-pixel-per-thread kernel.
-    // the kernels below take one frame per launch
+    // they fit (for a C >= 3 image, its planes in groups of two and one); below
+    // that the halo rows dominate (measured: an 8-row tile at halo 33 is slower
+    // than reading the corners through L1), so larger halos take the
+    // one-pixel-per-thread kernel.  The kernels below take one frame per launch.
     const size_t fsz = static_cast<size_t>(C) * H * W, psz = fr.pmap_shared ? 0 : static_cast<size_t>(DIMS) * H * W;
     for (int f = 0; f < fr.F; ++f) {
         const TIn* xs = static_cast<const TIn*>(src) + f * fsz;
