@@ -93,6 +93,21 @@ def test_sv_halo_violation_gives_nan(dev):
     assert torch.isnan(out).all()
 
 
+@pytest.mark.parametrize("seed,r0,declared", [(720, 26.5, 26), (820, 39.0, 33)])
+def test_sv_halo_violation_large_halo_paths(dev, seed, r0, declared):
+    """A declared halo below the real offsets on the large-halo paths (the
+    wide staged C = 3 kernel at 26; plane groups at 33): every output NaN."""
+    taps = [6, 6, 5]
+    basis = _basis(9, taps, seed=seed, r0=r0, dr=0.3)
+    b = disk.make_basis(to_dev(basis), taps, [3, 3])
+    b.desc.halo[1] = declared
+    img = to_dev(noise_image(70, 150, 3, seed=seed, n_rects=6))
+    P = to_dev(param_map(70, 150, seed=seed + 5, period=48.0, dims=2))
+    say("sv halo violation large", declared)
+    out = disk.disk_sv_filter(b, img, P)
+    assert torch.isnan(out).all()
+
+
 @pytest.mark.parametrize("C,io,taps,G", [
     (3, torch.float32, [8, 8, 8, 8], 16),
     (4, torch.float32, [5, 9, 3], 7),
