@@ -78,6 +78,26 @@ def test_sv_filter_max_structure(dev, C, grid, io):
     assert e <= (TOL_F32 if io == torch.float32 else TOL_BF16)
 
 
+@pytest.mark.parametrize("H,W,r0,want_max", [(1, 1, 26.5, 30), (2, 65, 26.5, 30), (1, 1, 39.0, 41), (3, 70, 39.0, 41)])
+def test_sv_filter_tiny_images_large_halo(dev, H, W, r0, want_max):
+    """Images far smaller than the halo on the large-halo paths (the wide
+    staged C = 3 kernel at halos up to 30, plane groups up to 41): every
+    staged read clamps into the few pixels; against the oracle."""
+    taps = [6, 6, 5]
+    basis = np.stack([random_theta(taps, r0 + 0.3 * k, seed=(720 if r0 < 30 else 820) + k)
+                      for k in range(9)]).astype(np.float32)
+    img = np.random.default_rng(H * W).random((3, H, W)).astype(np.float32)
+    P = np.random.default_rng(H + W).random((2, H, W)).astype(np.float32)
+    b = disk.make_basis(to_dev(basis), taps, [3, 3])
+    assert max(b.halo) == want_max
+    say("sv tiny image large halo", H, W, b.halo)
+    out = disk.disk_sv_filter(b, to_dev(img), to_dev(P))
+    want = SV.sv_chain(img.astype(np.float64), P.astype(np.float64), basis.astype(np.float64), [3, 3], taps)
+    e = rel_err(to_np(out), want)
+    print(f"sv {H} x {W} halo={b.halo}: {e:.2e}")
+    assert e <= TOL_F32
+
+
 def test_sv_filter_one_pixel_image(dev):
     """The SV filter on a 1 x 1 x 3 image: every read clamps to the one pixel,
     so the output is the pixel times the product of the layers' weight sums
