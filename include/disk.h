@@ -207,6 +207,14 @@ typedef struct {
     int32_t wgs_per_cu;        /* 1..4 for 256 threads, 1 for 1024 */
 } disk_opt_tune;
 size_t disk_optimize_workspace_size(const disk_batch_meta* meta, const disk_opt_tune* tune);
+/* The launch shape the built-in table gives a batch (what disk_optimize_batch
+ * uses with tune = NULL): the first row whose batch size, largest side and
+ * largest tap count bound meta's, else 256 threads x 4.  Host only, nothing
+ * enqueued.
+ *   meta   host: B >= 1, max_side >= 1, max_T >= 1.
+ *   out    host, written on success.
+ * Errors: DISK_INVALID_ARG for a NULL pointer or a field out of range. */
+disk_status disk_optimize_default_tune(const disk_batch_meta* meta, disk_opt_tune* out);
 disk_status disk_optimize_batch(const disk_batch_meta* meta, const disk_target* desc,
                                 const int32_t* taps, const float* targets, float* theta,
                                 float* psnr_db, int32_t* steps, int32_t* status,

@@ -88,6 +88,7 @@ def lib():
         "disk_backward_workspace_size": (c_size_t, [POINTER(DiskComplex), c_int32, c_int32, c_int32]),
         "disk_backward": (c_int32, [POINTER(DiskComplex), P, P, P, P, P, P, c_int32, c_int32, c_int32, c_int32, P, c_size_t, P]),
         "disk_optimize_workspace_size": (c_size_t, [POINTER(DiskBatchMeta), POINTER(DiskOptTune)]),
+        "disk_optimize_default_tune": (c_int32, [POINTER(DiskBatchMeta), POINTER(DiskOptTune)]),
         "disk_optimize_batch": (c_int32, [POINTER(DiskBatchMeta), P, P, P, P, P, P, P, P, POINTER(DiskOptParams),
                                           POINTER(DiskOptState), POINTER(DiskOptTune), P, c_size_t, P]),
         "disk_clock_rate_khz": (c_int64, []),
@@ -460,6 +461,13 @@ def disk_optimize_batch(batch: Batch, theta, params: OptParams, ticks=None, stat
                                  _ptr(theta), _ptr(psnr), _ptr(steps), _ptr(status), _ptr(ticks),
                                  ctypes.byref(params.c), st, tn, _ptr(ws), ws.numel(), _stream()))
     return psnr, steps, status
+
+
+def optimize_default_tune(B: int, max_side: int, max_T: int):
+    """The launch shape the built-in table gives a batch: (threads, wgs_per_cu)."""
+    out = DiskOptTune()
+    _check(lib().disk_optimize_default_tune(ctypes.byref(DiskBatchMeta(B, max_side, max_T)), ctypes.byref(out)))
+    return int(out.threads), int(out.wgs_per_cu)
 
 
 def optimize_workspace_size(batch: Batch, tune=None):

@@ -553,6 +553,15 @@ size_t disk_optimize_workspace_size(const disk_batch_meta* meta, const disk_opt_
     return optimize_ws(meta, tune, cv, &o, &q, &sc, &slot, &nwg) + 256;
 }
 
+disk_status disk_optimize_default_tune(const disk_batch_meta* meta, disk_opt_tune* out) {
+    if (!meta || !out) return fail(DISK_INVALID_ARG, "meta and out must not be NULL");
+    if (meta->B < 1 || meta->max_side < 1 || meta->max_T < 1)
+        return fail(DISK_INVALID_ARG, "bad batch meta (B=%d max_side=%d max_T=%d)", int(meta->B),
+                    int(meta->max_side), int(meta->max_T));
+    *out = opt_default_tune(*meta);
+    return ok();
+}
+
 disk_status disk_optimize_batch(const disk_batch_meta* meta, const disk_target* desc, const int32_t* taps,
                                 const float* targets, float* theta, float* psnr_db, int32_t* steps, int32_t* status,
                                 uint64_t* finish_ticks, const disk_opt_params* params, const disk_opt_state* state,
