@@ -1497,6 +1497,8 @@ static hipError_t launch_typed(const void* src, void* dst, const float* pmap, co
                 if (e == hipSuccess)
                     e = launch_typed<C - 2, DIMS, TIn, TOut>(xs + 2 * plane, ys + 2 * plane, ps, table, tap0, N, T,
                                                              G0, G1, H, W, halo, flag, nullptr, s, Frames{});
+            } else {
+                e = hipErrorInvalidValue;   // not reached: C < 3 never takes this branch
             }
         } else {
             const long px = static_cast<long>(H) * W;
